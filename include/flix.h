@@ -1,0 +1,183 @@
+/*
+ * flix.h - C ABI of the FliX flipped-index ordered key-value store on MI355X.
+ *
+ * FliX ("Flipped-Indexing for Scalable GPU Queries and Updates", arXiv
+ * 2604.16725) keeps an ordered map entirely in GPU memory with no index
+ * layer.  Keys live in buckets; bucket i holds the keys in
+ * (maxBucket[i-1], maxBucket[i]] as a chain of fixed-capacity sorted nodes
+ * (Section 3.2).  Every operation batch is sorted on the device; then each
+ * bucket binary-searches the sorted batch for its own slice and applies it in
+ * place (Sections 3.3 and 4.1): point lookup, successor, range, merge-insert
+ * with node split (Section 4.3.2), compact-delete with node reclamation
+ * (Section 4.4).
+ *
+ * Conventions for every entry point
+ *  - Keys and values have the same width: 32 or 64 bits (flix_config.key_bits).
+ *    Device buffers hold uint32_t or uint64_t elements accordingly.
+ *  - NOT_FOUND is the all-ones value of the value width.  It is returned for
+ *    misses and may not be inserted.  KEY_MAX is the all-ones key; 0 and
+ *    KEY_MAX are ordinary keys.
+ *  - Pointers named d_* are device pointers owned by the caller.  They must
+ *    stay valid until the work enqueued on `stream` has completed.  Inputs are
+ *    never modified; the library sorts copies in its own scratch memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    calls are asynchronous and stream-ordered unless marked "synchronizes".
+ *    A store may be used from one host thread at a time; when the caller
+ *    switches streams between calls it must order them (event + wait).
+ *  - n == 0 is a no-op returning FLIX_OK; null pointers are then allowed.
+ *  - Batch semantics equal applying the batch sequentially in input order:
+ *    within one insert batch the last occurrence of a key wins; deleting an
+ *    absent key is a no-op; read batches answer every element.
+ *
+ * Errors (return values)
+ *  FLIX_OK      0  success (for asynchronous calls: successfully enqueued)
+ *  FLIX_EINVAL -1  bad argument: null pointer with n > 0, n > max_batch, bad
+ *                  config, or (detected on the device) a value equal to
+ *                  NOT_FOUND in an insert batch
+ *  FLIX_ENOMEM -2  node pool exhausted (checked on the device before any
+ *                  node is touched) or a host allocation failed
+ *  FLIX_EHIP   -3  HIP runtime error
+ *  FLIX_ESTATE -4  null store handle
+ *  FLIX_EINTERNAL -5  (status only) a device-side consistency guard fired;
+ *                  never expected on a store the library itself maintains
+ *  Errors found on the device (reserved value, pool exhausted) cancel the
+ *  whole batch: the store is left exactly as before the call.  They are
+ *  recorded in a sticky status word that flix_status() returns and clears.
+ */
+#ifndef FLIX_H
+#define FLIX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FLIX_OK 0
+#define FLIX_EINVAL (-1)
+#define FLIX_ENOMEM (-2)
+#define FLIX_EHIP (-3)
+#define FLIX_ESTATE (-4)
+#define FLIX_EINTERNAL (-5)
+
+typedef struct flix_store flix_store; /* opaque; owns all memory it allocates */
+
+typedef struct {
+  uint32_t key_bits;        /* 32 or 64; values have the same width */
+  uint32_t bucket_capacity; /* node capacity NS (Section 5.3.1): power of 2 in [8, 256] */
+  uint32_t lanes_per_bucket;/* lanes cooperating on one bucket: 16, 32 or 64 (0 = 16) */
+  uint32_t radix_bits;      /* sort digit width: 4 or 8 (0 = 8) */
+  uint64_t max_batch;       /* largest n accepted by batch calls; sizes the scratch */
+  uint64_t pool_bytes;      /* node pool budget in bytes; 0 = automatic (see below) */
+  uint32_t fill;            /* keys per node at bulk load (Section 3.2: p = NS/2);
+                               0 = bucket_capacity/2; at most bucket_capacity */
+  uint32_t reserved;        /* must be 0 */
+} flix_config;
+
+/* Create an empty store (one bucket covering every key).  Allocates the
+ * directory, the node pool and scratch sized by cfg->max_batch.  With
+ * pool_bytes == 0 the pool is sized automatically: 2x the nodes a bulk load
+ * needs plus room for one max_batch of inserts, re-sized by flix_bulk_load.
+ * Synchronizes.  *out receives the handle (NULL on error). */
+int flix_create(const flix_config* cfg, void* stream, flix_store** out);
+
+/* Replace the contents with the n pairs (d_keys[i], d_vals[i]) (Section 3.2
+ * initial build: sort, cut into groups of `fill`, one node per bucket, the last
+ * key of a group is its maxBucket).  Duplicate keys: last occurrence wins.  n
+ * is not limited by max_batch.  A value equal to NOT_FOUND -> FLIX_EINVAL and
+ * the previous contents are kept.  Pool too small for a fixed pool_bytes ->
+ * FLIX_ENOMEM.  Synchronizes. */
+int flix_bulk_load(flix_store* s, const void* d_keys, const void* d_vals, uint64_t n,
+                   void* stream);
+
+/* Upsert n pairs (Section 4.3.2 TL-Bulk merge; full nodes split into halves,
+ * Section 5.3.1).  An existing key takes the new value. */
+int flix_insert(flix_store* s, const void* d_keys, const void* d_vals, uint64_t n,
+                void* stream);
+
+/* Delete n keys (Section 4.4 TL-Bulk delete with compaction; empty nodes are
+ * unlinked and returned to the free list; adjacent underfull nodes merge). */
+int flix_delete(flix_store* s, const void* d_keys, uint64_t n, void* stream);
+
+/* Point lookups (Section 3.3): d_vals_out[i] = value of d_keys[i] or NOT_FOUND. */
+int flix_lookup(flix_store* s, const void* d_keys, uint64_t n, void* d_vals_out, void* stream);
+
+/* Successor queries (Section 6.5): smallest stored key k' >= d_keys[i] and its
+ * value; (KEY_MAX, NOT_FOUND) when none exists. */
+int flix_successor(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
+                   void* d_vals_out, void* stream);
+
+/* Range queries (ordered-map ADT, Section 2.1): all pairs with
+ * d_lo[i] <= k <= d_hi[i], ascending.  d_counts[i] = exact number of such
+ * pairs (0 when lo > hi); the first min(count, max_per_query) keys/values are
+ * written to d_keys_out / d_vals_out at [i*max_per_query + r].  Either output
+ * may be NULL.  Slots beyond min(count, max_per_query) are not written. */
+int flix_range(flix_store* s, const void* d_lo, const void* d_hi, uint64_t n,
+               uint32_t max_per_query, uint32_t* d_counts, void* d_keys_out, void* d_vals_out,
+               void* stream);
+
+/* Free every resource of the store.  Synchronizes with the device. */
+int flix_destroy(flix_store* s);
+
+/* Number of stored keys.  Synchronizes `stream`. */
+int flix_size(flix_store* s, uint64_t* out, void* stream);
+
+/* Copy all pairs in ascending key order to d_keys_out / d_vals_out (device
+ * buffers of at least `capacity` elements).  *out_n = number of pairs; if it
+ * exceeds `capacity` nothing is copied and FLIX_EINVAL is returned.
+ * Synchronizes `stream`. */
+int flix_dump(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capacity,
+              uint64_t* out_n, void* stream);
+
+/* Device invariant checker: node keys strictly increasing and inside their
+ * node's (previous maxKey, maxKey] range, chain fences increasing and ending at
+ * maxBucket, sizes within capacity, no empty non-head node, chain lengths,
+ * total key count, live + free nodes == pool, free list without duplicates.
+ * Returns FLIX_OK or a positive code naming the first violated invariant (see
+ * flix_build.hpp).  Synchronizes `stream`. */
+int flix_check(flix_store* s, void* stream);
+
+/* Return and clear the sticky device error (FLIX_OK if none).  Synchronizes. */
+int flix_status(flix_store* s, void* stream);
+
+/* Layout statistics (for tests and the benchmark's byte model): number of
+ * buckets, pool nodes, nodes in use, node capacity.  Synchronizes. */
+typedef struct {
+  uint64_t buckets;
+  uint64_t pool_nodes;
+  uint64_t live_nodes;
+  uint64_t capacity;
+  uint64_t keys;
+} flix_stats;
+int flix_get_stats(flix_store* s, flix_stats* out, void* stream);
+
+/* Copy the raw layout to HOST buffers (tests only; any pointer may be NULL):
+ * maxBucket array [buckets], node headers as {fence u64, size u32, next u32}
+ * [pool_nodes], node keys and values [pool_nodes * capacity], free stack
+ * [pool_nodes] and its height.  Synchronizes. */
+int flix_copy_layout(flix_store* s, void* h_mkba, void* h_hdr, void* h_keys, void* h_vals,
+                     uint32_t* h_free, uint64_t* h_free_top, void* stream);
+
+/* Stable device radix sort of (key, index) used by every batch call, exposed
+ * for verification: d_keys_out = keys ascending, d_idx_out = input position of
+ * each output key (ties keep input order).  n <= max_batch.  Asynchronous. */
+int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
+                    uint32_t* d_idx_out, void* stream);
+
+/* Per-kernel timing on `stream` with HIP events (for the benchmark).  When
+ * enabled, every launch of the named kernel family is bracketed by events;
+ * flix_kernel_time returns the summed milliseconds and launch count since the
+ * last reset.  Families: "sort", "read_apply", "insert_apply", "delete_apply",
+ * "pre". */
+/* Text describing the last HIP runtime error a call of this host thread hit
+ * (which call and the runtime's message); "" if none.  Never NULL. */
+const char* flix_last_error(void);
+
+int flix_set_timing(flix_store* s, int enable);
+int flix_kernel_time(flix_store* s, const char* family, double* ms, uint64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLIX_H */

@@ -1,0 +1,814 @@
+// Host side of the FliX C ABI (include/flix.h): store allocation, the batch
+// pipelines (sort -> bucket kernels) and the test/ops aids.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/flix.h"
+#include "flix_build.hpp"
+#include "flix_device.hpp"
+#include "flix_read.hpp"
+#include "flix_sort.hpp"
+#include "flix_update.hpp"
+
+using namespace flix;
+
+namespace {
+
+constexpr int kFamilies = 5;
+const char* kFamilyNames[kFamilies] = {"sort", "read_apply", "insert_apply", "delete_apply",
+                                       "pre"};
+enum Family { F_SORT = 0, F_READ = 1, F_INSERT = 2, F_DELETE = 3, F_PRE = 4 };
+
+struct Timing {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  double ms[kFamilies] = {0, 0, 0, 0, 0};
+  uint64_t count[kFamilies] = {0, 0, 0, 0, 0};
+};
+
+}  // namespace
+
+struct flix_store {
+  flix_config cfg{};
+  int kb = 32;
+  u32 ksz = 4;
+  u32 cap = 64, fill = 32, rb = 8, gl = 16;
+  u64 max_batch = 0;
+  // directory and node pool
+  u32 nb = 0;          // buckets
+  u32 nb_alloc = 0;    // capacity of the directory arrays
+  u32 pool = 0;        // nodes
+  void* mkba = nullptr;
+  NodeHdr* hdr = nullptr;
+  void* nkeys = nullptr;
+  void* nvals = nullptr;
+  u32* bnodes = nullptr;
+  u32* free_ids = nullptr;
+  Ctl* ctl = nullptr;
+  // scratch
+  void* bk[2] = {nullptr, nullptr};   // sort keys ping-pong [max_batch]
+  void* bp[2] = {nullptr, nullptr};   // sort payload ping-pong [max_batch] (8-byte slots)
+  WorkItem* work = nullptr;           // [max_batch]
+  SortScratch ss;
+  Timing tm;
+};
+
+namespace {
+
+thread_local char g_last_error[256] = "";
+
+int note_hip_error(hipError_t e, const char* what, int line) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s (line %d): %s", what, line,
+                hipGetErrorString(e));
+  return FLIX_EHIP;
+}
+
+#define HIP_TRY(x)                                               \
+  do {                                                           \
+    hipError_t e_ = (x);                                         \
+    if (e_ != hipSuccess) return note_hip_error(e_, #x, __LINE__); \
+  } while (0)
+
+inline hipStream_t S(void* st) { return reinterpret_cast<hipStream_t>(st); }
+
+u64 node_bytes(const flix_store* s) { return (u64)s->cap * 2 * s->ksz + sizeof(NodeHdr); }
+
+// ---- timing -----------------------------------------------------------------
+void tm_begin(flix_store* s, hipStream_t st, hipEvent_t* b) {
+  *b = nullptr;
+  if (!s->tm.on) return;
+  if (s->tm.used + 2 > s->tm.pool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      s->tm.pool.push_back(e);
+    }
+  }
+  *b = s->tm.pool[s->tm.used++];
+  (void)hipEventRecord(*b, st);
+}
+void tm_end(flix_store* s, hipStream_t st, int fam, hipEvent_t b) {
+  if (!s->tm.on || b == nullptr) return;
+  hipEvent_t e = s->tm.pool[s->tm.used++];
+  (void)hipEventRecord(e, st);
+  s->tm.pending.push_back({fam, {b, e}});
+}
+void tm_collect(flix_store* s) {
+  for (auto& p : s->tm.pending) {
+    (void)hipEventSynchronize(p.second.second);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, p.second.first, p.second.second);
+    s->tm.ms[p.first] += ms;
+    s->tm.count[p.first] += 1;
+  }
+  s->tm.pending.clear();
+  s->tm.used = 0;
+}
+
+// ---- allocation -------------------------------------------------------------
+template <typename T>
+int dev_alloc(T** p, u64 bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) return FLIX_ENOMEM;
+  return FLIX_OK;
+}
+template <typename T>
+void dev_free(T** p) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+}
+
+int ensure_sort_capacity(flix_store* s, u64 items) {
+  if (items <= s->ss.max_items) return FLIX_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  dev_free(&s->ss.status);
+  u64 words = sort_status_words(items, 8);  // sized for the widest digit
+  int rc = dev_alloc(&s->ss.status, words * sizeof(u64));
+  if (rc) return rc;
+  HIP_TRY(hipMemset(s->ss.status, 0, words * sizeof(u64)));
+  s->ss.epoch = 0;
+  s->ss.max_items = items;
+  return FLIX_OK;
+}
+
+int alloc_pool(flix_store* s, u32 pool) {
+  dev_free(&s->hdr);
+  dev_free(&s->nkeys);
+  dev_free(&s->nvals);
+  dev_free(&s->free_ids);
+  s->pool = 0;
+  int rc;
+  if ((rc = dev_alloc(&s->hdr, (u64)pool * sizeof(NodeHdr)))) return rc;
+  if ((rc = dev_alloc(&s->nkeys, (u64)pool * s->cap * s->ksz))) return rc;
+  if ((rc = dev_alloc(&s->nvals, (u64)pool * s->cap * s->ksz))) return rc;
+  if ((rc = dev_alloc(&s->free_ids, (u64)pool * sizeof(u32)))) return rc;
+  s->pool = pool;
+  return FLIX_OK;
+}
+
+int alloc_dir(flix_store* s, u32 nb) {
+  if (nb <= s->nb_alloc) return FLIX_OK;
+  dev_free(&s->mkba);
+  dev_free(&s->bnodes);
+  int rc;
+  if ((rc = dev_alloc(&s->mkba, (u64)nb * s->ksz))) return rc;
+  if ((rc = dev_alloc(&s->bnodes, (u64)nb * sizeof(u32)))) return rc;
+  s->nb_alloc = nb;
+  return FLIX_OK;
+}
+
+u32 auto_pool(const flix_store* s, u64 nbuckets) {
+  u64 f = s->cap / 2;
+  u64 p = 2 * nbuckets + 2 * ((s->max_batch + f - 1) / f) + 64;
+  if (p > 0xFFFFFFF0ull) p = 0xFFFFFFF0ull;
+  return (u32)p;
+}
+
+// ---- sort dispatch ----------------------------------------------------------
+// payload: 0 none, 1 index, 2 value.  Result in s->bk[r], s->bp[r].
+template <typename K>
+int sort_batch_t(flix_store* s, const K* keys, const K* vals, u32 n, int pay, hipStream_t st,
+                 int* r) {
+  hipError_t e;
+  K* k0 = (K*)s->bk[0];
+  K* k1 = (K*)s->bk[1];
+  if (pay == kPayIndex) {
+    u32* p0 = (u32*)s->bp[0];
+    u32* p1 = (u32*)s->bp[1];
+    e = s->rb == 4 ? radix_sort<K, u32, 4, kPayIndex>(keys, nullptr, k0, p0, k1, p1, n, s->ss, st, r)
+                   : radix_sort<K, u32, 8, kPayIndex>(keys, nullptr, k0, p0, k1, p1, n, s->ss, st, r);
+  } else if (pay == kPayValue) {
+    K* p0 = (K*)s->bp[0];
+    K* p1 = (K*)s->bp[1];
+    e = s->rb == 4 ? radix_sort<K, K, 4, kPayValue>(keys, vals, k0, p0, k1, p1, n, s->ss, st, r)
+                   : radix_sort<K, K, 8, kPayValue>(keys, vals, k0, p0, k1, p1, n, s->ss, st, r);
+  } else {
+    e = s->rb == 4
+            ? radix_sort<K, u32, 4, kPayNone>(keys, nullptr, k0, nullptr, k1, nullptr, n, s->ss, st, r)
+            : radix_sort<K, u32, 8, kPayNone>(keys, nullptr, k0, nullptr, k1, nullptr, n, s->ss, st, r);
+  }
+  return e == hipSuccess ? FLIX_OK : note_hip_error(e, "sort", __LINE__);
+}
+
+// Per-call counters are cleared by a one-block kernel at the start of every
+// update call (they are read by the kernels that follow on the stream).
+__global__ void k_reset_call(Ctl* ctl) {
+  ctl->need = 0;
+  ctl->call_err = 0;
+  ctl->heavy_count = 0;
+  ctl->heavy_cursor = 0;
+}
+
+template <typename K>
+int sort_batch(flix_store* s, const void* keys, const void* vals, u64 n, int pay, hipStream_t st,
+               int* r) {
+  hipEvent_t b;
+  tm_begin(s, st, &b);
+  int rc = sort_batch_t<K>(s, (const K*)keys, (const K*)vals, (u32)n, pay, st, r);
+  tm_end(s, st, F_SORT, b);
+  return rc;
+}
+
+// ---- read path --------------------------------------------------------------
+template <typename K>
+struct ReadCfg;
+template <>
+struct ReadCfg<u32> {
+  static constexpr int S = 512;
+  static constexpr int STAGE = 2560;
+};
+template <>
+struct ReadCfg<u64> {
+  static constexpr int S = 256;
+  static constexpr int STAGE = 2560;
+};
+
+template <typename K>
+int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void* out_v,
+               const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
+  int r;
+  int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r);
+  if (rc) return rc;
+  ReadArgs<K> a;
+  a.skeys = (const K*)s->bk[r];
+  a.sidx = (const u32*)s->bp[r];
+  a.m = (u32)n;
+  a.mkba = (const K*)s->mkba;
+  a.nb = s->nb;
+  a.hdr = s->hdr;
+  a.nkeys = (const K*)s->nkeys;
+  a.nvals = (const K*)s->nvals;
+  a.cap = s->cap;
+  a.share = ReadCfg<K>::S;
+  a.out_v = (K*)out_v;
+  a.out_k = (K*)out_k;
+  a.hi = (const K*)hi;
+  a.counts = counts;
+  a.maxpq = maxpq;
+  u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
+  constexpr int NT = 256;
+  constexpr int SS = ReadCfg<K>::S;
+  constexpr int ST = ReadCfg<K>::STAGE;
+  hipEvent_t b;
+  tm_begin(s, st, &b);
+  if (op == kOpLookup)
+    hipLaunchKernelGGL((k_read_apply<K, NT, SS, ST, kOpLookup>), dim3(grid), dim3(NT), 0, st, a);
+  else if (op == kOpSuccessor)
+    hipLaunchKernelGGL((k_read_apply<K, NT, SS, ST, kOpSuccessor>), dim3(grid), dim3(NT), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_read_apply<K, NT, SS, ST, kOpRange>), dim3(grid), dim3(NT), 0, st, a);
+  tm_end(s, st, F_READ, b);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
+// ---- update path ------------------------------------------------------------
+template <typename K>
+struct SliceCfg;
+template <>
+struct SliceCfg<u32> {
+  static constexpr int S = 1024;
+};
+template <>
+struct SliceCfg<u64> {
+  static constexpr int S = 512;
+};
+
+constexpr int kUpdNT = 256;
+
+u32 upd_chunk(const flix_store* s) { return std::max<u32>(s->cap, 64u); }
+u32 upd_lds_items(const flix_store* s) { return s->cap + upd_chunk(s); }
+
+template <typename K, int GL>
+void launch_update(flix_store* s, bool insert, const UpdArgs<K>& a, u32 grid, hipStream_t st,
+                   u32 lds_items) {
+  size_t shm = (size_t)(kUpdNT / GL) * 2 * lds_items * sizeof(K);
+  static size_t attr_set[2] = {0, 0};
+  if (shm > 65536 && shm > attr_set[insert ? 1 : 0]) {
+    hipError_t e = hipFuncSetAttribute(
+        insert ? reinterpret_cast<const void*>(&k_insert_apply<K, GL, kUpdNT>)
+               : reinterpret_cast<const void*>(&k_delete_apply<K, GL, kUpdNT>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e == hipSuccess) attr_set[insert ? 1 : 0] = shm;
+    (void)hipGetLastError();
+  }
+  if (insert)
+    hipLaunchKernelGGL((k_insert_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
+                       lds_items);
+  else
+    hipLaunchKernelGGL((k_delete_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
+                       lds_items);
+}
+
+template <typename K>
+int update_batch(flix_store* s, bool insert, const void* keys, const void* vals, u64 n,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+  int r;
+  int rc = sort_batch<K>(s, keys, vals, n, insert ? kPayValue : kPayNone, st, &r);
+  if (rc) return rc;
+  SliceArgs<K> sa;
+  sa.skeys = (const K*)s->bk[r];
+  sa.svals = insert ? (const K*)s->bp[r] : nullptr;
+  sa.m = (u32)n;
+  sa.mkba = (const K*)s->mkba;
+  sa.nb = s->nb;
+  sa.hdr = s->hdr;
+  sa.bnodes = s->bnodes;
+  sa.cap = s->cap;
+  sa.share = SliceCfg<K>::S;
+  sa.work = s->work;
+  sa.ctl = s->ctl;
+  constexpr int SS = SliceCfg<K>::S;
+  u64 grid = ((u64)n + s->nb + sa.share - 1) / sa.share;
+  hipEvent_t b;
+  tm_begin(s, st, &b);
+  if (insert)
+    hipLaunchKernelGGL((k_slices<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa);
+  else
+    hipLaunchKernelGGL((k_slices<K, 256, SS, false>), dim3(grid), dim3(256), 0, st, sa);
+  tm_end(s, st, F_PRE, b);
+  HIP_TRY(hipGetLastError());
+
+  UpdArgs<K> ua;
+  ua.skeys = (const K*)s->bk[r];
+  ua.svals = insert ? (const K*)s->bp[r] : nullptr;
+  ua.m = (u32)n;
+  ua.hdr = s->hdr;
+  ua.nkeys = (K*)s->nkeys;
+  ua.nvals = (K*)s->nvals;
+  ua.bnodes = s->bnodes;
+  ua.free_ids = s->free_ids;
+  ua.cap = s->cap;
+  ua.chunk = upd_chunk(s);
+  ua.pool = s->pool;
+  ua.work = s->work;
+  ua.ctl = s->ctl;
+  ua.status = &s->ctl->status;
+  u32 lds_items = insert ? upd_lds_items(s) : s->cap;
+  u64 items = std::min<u64>(n, s->nb);
+  u32 gpb = kUpdNT / s->gl;
+  u64 g2 = (items + 2 * gpb - 1) / (2 * gpb);
+  if (g2 < 1) g2 = 1;
+  if (g2 > 16384) g2 = 16384;
+  tm_begin(s, st, &b);
+  switch (s->gl) {
+    case 16: launch_update<K, 16>(s, insert, ua, (u32)g2, st, lds_items); break;
+    case 32: launch_update<K, 32>(s, insert, ua, (u32)g2, st, lds_items); break;
+    default: launch_update<K, 64>(s, insert, ua, (u32)g2, st, lds_items); break;
+  }
+  tm_end(s, st, insert ? F_INSERT : F_DELETE, b);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
+// ---- bulk load --------------------------------------------------------------
+template <typename K>
+int bulk_load_t(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t st) {
+  if (n > 0xFFFFFFF0ull) return FLIX_EINVAL;
+  // reserved value check before anything changes
+  if (n) {
+    HIP_TRY(hipMemsetAsync(&s->ctl->call_err, 0, sizeof(u32), st));
+    u64 g = std::min<u64>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL((k_check_reserved<K>), dim3(g), dim3(256), 0, st, vals, n, &s->ctl->call_err);
+    HIP_TRY(hipGetLastError());
+    u32 err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &s->ctl->call_err, sizeof(u32), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (err) return FLIX_EINVAL;
+  }
+  // sorted, deduplicated pairs in temporary buffers
+  K *tk0 = nullptr, *tk1 = nullptr, *tv0 = nullptr, *tv1 = nullptr, *ck = nullptr, *cv = nullptr;
+  u32* bsum = nullptr;
+  u64 nd = 0;
+  int rc = FLIX_OK;
+  auto cleanup = [&]() {
+    dev_free(&tk0); dev_free(&tk1); dev_free(&tv0); dev_free(&tv1);
+    dev_free(&ck); dev_free(&cv); dev_free(&bsum);
+  };
+  if (n) {
+    if ((rc = ensure_sort_capacity(s, n))) return rc;
+    if ((rc = dev_alloc(&tk0, n * sizeof(K))) || (rc = dev_alloc(&tk1, n * sizeof(K))) ||
+        (rc = dev_alloc(&tv0, n * sizeof(K))) || (rc = dev_alloc(&tv1, n * sizeof(K))) ||
+        (rc = dev_alloc(&ck, n * sizeof(K))) || (rc = dev_alloc(&cv, n * sizeof(K)))) {
+      cleanup();
+      return rc;
+    }
+    int r = 0;
+    hipError_t e = s->rb == 4
+        ? radix_sort<K, K, 4, kPayValue>(keys, vals, tk0, tv0, tk1, tv1, (u32)n, s->ss, st, &r)
+        : radix_sort<K, K, 8, kPayValue>(keys, vals, tk0, tv0, tk1, tv1, (u32)n, s->ss, st, &r);
+    if (e != hipSuccess) { cleanup(); return note_hip_error(e, "bulk load sort", __LINE__); }
+    const K* sk = r ? tk1 : tk0;
+    const K* sv = r ? tv1 : tv0;
+    u32 nblk = (u32)((n + kCompactTile - 1) / kCompactTile);
+    if ((rc = dev_alloc(&bsum, (u64)nblk * sizeof(u32)))) { cleanup(); return rc; }
+    hipLaunchKernelGGL((k_compact_count<K>), dim3(nblk), dim3(kCompactNT), 0, st, sk, n, bsum);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bsum, nblk, &s->ctl->scan_total);
+    hipLaunchKernelGGL((k_compact_scatter<K>), dim3(nblk), dim3(kCompactNT), 0, st, sk, sv, n, bsum,
+                       ck, cv);
+    if ((e = hipGetLastError()) != hipSuccess) { cleanup(); return note_hip_error(e, "bulk load compaction", __LINE__); }
+    u32 tot = 0;
+    if (hipMemcpyAsync(&tot, &s->ctl->scan_total, sizeof(u32), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      cleanup();
+      return FLIX_EHIP;
+    }
+    nd = tot;
+  }
+  u64 nbk = nd ? (nd + s->fill - 1) / s->fill : 1;
+  if (nbk > 0xFFFFFF00ull) { cleanup(); return FLIX_EINVAL; }
+  u32 pool = s->cfg.pool_bytes ? (u32)std::min<u64>(s->cfg.pool_bytes / node_bytes(s), 0xFFFFFFF0ull)
+                               : auto_pool(s, nbk);
+  if (nbk > pool) { cleanup(); return FLIX_ENOMEM; }
+  if (pool != s->pool) {
+    HIP_TRY(hipStreamSynchronize(st));
+    if ((rc = alloc_pool(s, pool))) { cleanup(); return rc; }
+  }
+  if ((rc = alloc_dir(s, (u32)nbk))) { cleanup(); return rc; }
+  HIP_TRY(hipGetLastError());
+  s->nb = (u32)nbk;
+  (void)hipGetLastError();
+  if (nd) {
+    u64 g = std::min<u64>((nd + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_build_nodes<K>), dim3(g), dim3(256), 0, st, ck, cv, nd, s->fill, s->cap,
+                       (K*)s->nkeys, (K*)s->nvals);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_nodes", __LINE__); }
+  }
+  {
+    u64 g = std::min<u64>((nbk + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_build_dir<K>), dim3(g), dim3(256), 0, st, ck, nd, s->fill, (u32)nbk,
+                       (K*)s->mkba, s->hdr, s->bnodes);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_dir", __LINE__); }
+    u64 g2 = std::min<u64>((pool - nbk + 255) / 256 + 1, 65536);
+    hipLaunchKernelGGL(k_build_free, dim3(g2), dim3(256), 0, st, (u32)nbk, pool, nd, s->free_ids,
+                       s->ctl);
+    e0 = hipGetLastError();
+    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_free", __LINE__); }
+  }
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  cleanup();
+  if (e1 != hipSuccess) return note_hip_error(e1, "bulk load kernels", __LINE__);
+  if (e2 != hipSuccess) return note_hip_error(e2, "bulk load sync", __LINE__);
+  return FLIX_OK;
+}
+
+int check_args(flix_store* s, u64 n, std::initializer_list<const void*> ptrs) {
+  if (!s) return FLIX_ESTATE;
+  if (n == 0) return 1;  // no-op
+  if (n > s->max_batch) return FLIX_EINVAL;
+  for (const void* p : ptrs)
+    if (!p) return FLIX_EINVAL;
+  return FLIX_OK;
+}
+
+void destroy_all(flix_store* s) {
+  dev_free(&s->mkba);
+  dev_free(&s->hdr);
+  dev_free(&s->nkeys);
+  dev_free(&s->nvals);
+  dev_free(&s->bnodes);
+  dev_free(&s->free_ids);
+  dev_free(&s->ctl);
+  for (int i = 0; i < 2; ++i) {
+    dev_free(&s->bk[i]);
+    dev_free(&s->bp[i]);
+  }
+  dev_free(&s->work);
+  dev_free(&s->ss.hist);
+  dev_free(&s->ss.status);
+  dev_free(&s->ss.tile_ctr);
+  dev_free(&s->ss.err);
+  for (auto e : s->tm.pool) (void)hipEventDestroy(e);
+  s->tm.pool.clear();
+}
+
+}  // namespace
+
+// =============================================================================
+// C ABI
+// =============================================================================
+extern "C" {
+
+int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  if (!out) return FLIX_EINVAL;
+  *out = nullptr;
+  if (!cfg) return FLIX_EINVAL;
+  if (cfg->key_bits != 32 && cfg->key_bits != 64) return FLIX_EINVAL;
+  u32 cap = cfg->bucket_capacity;
+  if (cap < 8 || cap > 256 || (cap & (cap - 1))) return FLIX_EINVAL;
+  u32 gl = cfg->lanes_per_bucket ? cfg->lanes_per_bucket : 16;
+  if (gl != 16 && gl != 32 && gl != 64) return FLIX_EINVAL;
+  u32 rb = cfg->radix_bits ? cfg->radix_bits : 8;
+  if (rb != 4 && rb != 8) return FLIX_EINVAL;
+  u32 fill = cfg->fill ? cfg->fill : cap / 2;
+  if (fill > cap || fill == 0) return FLIX_EINVAL;
+  if (cfg->max_batch == 0 || cfg->max_batch > 0x7FFFFFFFull) return FLIX_EINVAL;
+  if (cfg->reserved != 0) return FLIX_EINVAL;
+  flix_store* s = new (std::nothrow) flix_store;
+  if (!s) return FLIX_ENOMEM;
+  s->cfg = *cfg;
+  s->kb = (int)cfg->key_bits;
+  s->ksz = cfg->key_bits / 8;
+  s->cap = cap;
+  s->gl = gl;
+  s->rb = rb;
+  s->fill = fill;
+  s->max_batch = cfg->max_batch;
+  int rc = FLIX_OK;
+  u64 mb = cfg->max_batch;
+  if ((rc = dev_alloc(&s->ctl, sizeof(Ctl))) || (rc = dev_alloc(&s->bk[0], mb * s->ksz)) ||
+      (rc = dev_alloc(&s->bk[1], mb * s->ksz)) || (rc = dev_alloc(&s->bp[0], mb * 8)) ||
+      (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, mb * sizeof(WorkItem))) ||
+      (rc = dev_alloc(&s->ss.hist, 2 * 2048 * sizeof(u32))) ||
+      (rc = dev_alloc(&s->ss.tile_ctr, 64)) || (rc = dev_alloc(&s->ss.err, 16))) {
+    destroy_all(s);
+    delete s;
+    return rc;
+  }
+  std::snprintf(g_last_error, sizeof(g_last_error), "flix_create: initial memset");
+  if (hipMemset(s->ctl, 0, sizeof(Ctl)) != hipSuccess ||
+      hipMemset(s->ss.hist, 0, 2 * 2048 * sizeof(u32)) != hipSuccess ||
+      hipMemset(s->ss.tile_ctr, 0, 64) != hipSuccess ||
+      hipMemset(s->ss.err, 0, 16) != hipSuccess) {
+    destroy_all(s);
+    delete s;
+    return FLIX_EHIP;
+  }
+  s->ss.max_items = 0;
+  s->ss.epoch = 0;
+  s->ss.parity = 0;
+  if ((rc = ensure_sort_capacity(s, mb))) {
+    destroy_all(s);
+    delete s;
+    return rc;
+  }
+  rc = s->kb == 32 ? bulk_load_t<u32>(s, nullptr, nullptr, 0, S(stream))
+                   : bulk_load_t<u64>(s, nullptr, nullptr, 0, S(stream));
+  if (rc) {
+    destroy_all(s);
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return FLIX_OK;
+}
+
+int flix_destroy(flix_store* s) {
+  if (!s) return FLIX_ESTATE;
+  (void)hipDeviceSynchronize();
+  destroy_all(s);
+  delete s;
+  return FLIX_OK;
+}
+
+int flix_bulk_load(flix_store* s, const void* d_keys, const void* d_vals, uint64_t n,
+                   void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  if (!s) return FLIX_ESTATE;
+  if (n && (!d_keys || !d_vals)) return FLIX_EINVAL;
+  return s->kb == 32 ? bulk_load_t<u32>(s, (const u32*)d_keys, (const u32*)d_vals, n, S(stream))
+                     : bulk_load_t<u64>(s, (const u64*)d_keys, (const u64*)d_vals, n, S(stream));
+}
+
+int flix_insert(flix_store* s, const void* d_keys, const void* d_vals, uint64_t n,
+                void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_keys, d_vals});
+  if (c) return c > 0 ? FLIX_OK : c;
+  return s->kb == 32 ? update_batch<u32>(s, true, d_keys, d_vals, n, S(stream))
+                     : update_batch<u64>(s, true, d_keys, d_vals, n, S(stream));
+}
+
+int flix_delete(flix_store* s, const void* d_keys, uint64_t n, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_keys});
+  if (c) return c > 0 ? FLIX_OK : c;
+  return s->kb == 32 ? update_batch<u32>(s, false, d_keys, nullptr, n, S(stream))
+                     : update_batch<u64>(s, false, d_keys, nullptr, n, S(stream));
+}
+
+int flix_lookup(flix_store* s, const void* d_keys, uint64_t n, void* d_vals_out, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_keys, d_vals_out});
+  if (c) return c > 0 ? FLIX_OK : c;
+  return s->kb == 32
+             ? read_batch<u32>(s, kOpLookup, d_keys, n, nullptr, d_vals_out, nullptr, nullptr, 0, S(stream))
+             : read_batch<u64>(s, kOpLookup, d_keys, n, nullptr, d_vals_out, nullptr, nullptr, 0, S(stream));
+}
+
+int flix_successor(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
+                   void* d_vals_out, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_keys, d_keys_out, d_vals_out});
+  if (c) return c > 0 ? FLIX_OK : c;
+  return s->kb == 32 ? read_batch<u32>(s, kOpSuccessor, d_keys, n, d_keys_out, d_vals_out, nullptr,
+                                       nullptr, 0, S(stream))
+                     : read_batch<u64>(s, kOpSuccessor, d_keys, n, d_keys_out, d_vals_out, nullptr,
+                                       nullptr, 0, S(stream));
+}
+
+int flix_range(flix_store* s, const void* d_lo, const void* d_hi, uint64_t n,
+               uint32_t max_per_query, uint32_t* d_counts, void* d_keys_out, void* d_vals_out,
+               void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_lo, d_hi, d_counts});
+  if (c) return c > 0 ? FLIX_OK : c;
+  return s->kb == 32 ? read_batch<u32>(s, kOpRange, d_lo, n, d_keys_out, d_vals_out, d_hi, d_counts,
+                                       max_per_query, S(stream))
+                     : read_batch<u64>(s, kOpRange, d_lo, n, d_keys_out, d_vals_out, d_hi, d_counts,
+                                       max_per_query, S(stream));
+}
+
+int flix_size(flix_store* s, uint64_t* out, void* stream) {
+  if (!s) return FLIX_ESTATE;
+  if (!out) return FLIX_EINVAL;
+  u64 v = 0;
+  HIP_TRY(hipMemcpyAsync(&v, &s->ctl->nkeys, sizeof(u64), hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipStreamSynchronize(S(stream)));
+  *out = v;
+  return FLIX_OK;
+}
+
+int flix_status(flix_store* s, void* stream) {
+  if (!s) return FLIX_ESTATE;
+  u32 v = 0, se = 0;
+  HIP_TRY(hipMemcpyAsync(&v, &s->ctl->status, sizeof(u32), hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipMemcpyAsync(&se, s->ss.err, sizeof(u32), hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipMemsetAsync(&s->ctl->status, 0, sizeof(u32), S(stream)));
+  HIP_TRY(hipMemsetAsync(s->ss.err, 0, sizeof(u32), S(stream)));
+  HIP_TRY(hipStreamSynchronize(S(stream)));
+  if (v == 0 && se != 0) return FLIX_EINTERNAL;
+  return (int)v;
+}
+
+int flix_dump(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capacity,
+              uint64_t* out_n, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  if (!s) return FLIX_ESTATE;
+  if (!out_n) return FLIX_EINVAL;
+  hipStream_t st = S(stream);
+  u64 n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, &s->ctl->nkeys, sizeof(u64), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out_n = n;
+  if (n > capacity) return FLIX_EINVAL;
+  if (n == 0) return FLIX_OK;
+  if (!d_keys_out || !d_vals_out) return FLIX_EINVAL;
+  u32 nb = s->nb;
+  u32 nblk = (nb + 255) / 256;
+  u32 *tot = nullptr, *off = nullptr, *bs = nullptr, *dummy = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&tot, (u64)nb * 4)) || (rc = dev_alloc(&off, (u64)nb * 4)) ||
+      (rc = dev_alloc(&bs, (u64)nblk * 4)) || (rc = dev_alloc(&dummy, 16))) {
+    dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
+    return rc;
+  }
+  u32 g = std::min<u32>(nblk, 65535);
+  hipLaunchKernelGGL(k_bucket_totals, dim3(g), dim3(256), 0, st, s->hdr, nb, s->pool, tot);
+  hipLaunchKernelGGL(k_scan_blocks_u32, dim3(nblk), dim3(256), 0, st, tot, nb, off, bs);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bs, nblk, dummy);
+  hipLaunchKernelGGL(k_scan_addback, dim3(nblk), dim3(256), 0, st, off, nb, bs);
+  u32 gw = std::min<u32>((nb + 3) / 4, 65535);
+  if (s->kb == 32)
+    hipLaunchKernelGGL((k_dump_copy<u32>), dim3(gw), dim3(256), 0, st, s->hdr, (const u32*)s->nkeys,
+                       (const u32*)s->nvals, nb, s->cap, s->pool, off, (u32*)d_keys_out,
+                       (u32*)d_vals_out, (u64)capacity);
+  else
+    hipLaunchKernelGGL((k_dump_copy<u64>), dim3(gw), dim3(256), 0, st, s->hdr, (const u64*)s->nkeys,
+                       (const u64*)s->nvals, nb, s->cap, s->pool, off, (u64*)d_keys_out,
+                       (u64*)d_vals_out, (u64)capacity);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
+  return (e1 == hipSuccess && e2 == hipSuccess) ? FLIX_OK : FLIX_EHIP;
+}
+
+int flix_check(flix_store* s, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  if (!s) return FLIX_ESTATE;
+  hipStream_t st = S(stream);
+  u32* mark = nullptr;
+  u32* err = nullptr;
+  unsigned long long* counters = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&mark, (u64)s->pool * 4)) || (rc = dev_alloc(&err, 16)) ||
+      (rc = dev_alloc(&counters, 16))) {
+    dev_free(&mark); dev_free(&err); dev_free(&counters);
+    return rc;
+  }
+  (void)hipMemsetAsync(mark, 0, (u64)s->pool * 4, st);
+  (void)hipMemsetAsync(err, 0, 16, st);
+  (void)hipMemsetAsync(counters, 0, 16, st);
+  u32 g = std::min<u32>((s->nb + 255) / 256, 65535);
+  if (s->kb == 32)
+    hipLaunchKernelGGL((k_check_buckets<u32>), dim3(g), dim3(256), 0, st, (const u32*)s->mkba,
+                       s->hdr, (const u32*)s->nkeys, s->bnodes, s->nb, s->cap, s->pool, mark,
+                       counters, err);
+  else
+    hipLaunchKernelGGL((k_check_buckets<u64>), dim3(g), dim3(256), 0, st, (const u64*)s->mkba,
+                       s->hdr, (const u64*)s->nkeys, s->bnodes, s->nb, s->cap, s->pool, mark,
+                       counters, err);
+  hipLaunchKernelGGL(k_check_free, dim3(std::min<u32>((s->pool + 255) / 256, 65535)), dim3(256), 0,
+                     st, s->free_ids, s->ctl, s->pool, mark, err);
+  u32 herr = 0;
+  unsigned long long hc[2] = {0, 0};
+  Ctl hctl;
+  (void)hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(hc, counters, 16, hipMemcpyDeviceToHost, st);
+  (void)hipMemcpyAsync(&hctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipStreamSynchronize(st);
+  dev_free(&mark); dev_free(&err); dev_free(&counters);
+  if (e != hipSuccess) return FLIX_EHIP;
+  if (herr) return (int)herr;
+  if (hc[0] != hctl.nkeys) return 9;
+  if (hc[1] + hctl.free_top != s->pool) return 10;
+  return FLIX_OK;
+}
+
+int flix_get_stats(flix_store* s, flix_stats* out, void* stream) {
+  if (!s) return FLIX_ESTATE;
+  if (!out) return FLIX_EINVAL;
+  Ctl hctl;
+  HIP_TRY(hipMemcpyAsync(&hctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipStreamSynchronize(S(stream)));
+  out->buckets = s->nb;
+  out->pool_nodes = s->pool;
+  out->live_nodes = s->pool - hctl.free_top;
+  out->capacity = s->cap;
+  out->keys = hctl.nkeys;
+  return FLIX_OK;
+}
+
+int flix_copy_layout(flix_store* s, void* h_mkba, void* h_hdr, void* h_keys, void* h_vals,
+                     uint32_t* h_free, uint64_t* h_free_top, void* stream) {
+  if (!s) return FLIX_ESTATE;
+  hipStream_t st = S(stream);
+  if (h_mkba) HIP_TRY(hipMemcpyAsync(h_mkba, s->mkba, (u64)s->nb * s->ksz, hipMemcpyDeviceToHost, st));
+  if (h_hdr) HIP_TRY(hipMemcpyAsync(h_hdr, s->hdr, (u64)s->pool * sizeof(NodeHdr), hipMemcpyDeviceToHost, st));
+  if (h_keys) HIP_TRY(hipMemcpyAsync(h_keys, s->nkeys, (u64)s->pool * s->cap * s->ksz, hipMemcpyDeviceToHost, st));
+  if (h_vals) HIP_TRY(hipMemcpyAsync(h_vals, s->nvals, (u64)s->pool * s->cap * s->ksz, hipMemcpyDeviceToHost, st));
+  if (h_free) HIP_TRY(hipMemcpyAsync(h_free, s->free_ids, (u64)s->pool * 4, hipMemcpyDeviceToHost, st));
+  Ctl hctl;
+  HIP_TRY(hipMemcpyAsync(&hctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h_free_top) *h_free_top = hctl.free_top;
+  return FLIX_OK;
+}
+
+int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
+                    uint32_t* d_idx_out, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_keys, d_keys_out, d_idx_out});
+  if (c) return c > 0 ? FLIX_OK : c;
+  hipStream_t st = S(stream);
+  int r;
+  int rc = s->kb == 32 ? sort_batch<u32>(s, d_keys, nullptr, n, kPayIndex, st, &r)
+                       : sort_batch<u64>(s, d_keys, nullptr, n, kPayIndex, st, &r);
+  if (rc) return rc;
+  HIP_TRY(hipMemcpyAsync(d_keys_out, s->bk[r], n * s->ksz, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_idx_out, s->bp[r], n * 4, hipMemcpyDeviceToDevice, st));
+  return FLIX_OK;
+}
+
+const char* flix_last_error(void) { return g_last_error; }
+
+int flix_set_timing(flix_store* s, int enable) {
+  if (!s) return FLIX_ESTATE;
+  tm_collect(s);
+  s->tm.on = enable != 0;
+  for (int i = 0; i < kFamilies; ++i) {
+    s->tm.ms[i] = 0;
+    s->tm.count[i] = 0;
+  }
+  return FLIX_OK;
+}
+
+int flix_kernel_time(flix_store* s, const char* family, double* ms, uint64_t* launches) {
+  if (!s) return FLIX_ESTATE;
+  if (!family || !ms || !launches) return FLIX_EINVAL;
+  tm_collect(s);
+  for (int i = 0; i < kFamilies; ++i) {
+    if (std::strcmp(family, kFamilyNames[i]) == 0) {
+      *ms = s->tm.ms[i];
+      *launches = s->tm.count[i];
+      return FLIX_OK;
+    }
+  }
+  return FLIX_EINVAL;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Device-side building blocks shared by the FliX kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flix {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+constexpr int kWave = 64;
+constexpr u32 kNil = 0xFFFFFFFFu;
+
+// Per-node metadata (Section 3.2: every node stores its maxKey and its size;
+// nodes of one bucket are chained through a node link).  The fence is kept in
+// 64 bits for both key widths so the record is always 16 bytes.
+struct alignas(16) NodeHdr {
+  u64 fence;  // largest key this node may hold (its "maxKey")
+  u32 size;   // live keys, stored sorted in slots [0, size)
+  u32 next;   // next node of the same bucket, or kNil
+};
+
+// Device control block: counters and status words owned by one store.
+struct alignas(64) Ctl {
+  u32 free_top;        // number of node ids on the free stack
+  u32 status;          // sticky first device-detected error (negative code)
+  u32 call_err;        // error raised by the pre-check of the current call
+  u32 pad0;
+  u64 need;            // pre-check: upper bound of nodes the call may take
+  u64 nkeys;           // number of live keys in the store
+  u32 free_snapshot;   // free_top as seen before the current apply kernel
+  u32 heavy_count;     // number of buckets queued for the heavy path
+  u32 heavy_cursor;    // work-stealing cursor over the heavy list
+  u32 scan_total;      // output of device-wide compaction scans
+  u64 pad1[3];
+};
+
+template <typename K>
+__device__ __forceinline__ K key_max() { return ~K(0); }
+
+__device__ __forceinline__ u32 lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// popcount(mask & lanes-below-me)
+__device__ __forceinline__ u32 rank_below(u64 m) {
+  return __builtin_amdgcn_mbcnt_hi((u32)(m >> 32), __builtin_amdgcn_mbcnt_lo((u32)m, 0u));
+}
+
+__device__ __forceinline__ u64 wave_ballot(bool p) { return __ballot(p); }
+
+// Agent-scope relaxed atomics for words other workgroups poll.
+__device__ __forceinline__ u64 ld_agent(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u32 ld_agent32(const u32* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// First index i in [lo, hi) with a[i] > x (a sorted ascending).
+template <typename K, typename Ptr>
+__device__ __forceinline__ u32 upper_bound_idx(Ptr a, u32 lo, u32 hi, K x) {
+  while (lo < hi) {
+    u32 mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// First index i in [lo, hi) with a[i] >= x.
+template <typename K, typename Ptr>
+__device__ __forceinline__ u32 lower_bound_idx(Ptr a, u32 lo, u32 hi, K x) {
+  while (lo < hi) {
+    u32 mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Block-wide exclusive scan of one u32 per thread (blockDim.x == NT, NT a
+// multiple of 64, at most 1024).  `tmp` needs NT/64 + 1 words of LDS.  Returns
+// the exclusive prefix; *total receives the block sum.  All threads must call.
+template <int NT>
+__device__ __forceinline__ u32 block_exclusive_scan(u32 v, u32* tmp, u32* total) {
+  const u32 lane = threadIdx.x & 63;
+  const u32 w = threadIdx.x >> 6;
+  // inclusive wave scan with shuffles
+  u32 x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    u32 y = __shfl_up(x, off, 64);
+    if (lane >= (u32)off) x += y;
+  }
+  if (lane == 63) tmp[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u32 run = 0;
+    for (int i = 0; i < NT / 64; ++i) {
+      u32 t = tmp[i];
+      tmp[i] = run;
+      run += t;
+    }
+    tmp[NT / 64] = run;
+  }
+  __syncthreads();
+  u32 res = tmp[w] + x - v;
+  *total = tmp[NT / 64];
+  __syncthreads();
+  return res;
+}
+
+}  // namespace flix

@@ -1,0 +1,306 @@
+// Onesweep LSD radix sort of (key, payload) pairs for gfx950.
+//
+// The paper sorts every operation batch on the GPU before the bucket kernels
+// run (Section 3.3; sort cost in Table 1 and Section 6.4).  The method used
+// here is Onesweep (Adinets & Merrill, 2022): one read of the keys builds the
+// digit histograms of every pass, then each pass is a single kernel in which
+// every tile ranks its items, publishes per-digit counts and obtains its
+// global offsets by decoupled look-back over the preceding tiles.  The sort is
+// stable, which gives "last occurrence wins" for duplicate insert keys.
+//
+// Layout for wave64: tile = NT threads x IPT items, items arranged wave-
+// striped (item k of lane l in wave w sits at w*64*IPT + k*64 + l), so ranking
+// item slots k = 0..IPT-1 in order, lanes in order, reproduces input order.
+//
+// Look-back status words are 64 bits: [63:34] epoch, [33:32] flag, [31:0]
+// count.  The epoch changes for every pass launch, so the status array never
+// needs clearing between passes or calls.
+#pragma once
+
+#include "flix_device.hpp"
+
+namespace flix {
+
+constexpr u64 kFlagAgg = 1;   // tile-local count published
+constexpr u64 kFlagPre = 2;   // inclusive prefix published
+
+__device__ __forceinline__ u64 pack_status(u32 epoch, u64 flag, u32 v) {
+  return ((u64)epoch << 34) | (flag << 32) | (u64)v;
+}
+
+template <typename K, int RB>
+struct RadixShape {
+  static constexpr int R = 1 << RB;
+  static constexpr int P = (int)((sizeof(K) * 8 + RB - 1) / RB);
+};
+
+template <typename K, int RB>
+__device__ __forceinline__ u32 digit_of(K k, u32 shift) {
+  return (u32)(k >> shift) & ((1u << RB) - 1u);
+}
+
+// Digit histograms of all passes in one read of the keys.  Block 0 also
+// clears `hist_next`, the histogram slot the next sort call will use.
+template <typename K, int RB>
+__global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, u32 n,
+                                                    u32* __restrict__ hist,
+                                                    u32* __restrict__ hist_next,
+                                                    u32* __restrict__ tile_ctr) {
+  constexpr int R = RadixShape<K, RB>::R;
+  constexpr int P = RadixShape<K, RB>::P;
+  __shared__ u32 sh[P * R];
+  for (int i = threadIdx.x; i < P * R; i += 256) sh[i] = 0;
+  if (blockIdx.x == 0 && hist_next != nullptr)
+    for (int i = threadIdx.x; i < P * R; i += 256) hist_next[i] = 0;
+  // per-pass tile tickets start at 0 (the passes run after this kernel)
+  if (blockIdx.x == 0 && threadIdx.x < (u32)P) tile_ctr[threadIdx.x] = 0;
+  __syncthreads();
+  for (u32 i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+    K k = keys[i];
+#pragma unroll
+    for (int p = 0; p < P; ++p) atomicAdd(&sh[p * R + digit_of<K, RB>(k, p * RB)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < P * R; i += 256)
+    if (sh[i]) atomicAdd(&hist[i], sh[i]);
+}
+
+// Payload modes.
+constexpr int kPayNone = 0;    // keys only
+constexpr int kPayIndex = 1;   // payload is u32; vin == nullptr means "input index"
+constexpr int kPayValue = 2;   // payload read from vin
+
+template <typename K, typename V, int RB, int NT, int IPT, int PAY>
+__global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
+                                                 const V* __restrict__ vin,
+                                                 K* __restrict__ kout, V* __restrict__ vout,
+                                                 u32 n, u32 shift,
+                                                 const u32* __restrict__ hist_p,
+                                                 u64* status, u32* tile_ctr, u32 ntiles,
+                                                 u32 epoch, u32* err) {
+  constexpr int R = 1 << RB;
+  constexpr int WAVES = NT / 64;
+  constexpr int TILE = NT * IPT;
+  static_assert(R <= NT, "one look-back thread per digit");
+
+  __shared__ K s_k[TILE];
+  __shared__ V s_v[PAY == kPayNone ? 1 : TILE];
+  __shared__ u32 s_wc[WAVES][R];
+  __shared__ u32 s_lstart[R];
+  __shared__ u32 s_gbase[R];
+  __shared__ u32 s_tmp[NT / 64 + 1];
+  __shared__ u32 s_tile;
+  __shared__ u32 s_trivial;
+
+  const u32 tid = threadIdx.x;
+  const u32 lane = tid & 63;
+  const u32 w = tid >> 6;
+
+  if (tid == 0) {
+    s_tile = atomicAdd(tile_ctr, 1u);
+    s_trivial = 0;
+  }
+  for (int i = tid; i < WAVES * R; i += NT) (&s_wc[0][0])[i] = 0;
+  __syncthreads();
+  const u32 tile = s_tile;
+  if (tile >= ntiles) {   // ticket counter out of step: never expected
+    if (tid == 0) atomicOr(err, 2u);
+    return;
+  }
+  const u32 tile0 = tile * (u32)TILE;
+
+  // Global exclusive digit offsets of this pass, and the trivial-pass test
+  // (all keys share one digit: the stable permutation is the identity).
+  u32 hcount = (tid < (u32)R) ? hist_p[tid] : 0u;
+  if (tid < (u32)R && hcount == n) s_trivial = 1;
+  u32 htotal;
+  u32 hexcl = block_exclusive_scan<NT>(hcount, s_tmp, &htotal);
+
+  // Load items (wave-striped).
+  K key[IPT];
+  V pay[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+    if (idx < n) {
+      key[k] = kin[idx];
+      if (PAY == kPayIndex) pay[k] = vin ? vin[idx] : (V)idx;
+      if (PAY == kPayValue) pay[k] = vin[idx];
+    } else {
+      key[k] = K(0);
+      if (PAY != kPayNone) pay[k] = V(0);
+    }
+  }
+
+  if (s_trivial) {  // uniform across the grid: no look-back is needed
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+      if (idx < n) {
+        kout[idx] = key[k];
+        if (PAY != kPayNone) vout[idx] = pay[k];
+      }
+    }
+    return;
+  }
+
+  // Stable rank of every item among the same-digit items of its wave.
+  u32 rank[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+    bool valid = idx < n;
+    u32 d = digit_of<K, RB>(key[k], shift);
+    u64 m = wave_ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      bool bit = (d >> b) & 1u;
+      u64 bb = wave_ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    u32 below = rank_below(m);
+    u32 cnt = __popcll(m);
+    u32 base = valid ? s_wc[w][d] : 0u;
+    rank[k] = base + below;
+    if (valid && below == cnt - 1) s_wc[w][d] = base + cnt;
+  }
+  __syncthreads();
+
+  // Per-digit totals of the tile; turn the per-wave counts into exclusive
+  // prefixes across waves.
+  u32 tot = 0;
+  if (tid < (u32)R) {
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) {
+      u32 c = s_wc[ww][tid];
+      s_wc[ww][tid] = tot;
+      tot += c;
+    }
+    // Publish the tile aggregate (tile 0 publishes its inclusive prefix).
+    st_agent(&status[(u64)tile * R + tid],
+             pack_status(epoch, tile == 0 ? kFlagPre : kFlagAgg, tot));
+  }
+  u32 dummy;
+  u32 lstart = block_exclusive_scan<NT>(tid < (u32)R ? tot : 0u, s_tmp, &dummy);
+  if (tid < (u32)R) {
+    s_lstart[tid] = lstart;
+    // Decoupled look-back over preceding tiles for this digit.
+    u32 excl = 0;
+    if (tile > 0) {
+      u32 pt = tile - 1;
+      u32 polls = 0;
+      while (true) {
+        u64 s = ld_agent(&status[(u64)pt * R + tid]);
+        u32 ep = (u32)(s >> 34);
+        u32 fl = (u32)(s >> 32) & 3u;
+        if (ep != epoch || fl == 0) {
+          // Bounded wait: a predecessor that never publishes is a bug, and the
+          // kernel must still end; the error word reports it.
+          if (++polls > (1u << 22)) {
+            atomicOr(err, 1u);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += (u32)s;
+        if (fl == kFlagPre || pt == 0) break;
+        --pt;
+      }
+      st_agent(&status[(u64)tile * R + tid], pack_status(epoch, kFlagPre, excl + tot));
+    }
+    s_gbase[tid] = hexcl + excl;
+  }
+  __syncthreads();
+
+  // Local counting sort of the tile into LDS.
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+    if (idx < n) {
+      u32 d = digit_of<K, RB>(key[k], shift);
+      u32 pos = s_lstart[d] + s_wc[w][d] + rank[k];
+      s_k[pos] = key[k];
+      if (PAY != kPayNone) s_v[pos] = pay[k];
+    }
+  }
+  __syncthreads();
+
+  // Write out in digit order: consecutive threads write consecutive slots of
+  // one digit's run.
+  u32 valid_n = (n - tile0) < (u32)TILE ? (n - tile0) : (u32)TILE;
+  for (u32 i = tid; i < valid_n; i += NT) {
+    K kk = s_k[i];
+    u32 d = digit_of<K, RB>(kk, shift);
+    u32 g = s_gbase[d] + (i - s_lstart[d]);
+    if (g < n) {   // always true for a consistent histogram
+      kout[g] = kk;
+      if (PAY != kPayNone) vout[g] = s_v[i];
+    }
+  }
+}
+
+// Scratch shared by every sort call of one store.
+struct SortScratch {
+  u32* hist = nullptr;      // [2][P*R] ping-pong histogram slots
+  u64* status = nullptr;    // [max_tiles * R]
+  u32* tile_ctr = nullptr;  // [16] per-pass tile ticket counters (cleared by k_radix_hist)
+  u32* err = nullptr;       // sticky sort error bits (1: look-back wait gave up, 2: bad ticket)
+  u32 epoch = 0;            // last epoch used
+  u32 parity = 0;           // histogram slot of the next call
+  u64 max_items = 0;        // capacity of the status array, in items
+};
+
+constexpr int kSortNT = 256;
+constexpr int kSortIPT = 8;
+constexpr int kSortTile = kSortNT * kSortIPT;
+
+inline u64 sort_status_words(u64 max_items, int rb) {
+  return ((max_items + kSortTile - 1) / kSortTile + 1) * (u64)(1 << rb);
+}
+
+// Host driver: sorts n pairs from (kin, vin) using ping-pong buffers
+// (k0, v0) / (k1, v1).  Returns which buffer holds the result (0 or 1).
+// `reset_status` is called when the epoch counter wraps.
+template <typename K, typename V, int RB, int PAY>
+hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u32 n,
+                      SortScratch& s, hipStream_t st, int* result_buf) {
+  constexpr int R = RadixShape<K, RB>::R;
+  constexpr int P = RadixShape<K, RB>::P;
+  if (n == 0) {
+    *result_buf = 0;
+    return hipSuccess;
+  }
+  if ((u64)n > s.max_items) return hipErrorInvalidValue;
+  const u32 ntiles = (n + kSortTile - 1) / kSortTile;
+  u32* hist = s.hist + (size_t)s.parity * (P * R);
+  u32* hist_next = s.hist + (size_t)(s.parity ^ 1u) * (P * R);
+  s.parity ^= 1u;
+  u32 hb = (n + 256u * 16u - 1u) / (256u * 16u);
+  if (hb > 1024u) hb = 1024u;
+  hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(hb), dim3(256), 0, st, kin, n, hist, hist_next,
+                     s.tile_ctr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int p = 0; p < P; ++p) {
+    if (s.epoch >= (1u << 30) - 1u) {
+      e = hipMemsetAsync(s.status, 0, sort_status_words(s.max_items, RB) * sizeof(u64), st);
+      if (e != hipSuccess) return e;
+      s.epoch = 0;
+    }
+    const u32 epoch = ++s.epoch;
+    const K* ki = (p == 0) ? kin : ((p & 1) ? k0 : k1);
+    const V* vi = (p == 0) ? vin : ((p & 1) ? v0 : v1);
+    K* ko = (p & 1) ? k1 : k0;
+    V* vo = (p & 1) ? v1 : v0;
+    hipLaunchKernelGGL((k_onesweep<K, V, RB, kSortNT, kSortIPT, PAY>), dim3(ntiles),
+                       dim3(kSortNT), 0, st, ki, vi, ko, vo, n, (u32)(p * RB),
+                       hist + p * R, s.status, s.tile_ctr + p, ntiles, epoch, s.err);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  *result_buf = ((P - 1) & 1) ? 1 : 0;
+  return hipSuccess;
+}
+
+}  // namespace flix

@@ -1,0 +1,583 @@
+// Update batches: insert (merge + split) and delete (compaction + node
+// reclamation), in the flipped form of Section 4.1: each bucket pulls its
+// slice of the sorted update list and applies it to its node chain.
+//
+// Pipeline per update batch (all on the caller's stream):
+//   sort (stable, key+value for inserts, keys only for deletes)
+//   k_slices   merge-path shares over MKBA (+) batch; every bucket with a
+//              non-empty slice is appended to the work list.  For inserts it
+//              also counts live keys (last of each equal-key run), rejects the
+//              reserved value and sums an upper bound of the nodes the batch
+//              may take from the free list.
+//   k_insert_apply / k_delete_apply
+//              a group of GL lanes per work item (bucket).  Inserts first check
+//              the node budget against the free-list height captured before
+//              the kernel, so a batch that could run out of nodes is rejected
+//              as a whole before any node is touched.
+#pragma once
+
+#include "flix_device.hpp"
+#include "flix_read.hpp"
+
+namespace flix {
+
+constexpr u32 kErrInval = 0xFFFFFFFFu;   // -1
+constexpr u32 kErrNomem = 0xFFFFFFFEu;   // -2
+constexpr u32 kErrInternal = 0xFFFFFFFBu;  // -5: internal consistency check failed
+
+// Work item: bucket and its slice [s, e) of the sorted batch.
+struct alignas(16) WorkItem {
+  u32 b, s, e, pad;
+};
+
+template <typename K>
+struct SliceArgs {
+  const K* skeys;
+  const K* svals;   // inserts only
+  u32 m;
+  const K* mkba;
+  u32 nb;
+  const NodeHdr* hdr;
+  const u32* bnodes;
+  u32 cap;
+  u32 share;
+  WorkItem* work;
+  Ctl* ctl;
+};
+
+template <typename K, int NT, int S, bool INSERT>
+__global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
+  __shared__ K s_q[S + 1];
+  __shared__ K s_mk[S];
+  __shared__ u32 s_e[S + 1];
+  __shared__ u32 s_live[S + 1];   // exclusive prefix of live flags
+  __shared__ u32 s_tmp[NT / 64 + 1];
+  __shared__ u32 s_part[4];
+  __shared__ u32 s_wbase;
+  __shared__ unsigned long long s_need;
+  __shared__ u32 s_bad;
+  __shared__ u32 s_gstart;
+
+  const u32 tid = threadIdx.x;
+  const u64 total = (u64)a.m + a.nb;
+  const u64 d0 = (u64)blockIdx.x * a.share;
+  const u64 d1 = d0 + a.share < total ? d0 + a.share : total;
+  if (blockIdx.x == 0 && tid == 0) a.ctl->free_snapshot = a.ctl->free_top;
+  if (tid == 0) {
+    u32 q0 = merge_path_keys(a.skeys, a.m, a.mkba, a.nb, d0);
+    s_part[0] = q0;
+    s_part[2] = (u32)(d0 - q0);
+    s_need = 0;
+    s_bad = 0;
+  } else if (tid == 64 % NT) {
+    u32 q1 = merge_path_keys(a.skeys, a.m, a.mkba, a.nb, d1);
+    s_part[1] = q1;
+    s_part[3] = (u32)(d1 - q1);
+  }
+  __syncthreads();
+  const u32 q0 = s_part[0], q1 = s_part[1];
+  const u32 b0 = s_part[2], b1 = s_part[3];
+  const u32 nq = q1 - q0;
+  const u32 nbl = b1 - b0;
+  // A bucket is emitted by the share that holds its maxBucket entry, with its
+  // whole slice; only local bucket 0 can have keys in earlier shares.
+  if (nbl == 0) return;
+  if (tid == 0) {
+    s_gstart = (b0 == 0) ? 0u : upper_bound_idx<K>(a.skeys, 0u, q0, a.mkba[b0 - 1]);
+  }
+  for (u32 j = tid; j <= nq; j += NT) {
+    if (j < nq || q0 + j < a.m) s_q[j] = a.skeys[q0 + j];
+  }
+  for (u32 i = tid; i < nbl; i += NT) s_mk[i] = a.mkba[b0 + i];
+  __syncthreads();
+  for (u32 lb = tid; lb <= nbl; lb += NT)
+    s_e[lb] = (lb < nbl) ? upper_bound_idx<K>(s_q, 0u, nq, s_mk[lb]) : nq;
+
+  if (INSERT) {
+    // live flags (last of each equal-key run in the whole batch) -> prefix
+    constexpr u32 PER = (S + NT - 1) / NT;
+    u32 f[PER];
+    u32 sum = 0;
+    bool bad = false;
+#pragma unroll
+    for (u32 r = 0; r < PER; ++r) {
+      u32 j = tid * PER + r;
+      u32 live = 0;
+      if (j < nq) {
+        bool last = (q0 + j + 1 == a.m) || (s_q[j] != s_q[j + 1]);
+        live = last ? 1u : 0u;
+        if (a.svals[q0 + j] == key_max<K>()) bad = true;
+      }
+      f[r] = live;
+      sum += live;
+    }
+    if (bad) s_bad = 1;
+    u32 tot;
+    u32 ex = block_exclusive_scan<NT>(sum, s_tmp, &tot);
+#pragma unroll
+    for (u32 r = 0; r < PER; ++r) {
+      u32 j = tid * PER + r;
+      if (j < nq) s_live[j] = ex;
+      ex += f[r];
+    }
+    if (tid == 0) s_live[nq] = tot;
+  }
+  __syncthreads();
+
+  // Append touched buckets to the work list (one atomic per workgroup).
+  // Local bucket lb < nbl has the global slice [q0 + s, q0 + e), except that
+  // bucket 0 starts at gstart (<= q0).  Local bucket nbl is left to the next
+  // share.
+  const u32 gstart = s_gstart;
+  constexpr u32 PERB = (S + NT - 1) / NT;
+  u32 cnt = 0;
+  unsigned long long need = 0;
+#pragma unroll
+  for (u32 r = 0; r < PERB; ++r) {
+    u32 lb = tid * PERB + r;
+    if (lb < nbl) {
+      u32 s = lb ? q0 + s_e[lb - 1] : gstart;
+      u32 e = q0 + s_e[lb];
+      if (e > s) {
+        ++cnt;
+        if (INSERT) {
+          // live keys inside this share, plus (bucket 0 only) every key before
+          // q0 counted as live: an upper bound is all the budget needs
+          u32 sl = lb ? s_e[lb - 1] : 0u;
+          u32 t = s_live[e - q0] - s_live[sl] + (lb ? 0u : q0 - gstart);
+          u32 b = b0 + lb;
+          u32 bn = a.bnodes[b];
+          u32 f = a.cap / 2;
+          if (bn == 1) {
+            u32 sa = a.hdr[b].size;
+            u64 c = (u64)sa + t;
+            if (c > a.cap) need += c / f - 1;
+          } else {
+            need += (u64)(bn < t ? bn : t) + t / f;
+          }
+        }
+      }
+    }
+  }
+  u32 tot_items;
+  u32 ex = block_exclusive_scan<NT>(cnt, s_tmp, &tot_items);
+  if (INSERT && need) atomicAdd(&s_need, need);
+  if (tid == 0 && tot_items) s_wbase = atomicAdd(&a.ctl->heavy_count, tot_items);
+  __syncthreads();
+  u32 w = s_wbase + ex;
+#pragma unroll
+  for (u32 r = 0; r < PERB; ++r) {
+    u32 lb = tid * PERB + r;
+    if (lb < nbl) {
+      u32 s = lb ? q0 + s_e[lb - 1] : gstart;
+      u32 e = q0 + s_e[lb];
+      if (e > s) {
+        WorkItem it;
+        it.b = b0 + lb;
+        it.s = s;
+        it.e = e;
+        it.pad = 0;
+        a.work[w++] = it;
+      }
+    }
+  }
+  if (INSERT && tid == 0) {
+    if (s_need) atomicAdd((unsigned long long*)&a.ctl->need, s_need);
+    if (s_bad) atomicExch(&a.ctl->call_err, kErrInval);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Lane groups: GL consecutive lanes of a wave cooperate on one bucket.  All
+// lanes of a group follow the same control flow; groups of one wave may
+// diverge, so group code never uses workgroup barriers.
+// ---------------------------------------------------------------------------
+template <int GL>
+struct Group {
+  u32 lane;   // lane index inside the group
+  u32 gbase;  // wave lane of the group's lane 0
+  u64 gmask;  // wave-positioned mask of the group's lanes
+  __device__ __forceinline__ Group() {
+    u32 wl = lane_id();
+    lane = wl % GL;
+    gbase = wl - lane;
+    gmask = (GL == 64) ? ~0ull : (((1ull << GL) - 1ull) << gbase);
+  }
+  __device__ __forceinline__ u64 ballot(bool p) const { return wave_ballot(p) & gmask; }
+  __device__ __forceinline__ u32 count(bool p) const { return (u32)__popcll(ballot(p)); }
+  __device__ __forceinline__ u32 rank(bool p) const { return rank_below(ballot(p)); }
+  template <typename T>
+  __device__ __forceinline__ T bcast(T v, u32 src) const {
+    return __shfl(v, (int)(gbase + src), 64);
+  }
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Reads of node data this kernel may have written earlier (coherent at agent
+// scope, so never served from a stale per-CU cache line).
+template <typename K>
+__device__ __forceinline__ K ld_fresh(const K* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ NodeHdr ld_hdr(const NodeHdr* p, bool fresh) {
+  if (!fresh) return *p;
+  NodeHdr h;
+  const u64* q = reinterpret_cast<const u64*>(p);
+  h.fence = ld_fresh(q);
+  u64 w = ld_fresh(q + 1);
+  h.size = (u32)w;
+  h.next = (u32)(w >> 32);
+  return h;
+}
+
+template <typename K>
+struct UpdArgs {
+  const K* skeys;
+  const K* svals;
+  u32 m;
+  NodeHdr* hdr;
+  K* nkeys;
+  K* nvals;
+  u32* bnodes;
+  u32* free_ids;
+  u32 cap;
+  u32 chunk;          // batch items staged per merge step (<= per-group LDS room)
+  u32 pool;           // node pool size
+  const WorkItem* work;
+  Ctl* ctl;
+  u32* status;        // sticky status word (== &ctl->status)
+};
+
+// Position of merged item `pos` among k pieces of c items: piece p covers
+// [floor(p*c/k), floor((p+1)*c/k)).
+__device__ __forceinline__ u32 piece_start(u32 p, u32 c, u32 k) {
+  return (u32)(((u64)p * c) / k);
+}
+__device__ __forceinline__ u32 piece_of(u32 pos, u32 c, u32 k) {
+  u32 p = (u32)(((u64)pos * k) / c);
+  if (p + 1 < k && piece_start(p + 1, c, k) <= pos) ++p;
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Insert (Section 4.3.2 TL-Bulk, re-expressed for wave64 + LDS): for the node
+// X whose range holds the next batch keys, the group stages X's keys and a
+// chunk of at most `chunk` batch items (deduplicated: last of each equal-key
+// run), computes every item's merged position by binary search in LDS (equal
+// keys: the batch pair replaces the stored one), and writes the result back.
+// If the merged count c exceeds the capacity, X splits (Section 5.3.1) into
+// k = floor(c / (cap/2)) pieces of near-equal size; pieces 1..k-1 come from
+// the free list and are linked after X; every piece but the last is fenced by
+// its last key and the last one keeps X's fence and link.
+// ---------------------------------------------------------------------------
+template <typename K, int GL, int NT>
+__global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items) {
+  extern __shared__ unsigned char s_dyn[];
+  constexpr int GPB = NT / GL;
+  __shared__ unsigned long long s_added;
+  Group<GL> g;
+  const u32 gid = threadIdx.x / GL;
+  K* gk = reinterpret_cast<K*>(s_dyn) + (size_t)gid * 2 * lds_items;  // keys region
+  K* gv = gk + lds_items;                                               // values region
+  K* ak = gk;                  // node keys   [cap]
+  K* av = gv;
+  K* bk = gk + a.cap;          // batch chunk [chunk]
+  K* bv = gv + a.cap;
+  if (threadIdx.x == 0) s_added = 0;
+  __syncthreads();
+  const Ctl* ctl = a.ctl;
+  bool abort_all = ctl->call_err != 0 || ctl->need > ctl->free_snapshot;
+  if (abort_all) {
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->call_err == 0)
+      atomicCAS(a.status, 0u, kErrNomem);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->call_err != 0)
+      atomicCAS(a.status, 0u, ctl->call_err);
+    return;
+  }
+  const u32 nitems = ctl->heavy_count;
+  const u32 f = a.cap / 2;
+  u64 added = 0;
+  for (u32 it = blockIdx.x * GPB + gid; it < nitems; it += gridDim.x * GPB) {
+    const WorkItem w = a.work[it];
+    u32 X = w.b;
+    NodeHdr hX = a.hdr[X];
+    bool fresh = false;   // this group has written nodes of this bucket: read coherently
+    u32 j = w.s;
+    u32 nodes_added = 0;
+    while (j < w.e) {
+      const K first = a.skeys[j];
+      bool broken = false;
+      while ((u64)first > hX.fence) {   // walk to the node holding `first`
+        if (hX.next == kNil) { broken = true; break; }
+        X = hX.next;
+        hX = ld_hdr(a.hdr + X, fresh);
+      }
+      if (broken || hX.size > a.cap) {   // never on a consistent store
+        if (g.lane == 0) atomicCAS(a.status, 0u, kErrInternal);
+        break;
+      }
+      u32 j2 = upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence);
+      if (j2 - j > a.chunk) j2 = j + a.chunk;
+      // stage node X
+      const u32 sa = hX.size;
+      for (u32 i = g.lane; i < sa; i += GL) {
+        const u64 o = (u64)X * a.cap + i;
+        ak[i] = fresh ? ld_fresh(a.nkeys + o) : a.nkeys[o];
+        av[i] = fresh ? ld_fresh(a.nvals + o) : a.nvals[o];
+      }
+      // stage the chunk, keeping the last item of each equal-key run
+      u32 tb = 0;
+      for (u32 base = j; base < j2; base += GL) {
+        u32 idx = base + g.lane;
+        bool in = idx < j2;
+        K kk = in ? a.skeys[idx] : K(0);
+        bool live = in && (idx + 1 == a.m || a.skeys[idx + 1] != kk);
+        u32 r = g.rank(live);
+        if (live) {
+          bk[tb + r] = kk;
+          bv[tb + r] = a.svals[idx];
+        }
+        tb += g.count(live);
+      }
+      wave_lds_sync();
+      if (tb == 0) {   // only shadowed duplicates in this chunk
+        j = j2;
+        continue;
+      }
+      // duplicates between node and chunk
+      u32 dd = 0;
+      for (u32 i0 = 0; i0 < sa; i0 += GL) {
+        u32 i = i0 + g.lane;
+        bool drop = false;
+        if (i < sa) {
+          u32 p = lower_bound_idx<K>(bk, 0u, tb, ak[i]);
+          drop = p < tb && bk[p] == ak[i];
+        }
+        dd += g.count(drop);
+      }
+      const u32 c = sa + tb - dd;
+      u32 k = 1;
+      u32 base_id = 0;
+      if (c > a.cap) {
+        k = c / f;
+        if (g.lane == 0) base_id = atomicSub(&a.ctl->free_top, k - 1);
+        base_id = g.bcast(base_id, 0);
+        if (base_id < k - 1 || base_id > a.pool) {   // budget bound violated: never expected
+          if (g.lane == 0) atomicCAS(a.status, 0u, kErrInternal);
+          break;
+        }
+        nodes_added += k - 1;
+      }
+      // node id of piece p: X for p == 0, free_ids[base_id - p] otherwise
+      // write node items
+      u32 drop_before = 0;
+      for (u32 i0 = 0; i0 < sa; i0 += GL) {
+        u32 i = i0 + g.lane;
+        bool drop = false;
+        u32 pos = 0;
+        K kk = K(0), vv = K(0);
+        if (i < sa) {
+          kk = ak[i];
+          vv = av[i];
+          u32 p = lower_bound_idx<K>(bk, 0u, tb, kk);
+          drop = p < tb && bk[p] == kk;
+          pos = i - (drop_before + g.rank(drop)) + p;
+        }
+        drop_before += g.count(drop);
+        if (i < sa && !drop) {
+          u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
+          u32 node = pc == 0 ? X : a.free_ids[base_id - pc];
+          u32 slot = pos - piece_start(pc, c, k);
+          a.nkeys[(u64)node * a.cap + slot] = kk;
+          a.nvals[(u64)node * a.cap + slot] = vv;
+          if (k > 1 && pc + 1 < k && slot + 1 == piece_start(pc + 1, c, k) - piece_start(pc, c, k))
+            a.hdr[node].fence = (u64)kk;
+        }
+      }
+      // write chunk items
+      u32 match_before = 0;
+      for (u32 j0 = 0; j0 < tb; j0 += GL) {
+        u32 jj = j0 + g.lane;
+        bool match = false;
+        u32 pos = 0;
+        K kk = K(0), vv = K(0);
+        if (jj < tb) {
+          kk = bk[jj];
+          vv = bv[jj];
+          u32 p = lower_bound_idx<K>(ak, 0u, sa, kk);
+          match = p < sa && ak[p] == kk;
+          pos = jj + p - (match_before + g.rank(match));
+        }
+        match_before += g.count(match);
+        if (jj < tb) {
+          u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
+          u32 node = pc == 0 ? X : a.free_ids[base_id - pc];
+          u32 slot = pos - piece_start(pc, c, k);
+          a.nkeys[(u64)node * a.cap + slot] = kk;
+          a.nvals[(u64)node * a.cap + slot] = vv;
+          if (k > 1 && pc + 1 < k && slot + 1 == piece_start(pc + 1, c, k) - piece_start(pc, c, k))
+            a.hdr[node].fence = (u64)kk;
+        }
+      }
+      added += c - sa;
+      // headers: size and link of every piece; the last keeps X's fence/link
+      if (k == 1) {
+        if (g.lane == 0) a.hdr[X].size = c;
+        hX.size = c;
+      } else {
+        for (u32 p = g.lane; p < k; p += GL) {
+          u32 node = p == 0 ? X : a.free_ids[base_id - p];
+          u32 sz = piece_start(p + 1, c, k) - piece_start(p, c, k);
+          a.hdr[node].size = sz;
+          a.hdr[node].next = (p + 1 < k) ? a.free_ids[base_id - (p + 1)] : hX.next;
+          if (p + 1 == k) a.hdr[node].fence = hX.fence;
+        }
+      }
+      j = j2;
+      fresh = true;
+      // The next batch keys may fall into any piece: continue the walk from
+      // piece 0 (X) with coherent reads of what this group just wrote.
+      __threadfence();
+      wave_lds_sync();
+      if (k > 1 && j < w.e) hX = ld_hdr(a.hdr + X, true);
+    }
+    if (nodes_added && g.lane == 0) a.bnodes[w.b] += nodes_added;
+  }
+  // per-lane `added` is identical across a group's lanes: count once per group
+  if (g.lane == 0 && added) atomicAdd(&s_added, added);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_added) atomicAdd((unsigned long long*)&a.ctl->nkeys, s_added);
+}
+
+// ---------------------------------------------------------------------------
+// Delete (Section 4.4 TL-Bulk with compaction): for every node of the bucket's
+// chain whose range meets the slice, the group stages the node, marks the
+// keys present in the slice (binary search in the sorted batch), and moves
+// each survivor left by the number of deletions before it (ballot + mbcnt).
+// Structure upkeep along the walk: a node that can join its predecessor
+// (sizes summing to at most cap/2, or an emptied head) is appended to it and
+// returned to the free list; this also unlinks every emptied non-head node
+// (Section 4.4 step 5).  The head node is never freed.
+// ---------------------------------------------------------------------------
+template <typename K, int GL, int NT>
+__global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items) {
+  extern __shared__ unsigned char s_dyn[];
+  constexpr int GPB = NT / GL;
+  __shared__ unsigned long long s_removed;
+  Group<GL> g;
+  const u32 gid = threadIdx.x / GL;
+  K* ak = reinterpret_cast<K*>(s_dyn) + (size_t)gid * 2 * lds_items;
+  K* av = ak + lds_items;
+  if (threadIdx.x == 0) s_removed = 0;
+  __syncthreads();
+  const u32 nitems = a.ctl->heavy_count;
+  const u32 f = a.cap / 2;
+  u64 removed = 0;
+  for (u32 it = blockIdx.x * GPB + gid; it < nitems; it += gridDim.x * GPB) {
+    const WorkItem w = a.work[it];
+    // predecessor state (P), kept in registers; P == kNil before the head
+    u32 P = kNil;
+    NodeHdr hP;
+    hP.fence = 0; hP.size = 0; hP.next = kNil;
+    bool p_dirty = false;
+    bool p_is_head = false;
+    u32 X = w.b;
+    NodeHdr hX = a.hdr[X];
+    u32 j = w.s;
+    int freed = 0;
+    while (true) {
+      u32 j2 = (j < w.e) ? upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence) : j;
+      const bool touched = j2 > j;
+      const bool join = (P != kNil) &&
+                        ((hP.size + hX.size <= f) || (p_is_head && hP.size == 0));
+      u32 sx = hX.size;
+      if (sx > a.cap) {   // never on a consistent store
+        if (g.lane == 0) atomicCAS(a.status, 0u, kErrInternal);
+        break;
+      }
+      if (touched || join) {
+        // stage X (X's data has not been written by this kernel)
+        for (u32 i = g.lane; i < sx; i += GL) {
+          ak[i] = a.nkeys[(u64)X * a.cap + i];
+          av[i] = a.nvals[(u64)X * a.cap + i];
+        }
+        wave_lds_sync();
+      }
+      if (touched) {
+        // mark + compact in LDS (survivors only move left)
+        u32 kept = 0;
+        for (u32 i0 = 0; i0 < sx; i0 += GL) {
+          u32 i = i0 + g.lane;
+          bool keep = false;
+          K kk = K(0), vv = K(0);
+          if (i < sx) {
+            kk = ak[i];
+            vv = av[i];
+            u32 p = lower_bound_idx<K>(a.skeys, j, j2, kk);
+            keep = !(p < j2 && a.skeys[p] == kk);
+          }
+          u32 dst = kept + g.rank(keep);
+          kept += g.count(keep);
+          if (keep) {
+            ak[dst] = kk;
+            av[dst] = vv;
+          }
+        }
+        wave_lds_sync();
+        removed += sx - kept;
+        sx = kept;
+      }
+      const bool join2 = (P != kNil) &&
+                         ((hP.size + sx <= f) || sx == 0 || (p_is_head && hP.size == 0));
+      if (join2) {
+        // append X's survivors to P, unlink X, free X
+        for (u32 i = g.lane; i < sx; i += GL) {
+          a.nkeys[(u64)P * a.cap + hP.size + i] = ak[i];
+          a.nvals[(u64)P * a.cap + hP.size + i] = av[i];
+        }
+        hP.size += sx;
+        hP.fence = hX.fence;
+        hP.next = hX.next;
+        p_dirty = true;
+        if (g.lane == 0) {
+          u32 pos = atomicAdd(&a.ctl->free_top, 1u);
+          a.free_ids[pos] = X;
+        }
+        ++freed;
+      } else {
+        if (touched) {
+          for (u32 i = g.lane; i < sx; i += GL) {
+            a.nkeys[(u64)X * a.cap + i] = ak[i];
+            a.nvals[(u64)X * a.cap + i] = av[i];
+          }
+          hX.size = sx;
+        }
+        if (P != kNil && p_dirty && g.lane == 0) a.hdr[P] = hP;
+        P = X;
+        hP = hX;
+        p_dirty = touched;
+        p_is_head = (X == w.b);
+      }
+      wave_lds_sync();
+      j = j2;
+      const u32 nxt = hP.next;   // next node after the current predecessor
+      if (nxt == kNil) break;
+      const bool more = j < w.e || (p_is_head && hP.size == 0) || (p_dirty && hP.size <= f);
+      if (!more) break;
+      X = nxt;
+      hX = a.hdr[X];
+    }
+    if (P != kNil && p_dirty && g.lane == 0) a.hdr[P] = hP;
+    if (freed && g.lane == 0) a.bnodes[w.b] -= (u32)freed;
+  }
+  if (g.lane == 0 && removed) atomicAdd(&s_removed, removed);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_removed)
+    atomicAdd((unsigned long long*)&a.ctl->nkeys, (unsigned long long)(0ull - s_removed));
+}
+
+}  // namespace flix

@@ -1,0 +1,265 @@
+"""Thin ctypes binding of the FliX C ABI (``include/flix.h``).
+
+Argument marshalling only: every step of every operation runs in the HIP
+library ``lib/libflix.so``.  Device buffers are torch tensors on the GPU
+(torch is used for device memory and streams, nothing else).  If the library
+is missing, loading fails loudly; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libflix.so")
+
+FLIX_OK, FLIX_EINVAL, FLIX_ENOMEM, FLIX_EHIP, FLIX_ESTATE = 0, -1, -2, -3, -4
+_ERR_NAMES = {-1: "FLIX_EINVAL", -2: "FLIX_ENOMEM", -3: "FLIX_EHIP", -4: "FLIX_ESTATE"}
+
+
+class FlixError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        detail = ""
+        if code == FLIX_EHIP and _lib is not None:
+            detail = " (" + _lib.flix_last_error().decode(errors="replace") + ")"
+        super().__init__(f"{what} failed: {_ERR_NAMES.get(code, code)}{detail}")
+        self.code = code
+
+
+class FlixConfig(ctypes.Structure):
+    _fields_ = [
+        ("key_bits", ctypes.c_uint32),
+        ("bucket_capacity", ctypes.c_uint32),
+        ("lanes_per_bucket", ctypes.c_uint32),
+        ("radix_bits", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint64),
+        ("pool_bytes", ctypes.c_uint64),
+        ("fill", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class FlixStats(ctypes.Structure):
+    _fields_ = [
+        ("buckets", ctypes.c_uint64),
+        ("pool_nodes", ctypes.c_uint64),
+        ("live_nodes", ctypes.c_uint64),
+        ("capacity", ctypes.c_uint64),
+        ("keys", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libflix.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"FliX HIP library not found at {path}; build it with "
+            "`python -m paper_2604_16725_amd.build_lib` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    sig = {
+        "flix_create": (i32, [ctypes.POINTER(FlixConfig), vp, ctypes.POINTER(vp)]),
+        "flix_bulk_load": (i32, [vp, vp, vp, u64, vp]),
+        "flix_insert": (i32, [vp, vp, vp, u64, vp]),
+        "flix_delete": (i32, [vp, vp, u64, vp]),
+        "flix_lookup": (i32, [vp, vp, u64, vp, vp]),
+        "flix_successor": (i32, [vp, vp, u64, vp, vp, vp]),
+        "flix_range": (i32, [vp, vp, vp, u64, u32, vp, vp, vp, vp]),
+        "flix_destroy": (i32, [vp]),
+        "flix_size": (i32, [vp, ctypes.POINTER(u64), vp]),
+        "flix_dump": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
+        "flix_check": (i32, [vp, vp]),
+        "flix_status": (i32, [vp, vp]),
+        "flix_get_stats": (i32, [vp, ctypes.POINTER(FlixStats), vp]),
+        "flix_copy_layout": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(u64), vp]),
+        "flix_sort_pairs": (i32, [vp, vp, u64, vp, vp, vp]),
+        "flix_last_error": (ctypes.c_char_p, []),
+        "flix_set_timing": (i32, [vp, i32]),
+        "flix_kernel_time": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(u64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0) if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Store:
+    """A FliX store on the current GPU.
+
+    Keys/values are 32- or 64-bit integer torch tensors on the GPU (signed or
+    unsigned; the bits are read as unsigned keys).  Results come back in
+    int32/int64 tensors carrying the unsigned bit patterns.
+    """
+
+    def __init__(self, key_bits: int = 32, capacity: int = 128, lanes: int = 16,
+                 radix_bits: int = 8, max_batch: int = 1 << 20, pool_bytes: int = 0,
+                 fill: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.key_bits = key_bits
+        self.dtype = torch.int32 if key_bits == 32 else torch.int64
+        self._ok_dtypes = ((torch.int32, torch.uint32) if key_bits == 32
+                           else (torch.int64, torch.uint64))
+        self.cfg = FlixConfig(key_bits, capacity, lanes, radix_bits, max_batch, pool_bytes,
+                              fill, 0)
+        h = ctypes.c_void_p()
+        rc = self.lib.flix_create(ctypes.byref(self.cfg), _stream(stream), ctypes.byref(h))
+        if rc != FLIX_OK:
+            raise FlixError(rc, "flix_create")
+        self.h = h
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.flix_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc, what):
+        if rc != FLIX_OK:
+            raise FlixError(rc, what)
+
+    def _dev(self, t):
+        if not (t.is_cuda and t.dtype in self._ok_dtypes and t.is_contiguous()):
+            raise TypeError(f"expected a contiguous {self.key_bits}-bit integer CUDA tensor, "
+                            f"got {t.dtype} on {t.device}")
+        return t
+
+    def _empty(self, n, dtype=None):
+        return self.torch.empty(n, dtype=dtype or self.dtype, device="cuda")
+
+    # -- operations ----------------------------------------------------------
+    def bulk_load(self, keys, vals, stream=None):
+        self._chk(self.lib.flix_bulk_load(self.h, _ptr(self._dev(keys)), _ptr(self._dev(vals)),
+                                          keys.numel(), _stream(stream)), "flix_bulk_load")
+
+    def insert(self, keys, vals, stream=None, check=True):
+        rc = self.lib.flix_insert(self.h, _ptr(self._dev(keys)), _ptr(self._dev(vals)),
+                                  keys.numel(), _stream(stream))
+        if check:
+            self._chk(rc, "flix_insert")
+        return rc
+
+    def delete(self, keys, stream=None, check=True):
+        rc = self.lib.flix_delete(self.h, _ptr(self._dev(keys)), keys.numel(), _stream(stream))
+        if check:
+            self._chk(rc, "flix_delete")
+        return rc
+
+    def lookup(self, keys, out=None, stream=None):
+        out = self._empty(keys.numel()) if out is None else out
+        self._chk(self.lib.flix_lookup(self.h, _ptr(self._dev(keys)), keys.numel(), _ptr(out),
+                                       _stream(stream)), "flix_lookup")
+        return out
+
+    def successor(self, keys, out_k=None, out_v=None, stream=None):
+        n = keys.numel()
+        out_k = self._empty(n) if out_k is None else out_k
+        out_v = self._empty(n) if out_v is None else out_v
+        self._chk(self.lib.flix_successor(self.h, _ptr(self._dev(keys)), n, _ptr(out_k),
+                                          _ptr(out_v), _stream(stream)), "flix_successor")
+        return out_k, out_v
+
+    def range(self, lo, hi, max_per_query: int, counts=None, out_k=None, out_v=None,
+              want_keys=True, want_vals=True, stream=None):
+        n = lo.numel()
+        counts = self._empty(n, self.torch.int32) if counts is None else counts
+        if want_keys and out_k is None:
+            out_k = self._empty(max(n * max_per_query, 1))
+        if want_vals and out_v is None:
+            out_v = self._empty(max(n * max_per_query, 1))
+        self._chk(self.lib.flix_range(self.h, _ptr(self._dev(lo)), _ptr(self._dev(hi)), n,
+                                      max_per_query, _ptr(counts),
+                                      _ptr(out_k if want_keys else None),
+                                      _ptr(out_v if want_vals else None), _stream(stream)),
+                  "flix_range")
+        return counts, out_k, out_v
+
+    def size(self, stream=None) -> int:
+        v = ctypes.c_uint64()
+        self._chk(self.lib.flix_size(self.h, ctypes.byref(v), _stream(stream)), "flix_size")
+        return int(v.value)
+
+    def dump(self, stream=None):
+        n = self.size(stream)
+        k, v = self._empty(max(n, 1)), self._empty(max(n, 1))
+        out_n = ctypes.c_uint64()
+        self._chk(self.lib.flix_dump(self.h, _ptr(k), _ptr(v), max(n, 1), ctypes.byref(out_n),
+                                     _stream(stream)), "flix_dump")
+        m = int(out_n.value)
+        return k[:m], v[:m]
+
+    def check(self, stream=None) -> int:
+        return int(self.lib.flix_check(self.h, _stream(stream)))
+
+    def status(self, stream=None) -> int:
+        return int(self.lib.flix_status(self.h, _stream(stream)))
+
+    def stats(self, stream=None) -> dict:
+        st = FlixStats()
+        self._chk(self.lib.flix_get_stats(self.h, ctypes.byref(st), _stream(stream)), "flix_get_stats")
+        return {f: int(getattr(st, f)) for f, _ in FlixStats._fields_}
+
+    def copy_layout(self, stream=None):
+        """Raw layout on the host as numpy arrays (tests only)."""
+        import numpy as np
+        st = self.stats(stream)
+        nb, pool, cap = st["buckets"], st["pool_nodes"], st["capacity"]
+        dt = np.uint32 if self.key_bits == 32 else np.uint64
+        mkba = np.empty(nb, dtype=dt)
+        hdr = np.empty(pool * 2, dtype=np.uint64)
+        keys = np.empty(pool * cap, dtype=dt)
+        vals = np.empty(pool * cap, dtype=dt)
+        free = np.empty(pool, dtype=np.uint32)
+        top = ctypes.c_uint64()
+        p = lambda a: ctypes.c_void_p(a.ctypes.data)
+        self._chk(self.lib.flix_copy_layout(self.h, p(mkba), p(hdr), p(keys), p(vals), p(free),
+                                            ctypes.byref(top), _stream(stream)), "flix_copy_layout")
+        hv = hdr.view(np.uint32).reshape(pool, 4)
+        return dict(mkba=mkba, fence=hdr[0::2].copy(), size=hv[:, 2].copy(),
+                    next=hv[:, 3].copy(), keys=keys.reshape(pool, cap),
+                    vals=vals.reshape(pool, cap), free=free[: top.value].copy(),
+                    buckets=nb, pool=pool, cap=cap)
+
+    def sort_pairs(self, keys, stream=None):
+        n = keys.numel()
+        ko = self._empty(n)
+        io = self._empty(n, self.torch.int32)
+        self._chk(self.lib.flix_sort_pairs(self.h, _ptr(self._dev(keys)), n, _ptr(ko), _ptr(io),
+                                           _stream(stream)), "flix_sort_pairs")
+        return ko, io
+
+    def set_timing(self, on: bool):
+        self._chk(self.lib.flix_set_timing(self.h, 1 if on else 0), "flix_set_timing")
+
+    def kernel_time(self, family: str):
+        ms = ctypes.c_double()
+        n = ctypes.c_uint64()
+        self._chk(self.lib.flix_kernel_time(self.h, family.encode(), ctypes.byref(ms),
+                                            ctypes.byref(n)), "flix_kernel_time")
+        return ms.value, int(n.value)

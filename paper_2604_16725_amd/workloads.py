@@ -2,7 +2,7 @@
 
 This module only decides WHICH keys, values and operations are requested.  It
 holds none of the store's arithmetic (no bucket routing, merging or searching
-of a store), and both the GPU path and the CPU oracle receive exactly the
+of a store), and both sides of every parity check receive exactly the
 arrays it returns.
 
 The paper's workloads are all synthetic (Section 5.2.1: uniform and dense

@@ -1,0 +1,314 @@
+"""GPU parity: every FliX batch operation through the C ABI against the CPU
+oracle, bit-exact (all of this is integer work), plus the device invariant
+checker and the paper's worked examples at the node level.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import (assert_same_contents, check_reads, ktype, log, new_pair, to_dev,
+                         to_host)
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_16725_amd import flix
+    flix.load_library()
+    yield
+
+
+def _keys(rng, kb, n, hi=None):
+    mx = (1 << kb) - 1 if hi is None else hi
+    return rng.integers(0, mx, n, dtype=np.uint64, endpoint=True).astype(ktype(kb))
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("rb", [4, 8])
+@pytest.mark.parametrize("n", [1, 100, 2048, 2049, 5000, (1 << 17) + 3])
+def test_sort_matches_stable_argsort(kb, rb, n):
+    log(f"sort kb={kb} rb={rb} n={n}")
+    from paper_2604_16725_amd.flix import Store
+    s = Store(key_bits=kb, capacity=64, radix_bits=rb, max_batch=1 << 18)
+    rng = np.random.default_rng(n * 7 + kb + rb)
+    k = _keys(rng, kb, n)
+    k[rng.random(n) < 0.3] = ktype(kb)(12345)        # heavy duplicates
+    k[: min(n, 3)] = [0, (1 << kb) - 1, 7][: min(n, 3)]
+    ko, io = s.sort_pairs(to_dev(k))
+    ko, io = to_host(ko, kb), io.cpu().numpy()
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io, ref.astype(np.int32))
+    assert np.array_equal(ko, k[ref])
+
+
+def test_sort_single_digit_keys_take_copy_pass():
+    from paper_2604_16725_amd.flix import Store
+    s = Store(key_bits=64, capacity=64, radix_bits=8, max_batch=1 << 16)
+    rng = np.random.default_rng(5)
+    k = (np.uint64(0xABCD000000000000) + rng.integers(0, 256, 50000).astype(np.uint64))
+    ko, io = s.sort_pairs(to_dev(k))
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
+    assert np.array_equal(to_host(ko, 64), k[ref])
+
+
+# ---------------------------------------------------------------------------
+def test_bulk_load_layout_follows_build_rule():
+    g = json.load(open(os.path.join(GOLDEN, "initial_build_example.json")))
+    from paper_2604_16725_amd.flix import Store
+    s = Store(key_bits=32, capacity=8, fill=2, max_batch=64)
+    k = np.array(g["build_keys_unsorted"], dtype=np.uint32)
+    s.bulk_load(to_dev(k), to_dev(k * np.uint32(3)))
+    lay = s.copy_layout()
+    assert lay["buckets"] == len(g["groups"])
+    assert lay["mkba"].tolist() == g["mkba_u32"]
+    for i, grp in enumerate(g["groups"]):
+        assert lay["size"][i] == len(grp)
+        assert lay["keys"][i, : len(grp)].tolist() == grp
+        assert lay["vals"][i, : len(grp)].tolist() == [3 * x for x in grp]
+        assert lay["next"][i] == 0xFFFFFFFF
+        assert lay["fence"][i] == g["mkba_u32"][i]
+    assert lay["free"].size == lay["pool"] - lay["buckets"]
+    assert s.check() == 0
+
+
+def test_worked_insert_example_table2():
+    g = json.load(open(os.path.join(GOLDEN, "tl_bulk_insert_example.json")))
+    from paper_2604_16725_amd.flix import Store
+    s = Store(key_bits=32, capacity=8, fill=8, max_batch=64, lanes=16)
+    nb = np.array(g["node_before"], dtype=np.uint32)
+    s.bulk_load(to_dev(nb), to_dev(nb + np.uint32(100)))
+    ins = np.array(g["insert_first"], dtype=np.uint32)
+    s.insert(to_dev(ins), to_dev(ins + np.uint32(100)))
+    lay = s.copy_layout()
+    assert lay["buckets"] == 1
+    assert lay["size"][0] == 8 and lay["keys"][0].tolist() == g["node_after_first"]
+    assert lay["next"][0] == 0xFFFFFFFF
+    ins2 = np.array(g["insert_second"], dtype=np.uint32)
+    s.insert(to_dev(ins2), to_dev(ins2 + np.uint32(100)))
+    lay = s.copy_layout()
+    left, right = g["split_halves_after_second"]
+    assert lay["size"][0] == len(left) and lay["keys"][0, : len(left)].tolist() == left
+    nxt = int(lay["next"][0])
+    assert nxt != 0xFFFFFFFF
+    assert lay["size"][nxt] == len(right) and lay["keys"][nxt, : len(right)].tolist() == right
+    assert lay["fence"][0] == left[-1]
+    assert lay["fence"][nxt] == 0xFFFFFFFF and lay["next"][nxt] == 0xFFFFFFFF
+    assert s.check() == 0
+    k, v = s.dump()
+    assert to_host(k, 32).tolist() == g["contents_after_second"]
+    assert to_host(v, 32).tolist() == [x + 100 for x in g["contents_after_second"]]
+
+
+def test_worked_delete_example_table3():
+    g = json.load(open(os.path.join(GOLDEN, "tl_bulk_delete_example.json")))
+    from paper_2604_16725_amd.flix import Store
+    s = Store(key_bits=32, capacity=8, fill=8, max_batch=64)
+    nb = np.array(g["node_before"], dtype=np.uint32)
+    s.bulk_load(to_dev(nb), to_dev(nb * np.uint32(7)))
+    d = np.array(g["delete"], dtype=np.uint32)
+    s.delete(to_dev(d))
+    lay = s.copy_layout()
+    n = len(g["node_after"])
+    assert lay["size"][0] == n
+    assert lay["keys"][0, :n].tolist() == g["node_after"]
+    assert lay["vals"][0, :n].tolist() == [7 * x for x in g["node_after"]]
+    assert s.check() == 0
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("cap", [8, 64, 256])
+def test_reads_small(kb, cap):
+    log(f"reads kb={kb} cap={cap}")
+    rng = np.random.default_rng(kb * 1000 + cap)
+    s, o = new_pair(kb, cap=cap, max_batch=1 << 15)
+    mx = (1 << kb) - 1
+    k = np.unique(_keys(rng, kb, 20000))
+    k = np.unique(np.concatenate([k, np.array([0, mx, 1, mx - 1], dtype=ktype(kb))]))
+    rng.shuffle(k)
+    v = (k ^ ktype(kb)(0x5A5A)) % ktype(kb)(mx)
+    s.bulk_load(to_dev(k), to_dev(v))
+    o.bulk_load(k, v)
+    assert_same_contents(s, o, kb, "bulk")
+    q = np.concatenate([k[rng.integers(0, k.size, 6000)], _keys(rng, kb, 6000),
+                        np.array([0, mx, 1, mx - 1, 2], dtype=ktype(kb))])
+    rng.shuffle(q)
+    check_reads(s, o, kb, q, maxpq=8, where=f"cap{cap}")
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_reads_on_empty_and_single(kb):
+    s, o = new_pair(kb, cap=64, max_batch=1024)
+    mx = (1 << kb) - 1
+    q = np.array([0, 5, mx], dtype=ktype(kb))
+    check_reads(s, o, kb, q, maxpq=4, where="empty")
+    s.bulk_load(to_dev(np.array([mx], dtype=ktype(kb))), to_dev(np.array([9], dtype=ktype(kb))))
+    o.bulk_load(np.array([mx], dtype=ktype(kb)), np.array([9], dtype=ktype(kb)))
+    check_reads(s, o, kb, q, maxpq=4, where="single")
+    # n == 0 calls are no-ops
+    import torch
+    e = torch.empty(0, dtype=torch.int32 if kb == 32 else torch.int64, device="cuda")
+    s.lookup(e)
+    s.insert(e, e)
+    s.delete(e)
+    assert_same_contents(s, o, kb, "after empty calls")
+
+
+# ---------------------------------------------------------------------------
+def test_tiny_plain_workload_full_sequence():
+    """u32, capacity 64: bulk 2^16, then insert, lookup, delete, successor."""
+    from paper_2604_16725_amd import workloads as w
+    t = w.tiny_plain()
+    kb = 32
+    s, o = new_pair(kb, cap=t["capacity"], max_batch=1 << 16)
+    s.bulk_load(to_dev(t["build_keys"]), to_dev(t["build_vals"]))
+    o.bulk_load(t["build_keys"], t["build_vals"])
+    assert_same_contents(s, o, kb, "bulk")
+    for b in t["batches"]:
+        log("tiny_plain", b[0])
+        if b[0] == "insert":
+            s.insert(to_dev(b[1]), to_dev(b[2]))
+            assert o.insert(b[1], b[2]) == 0
+            assert s.status() == 0
+            assert_same_contents(s, o, kb, "insert")
+        elif b[0] == "delete":
+            s.delete(to_dev(b[1]))
+            o.delete(b[1])
+            assert_same_contents(s, o, kb, "delete")
+        elif b[0] == "lookup":
+            g = to_host(s.lookup(to_dev(b[1])), kb)
+            assert np.array_equal(g, o.lookup(b[1]))
+        else:
+            gk, gv = s.successor(to_dev(b[1]))
+            ok, ov = o.successor(b[1])
+            assert np.array_equal(to_host(gk, kb), ok) and np.array_equal(to_host(gv, kb), ov)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("cap,lanes", [(8, 16), (16, 32), (64, 64), (32, 16)])
+def test_random_sessions(kb, cap, lanes):
+    """Tiny key universes force duplicates, overwrites, absent deletes, empty
+    buckets, splits, merges and chains; contents are compared after every op."""
+    log(f"sessions kb={kb} cap={cap} lanes={lanes}")
+    mx = (1 << kb) - 1
+    for seed in range(6):
+        rng = np.random.default_rng(seed * 31 + cap + kb)
+        universe = np.unique(np.concatenate([
+            _keys(rng, kb, 3000), np.array([0, 1, 2, mx, mx - 1], dtype=ktype(kb))]))
+        s, o = new_pair(kb, cap=cap, lanes=lanes, max_batch=8192)
+        n0 = int(rng.integers(0, 1500))
+        k0 = rng.choice(universe, n0)
+        v0 = rng.integers(0, mx, n0, dtype=np.uint64).astype(ktype(kb))
+        s.bulk_load(to_dev(k0), to_dev(v0)) if n0 else None
+        o.bulk_load(k0, v0)
+        assert_same_contents(s, o, kb, f"s{seed} bulk")
+        for step in range(10):
+            op = rng.choice(["insert", "insert", "delete", "read"])
+            n = int(rng.integers(1, 4096))
+            ks = rng.choice(universe, n)
+            if op == "insert":
+                vs = rng.integers(0, mx, n, dtype=np.uint64).astype(ktype(kb))
+                s.insert(to_dev(ks), to_dev(vs))
+                o.insert(ks, vs)
+                assert s.status() == 0
+                assert_same_contents(s, o, kb, f"s{seed} step{step} insert")
+            elif op == "delete":
+                s.delete(to_dev(ks))
+                o.delete(ks)
+                assert_same_contents(s, o, kb, f"s{seed} step{step} delete")
+            else:
+                q = np.concatenate([ks, _keys(rng, kb, 200)])
+                check_reads(s, o, kb, q, maxpq=5, where=f"s{seed} step{step}")
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_clustered_runs_long_chains(kb):
+    """Dense runs of consecutive keys land in few buckets: long chains, chunked
+    merges, many splits; then rank-contiguous deletes merge and free nodes."""
+    rng = np.random.default_rng(77 + kb)
+    s, o = new_pair(kb, cap=16, lanes=16, max_batch=1 << 15)
+    base = np.unique(_keys(rng, kb, 4000))
+    s.bulk_load(to_dev(base), to_dev(base))
+    o.bulk_load(base, base)
+    for r in range(4):
+        starts = rng.integers(0, (1 << kb) - 5000, 6, dtype=np.uint64)
+        ins = np.unique(np.concatenate([np.arange(st, st + 3000, dtype=np.uint64) for st in starts]))
+        ins = ins.astype(ktype(kb))
+        rng.shuffle(ins)
+        vals = (ins * ktype(kb)(3)) % ktype(kb)((1 << kb) - 1)
+        s.insert(to_dev(ins), to_dev(vals))
+        o.insert(ins, vals)
+        assert s.status() == 0
+        assert_same_contents(s, o, kb, f"round{r} insert")
+        check_reads(s, o, kb, np.concatenate([ins[:2000], _keys(rng, kb, 2000)]), maxpq=16,
+                    where=f"round{r}")
+        cur, _ = o.dump()
+        st = int(rng.integers(0, max(1, cur.size - 5000)))
+        dele = cur[st: st + 5000].copy()
+        rng.shuffle(dele)
+        s.delete(to_dev(dele))
+        o.delete(dele)
+        assert_same_contents(s, o, kb, f"round{r} delete")
+    st = s.stats()
+    assert st["live_nodes"] <= st["pool_nodes"]
+
+
+def test_insert_into_empty_store_grows_one_bucket():
+    kb = 32
+    s, o = new_pair(kb, cap=32, max_batch=1 << 14)
+    rng = np.random.default_rng(3)
+    k = _keys(rng, kb, 10000)
+    s.insert(to_dev(k), to_dev(k))
+    o.insert(k, k)
+    assert s.status() == 0
+    assert_same_contents(s, o, kb, "grow")
+    assert s.stats()["buckets"] == 1
+
+
+# ---------------------------------------------------------------------------
+def test_error_paths_leave_store_unchanged():
+    from paper_2604_16725_amd.flix import FLIX_EINVAL, FLIX_ENOMEM, Store
+    kb = 32
+    s, o = new_pair(kb, cap=16, max_batch=4096)
+    rng = np.random.default_rng(9)
+    k = np.unique(_keys(rng, kb, 2000))
+    s.bulk_load(to_dev(k), to_dev(k))
+    o.bulk_load(k, k)
+    # n > max_batch: rejected on the host
+    big = _keys(rng, kb, 5000)
+    assert s.insert(to_dev(big), to_dev(big), check=False) == FLIX_EINVAL
+    # reserved value: rejected on the device, whole batch cancelled
+    ins = _keys(rng, kb, 100)
+    vals = ins.copy()
+    vals[50] = np.uint32(0xFFFFFFFF)
+    assert s.insert(to_dev(ins), to_dev(vals), check=False) == 0
+    assert s.status() == FLIX_EINVAL
+    assert s.status() == 0   # cleared
+    assert_same_contents(s, o, kb, "after reserved value")
+    # pool exhaustion: tiny fixed pool
+    node_bytes = 16 * 2 * 4 + 16
+    t = Store(key_bits=32, capacity=16, max_batch=4096, pool_bytes=node_bytes * 300)
+    kk = np.unique(_keys(rng, kb, 1000))
+    t.bulk_load(to_dev(kk), to_dev(kk))
+    o2 = __import__("oracle.oracle", fromlist=["Oracle"]).Oracle(32)
+    o2.bulk_load(kk, kk)
+    flood = _keys(rng, kb, 4000)
+    assert t.insert(to_dev(flood), to_dev(flood), check=False) == 0
+    assert t.status() == FLIX_ENOMEM
+    assert_same_contents(t, o2, kb, "after ENOMEM")
+    # the store keeps working
+    small = _keys(rng, kb, 50)
+    t.insert(to_dev(small), to_dev(small))
+    o2.insert(small, small)
+    assert t.status() == 0
+    assert_same_contents(t, o2, kb, "after ENOMEM then insert")
