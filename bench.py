@@ -1,0 +1,308 @@
+#!/usr/bin/env python3
+"""FliX batch-operation benchmark on one MI355X.
+
+Workload: the read-path store of the paper's method at full size: 2^26
+distinct uniform uint32 keys with uint32 values, node capacity 128 (bulk fill
+64), batches of 2^20 operations.  One step is one pass of the whole hot path:
+  lookup    2^20 keys, 90% present (uniform with replacement), 10% absent
+  successor 2^20 uniform keys
+  range     2^20 ranges [lo, lo+15], uniform lo, up to 16 results each
+  insert    2^20 new keys
+  delete    the same 2^20 keys (the store returns to its bulk-loaded contents)
+Every call sorts its batch on the device (onesweep), finds every bucket's slice
+and applies it; inputs are resident in HBM before the timed region starts.
+
+Prints ONE JSON line (rank 0) with the throughput of the step in Mops/s, the
+HBM roofline of the dominant kernel (algorithmic bytes / its average duration
+from HIP events), and the CPU oracle timed on a bounded sample as a baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mops/s lookup/insert/delete at 2^26 keys; p99 batch latency vs plain launch"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--keys-log2", type=int, default=26)
+    ap.add_argument("--batch-log2", type=int, default=20)
+    ap.add_argument("--capacity", type=int, default=128)
+    ap.add_argument("--lanes", type=int, default=16)
+    ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true")
+    return ap.parse_args()
+
+
+def ensure_built():
+    from paper_2604_16725_amd import build_lib
+    if not os.path.exists(build_lib.LIB):
+        build_lib.build()
+
+
+# ----------------------------------------------------------------------------
+# Algorithmic byte model (what the method must move)
+# ----------------------------------------------------------------------------
+def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
+    """Bytes per step for every kernel family, from the actual batches."""
+    m = wl["lookup"].size
+    nb = mkba.size
+    P = (8 * kbytes + rb - 1) // rb
+    live_line = lambda size: np.ceil(size * kbytes / 128.0) * 128.0
+
+    def touched(keys):
+        b = np.searchsorted(mkba, keys, side="left")
+        return np.unique(b)
+
+    build_sorted = wl["_build_sorted"]
+    size_of = sizes_cap  # keys per bucket after bulk load (array over buckets)
+
+    fam = {}
+    # sort: 5 sorts per step (lookup, successor, range, insert, delete)
+    fam["sort_hist"] = 5 * m * kbytes
+    pay = [4, 4, 4, vbytes, 0]
+    fam["sort_pass"] = sum(P * m * 2 * (kbytes + p) for p in pay)
+
+    def read_bytes(keys, extra_out, val_reads):
+        t = touched(keys)
+        return (nb * kbytes + m * (kbytes + 4) + t.size * 16
+                + float(live_line(size_of[t]).sum()) + val_reads * vbytes + extra_out)
+
+    hits = np.isin(wl["lookup"], build_sorted).sum()
+    look = read_bytes(wl["lookup"], m * vbytes, hits)
+    succ = read_bytes(wl["successor"], m * (kbytes + vbytes), m)
+    lo, hi = wl["range_lo"], wl["range_hi"]
+    cnt = (np.searchsorted(build_sorted, hi, side="right")
+           - np.searchsorted(build_sorted, lo, side="left")).sum()
+    rng = read_bytes(lo, m * (4 + vbytes) + cnt * (kbytes + vbytes), cnt)
+    fam["read_apply"] = look + succ + rng
+
+    ins = wl["insert_keys"]
+    ti = touched(ins)
+    per_bucket = np.bincount(np.searchsorted(mkba, ins, side="left"), minlength=nb)[ti]
+    node = size_of[ti] * (kbytes + vbytes)
+    fam["slices"] = 2 * (nb * kbytes + m * kbytes + ti.size * (16 + 4 + 16)) + m * vbytes
+    fam["insert_apply"] = float(ti.size * 16 + m * (kbytes + vbytes) + node.sum()
+                                + (node + per_bucket * (kbytes + vbytes)).sum() + ti.size * 16)
+    node_after = (size_of[ti] + per_bucket) * (kbytes + vbytes)
+    fam["delete_apply"] = float(ti.size * 16 + m * kbytes + node_after.sum()
+                                + node.sum() + ti.size * 16)
+    return fam
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the store would shard by key range; see DESIGN.md). Run with --gpus 1.",
+              file=sys.stderr, flush=True)
+        sys.exit(2)
+    ensure_built()
+    import torch
+    from paper_2604_16725_amd import flix
+    from paper_2604_16725_amd import workloads as w
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n_keys, m = 1 << args.keys_log2, 1 << args.batch_log2
+    t0 = time.time()
+    wl = w.read_path(n_keys=n_keys, batch=m, with_zipf=not args.no_breakdown, with_updates=True)
+    log(f"[bench] workload generated in {time.time() - t0:.1f}s")
+
+    def dev(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+    st = flix.Store(key_bits=32, capacity=args.capacity, lanes=args.lanes,
+                    radix_bits=args.radix_bits, max_batch=m)
+    bk, bv = dev(wl["build_keys"]), dev(wl["build_vals"])
+    t0 = time.time()
+    st.bulk_load(bk, bv)
+    log(f"[bench] bulk load of {n_keys} keys in {time.time() - t0:.2f}s")
+    del bk, bv
+    stats = st.stats()
+    dl, ds = dev(wl["lookup"]), dev(wl["successor"])
+    dlo, dhi = dev(wl["range_lo"]), dev(wl["range_hi"])
+    di, dv = dev(wl["insert_keys"]), dev(wl["insert_vals"])
+    ol = torch.empty(m, dtype=torch.int32, device="cuda")
+    sk = torch.empty(m, dtype=torch.int32, device="cuda")
+    sv = torch.empty(m, dtype=torch.int32, device="cuda")
+    L = wl["range_len"]
+    rc = torch.empty(m, dtype=torch.int32, device="cuda")
+    rk = torch.empty(m * L, dtype=torch.int32, device="cuda")
+    rv = torch.empty(m * L, dtype=torch.int32, device="cuda")
+
+    def step():
+        st.lookup(dl, out=ol)
+        st.successor(ds, out_k=sk, out_v=sv)
+        st.range(dlo, dhi, L, counts=rc, out_k=rk, out_v=rv)
+        st.insert(di, dv)
+        st.delete(di)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if st.status() != 0:
+        raise RuntimeError("device error during warmup")
+    log("[bench] warmup done")
+
+    # -- timed region: exactly K steps, per-kernel HIP events on the stream --
+    st.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    fam_t = {f: st.kernel_time(f) for f in ["sort_hist", "sort_pass", "read_apply", "slices",
+                                            "insert_apply", "delete_apply"]}
+    st.set_timing(False)
+    ms_step = (t1 - t0) * 1000.0 / args.steps
+    ops_step = 5 * m
+    value = ops_step / (ms_step / 1000.0) / 1e6
+    log(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step, {value:.1f} Mops/s")
+    if st.status() != 0:
+        raise RuntimeError("device error during timed steps")
+
+    # same K steps without per-kernel events (overhead check)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step_noev = (time.perf_counter() - t2) * 1000.0 / args.steps
+
+    # -- roofline of the dominant kernel ------------------------------------
+    build_sorted = np.sort(wl["build_keys"])
+    wl["_build_sorted"] = build_sorted
+    f = st.cfg.fill or args.capacity // 2
+    nb = stats["buckets"]
+    mkba = build_sorted[f - 1::f].copy()
+    if mkba.size < nb:
+        mkba = np.append(mkba, np.uint32(0xFFFFFFFF))
+    mkba[-1] = np.uint32(0xFFFFFFFF)
+    assert mkba.size == nb, (mkba.size, nb)
+    sizes = np.full(nb, f, dtype=np.int64)
+    sizes[-1] = n_keys - f * (nb - 1)
+    model = byte_model(wl, mkba, sizes, rb=args.radix_bits)
+    per_fam = {}
+    for fam, (ms, n) in fam_t.items():
+        if n == 0:
+            continue
+        bytes_step = model.get(fam, 0.0)
+        per_fam[fam] = {
+            "ms_per_step": ms / args.steps,
+            "launches_per_step": n / args.steps,
+            "avg_launch_us": 1000.0 * ms / n,
+            "alg_GBps": bytes_step / (ms / args.steps / 1000.0) / 1e9,
+        }
+    dom = max(per_fam, key=lambda k: per_fam[k]["ms_per_step"])
+    ach = per_fam[dom]["alg_GBps"]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_launch": model[dom] / per_fam[dom]["launches_per_step"],
+                "avg_launch_us": round(per_fam[dom]["avg_launch_us"], 2)}
+
+    # -- per-operation breakdown (each call timed alone with events) --------
+    breakdown = {}
+    if not args.no_breakdown:
+        reps = max(5, args.steps)
+
+        def timeit(name, fn, nops):
+            evs = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                b.record()
+                evs.append((a, b))
+            torch.cuda.synchronize()
+            ms = np.array([a.elapsed_time(b) for a, b in evs])
+            breakdown[name] = {"Mops_s": round(nops / (np.median(ms) / 1000) / 1e6, 1),
+                               "p50_ms": round(float(np.percentile(ms, 50)), 4),
+                               "p99_ms": round(float(np.percentile(ms, 99)), 4)}
+
+        timeit("lookup", lambda: st.lookup(dl, out=ol), m)
+        timeit("successor", lambda: st.successor(ds, out_k=sk, out_v=sv), m)
+        timeit("range16", lambda: st.range(dlo, dhi, L, counts=rc, out_k=rk, out_v=rv), m)
+
+        def ins_then_del():
+            st.insert(di, dv)
+            st.delete(di)
+        timeit("insert+delete", ins_then_del, 2 * m)
+        zl, zs = dev(wl["zipf_lookup"]), dev(wl["zipf_successor"])
+        zlo, zhi = dev(wl["zipf_range_lo"]), dev(wl["zipf_range_hi"])
+        timeit("zipf_lookup", lambda: st.lookup(zl, out=ol), m)
+        timeit("zipf_successor", lambda: st.successor(zs, out_k=sk, out_v=sv), m)
+        timeit("zipf_range16", lambda: st.range(zlo, zhi, L, counts=rc, out_k=rk, out_v=rv), m)
+        if st.status() != 0:
+            raise RuntimeError("device error during breakdown")
+
+    # -- CPU baseline: the oracle on a bounded sample -----------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle.oracle import Oracle
+        o = Oracle(32)
+        t0 = time.time()
+        o.bulk_load(wl["build_keys"], wl["build_vals"])
+        log(f"[bench] oracle bulk load {time.time() - t0:.1f}s (untimed)")
+        t0 = time.perf_counter()
+        o.lookup(wl["lookup"])
+        o.successor(wl["successor"])
+        o.range(wl["range_lo"], wl["range_hi"], L)
+        o.insert(wl["insert_keys"], wl["insert_vals"])
+        o.delete(wl["insert_keys"])
+        cpu_s = time.perf_counter() - t0
+        cpu = {"value": round(ops_step / cpu_s / 1e6, 3), "unit": "Mops/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"one step (lookup, successor, range16, insert, delete of {m} ops each) "
+                         f"on the bulk-loaded {n_keys}-key store, single thread, "
+                         f"{cpu_s:.2f}s"}
+        log(f"[bench] oracle step {cpu_s:.2f}s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "flix read-path store, 2^26 uniform u32 keys, capacity 128, "
+                               "step = lookup+successor+range16+insert+delete of 2^20 ops each",
+                   "keys": n_keys, "batch": m, "capacity": args.capacity, "lanes": args.lanes,
+                   "radix_bits": args.radix_bits, "ops_per_step": ops_step,
+                   "global_batch": m, "parallelism": "single-gpu"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "ms_per_step_without_kernel_events": round(ms_step_noev, 4),
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_fam.items()},
+        "breakdown": breakdown,
+    }
+    print(json.dumps(out), flush=True)
+    st.close()
+
+
+if __name__ == "__main__":
+    main()

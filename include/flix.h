@@ -167,8 +167,10 @@ int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_
 /* Per-kernel timing on `stream` with HIP events (for the benchmark).  When
  * enabled, every launch of the named kernel family is bracketed by events;
  * flix_kernel_time returns the summed milliseconds and launch count since the
- * last reset.  Families: "sort", "read_apply", "insert_apply", "delete_apply",
- * "pre". */
+ * last reset.  Each family is one kernel: "sort_hist" (digit histograms),
+ * "sort_pass" (one onesweep pass), "read_apply" (lookup/successor/range
+ * bucket kernel), "slices" (update slice discovery and node budget),
+ * "insert_apply", "delete_apply".  Enabling or disabling resets the sums. */
 /* Text describing the last HIP runtime error a call of this host thread hit
  * (which call and the runtime's message); "" if none.  Never NULL. */
 const char* flix_last_error(void);

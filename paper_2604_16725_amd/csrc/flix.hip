@@ -19,18 +19,18 @@ using namespace flix;
 
 namespace {
 
-constexpr int kFamilies = 5;
-const char* kFamilyNames[kFamilies] = {"sort", "read_apply", "insert_apply", "delete_apply",
-                                       "pre"};
-enum Family { F_SORT = 0, F_READ = 1, F_INSERT = 2, F_DELETE = 3, F_PRE = 4 };
+constexpr int kFamilies = 6;
+const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
+                                       "insert_apply", "delete_apply"};
+enum Family { F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5 };
 
 struct Timing {
   bool on = false;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  double ms[kFamilies] = {0, 0, 0, 0, 0};
-  uint64_t count[kFamilies] = {0, 0, 0, 0, 0};
+  double ms[kFamilies] = {0, 0, 0, 0, 0, 0};
+  uint64_t count[kFamilies] = {0, 0, 0, 0, 0, 0};
 };
 
 }  // namespace
@@ -207,14 +207,20 @@ __global__ void k_reset_call(Ctl* ctl) {
   ctl->heavy_cursor = 0;
 }
 
+void sort_hook_begin(void* ctx, hipStream_t st, void** tok) {
+  hipEvent_t b;
+  tm_begin(static_cast<flix_store*>(ctx), st, &b);
+  *tok = b;
+}
+void sort_hook_end(void* ctx, hipStream_t st, int fam, void* tok) {
+  tm_end(static_cast<flix_store*>(ctx), st, fam == 0 ? F_HIST : F_PASS,
+         static_cast<hipEvent_t>(tok));
+}
+
 template <typename K>
 int sort_batch(flix_store* s, const void* keys, const void* vals, u64 n, int pay, hipStream_t st,
                int* r) {
-  hipEvent_t b;
-  tm_begin(s, st, &b);
-  int rc = sort_batch_t<K>(s, (const K*)keys, (const K*)vals, (u32)n, pay, st, r);
-  tm_end(s, st, F_SORT, b);
-  return rc;
+  return sort_batch_t<K>(s, (const K*)keys, (const K*)vals, (u32)n, pay, st, r);
 }
 
 // ---- read path --------------------------------------------------------------
@@ -790,6 +796,9 @@ int flix_set_timing(flix_store* s, int enable) {
   if (!s) return FLIX_ESTATE;
   tm_collect(s);
   s->tm.on = enable != 0;
+  s->ss.on_begin = s->tm.on ? sort_hook_begin : nullptr;
+  s->ss.on_end = s->tm.on ? sort_hook_end : nullptr;
+  s->ss.hook_ctx = s;
   for (int i = 0; i < kFamilies; ++i) {
     s->tm.ms[i] = 0;
     s->tm.count[i] = 0;

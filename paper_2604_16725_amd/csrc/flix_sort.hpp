@@ -249,6 +249,22 @@ struct SortScratch {
   u32 epoch = 0;            // last epoch used
   u32 parity = 0;           // histogram slot of the next call
   u64 max_items = 0;        // capacity of the status array, in items
+  // optional per-kernel timing hooks (family 0: histogram, 1: one pass)
+  void (*on_begin)(void* ctx, hipStream_t st, void** tok) = nullptr;
+  void (*on_end)(void* ctx, hipStream_t st, int family, void* tok) = nullptr;
+  void* hook_ctx = nullptr;
+};
+
+struct SortTimer {
+  SortScratch& s;
+  hipStream_t st;
+  void* tok = nullptr;
+  SortTimer(SortScratch& s_, hipStream_t st_) : s(s_), st(st_) {
+    if (s.on_begin) s.on_begin(s.hook_ctx, st, &tok);
+  }
+  void end(int fam) {
+    if (s.on_end) s.on_end(s.hook_ctx, st, fam, tok);
+  }
 };
 
 constexpr int kSortNT = 256;
@@ -278,8 +294,12 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
   s.parity ^= 1u;
   u32 hb = (n + 256u * 16u - 1u) / (256u * 16u);
   if (hb > 1024u) hb = 1024u;
-  hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(hb), dim3(256), 0, st, kin, n, hist, hist_next,
-                     s.tile_ctr);
+  {
+    SortTimer t(s, st);
+    hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(hb), dim3(256), 0, st, kin, n, hist,
+                       hist_next, s.tile_ctr);
+    t.end(0);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int p = 0; p < P; ++p) {
@@ -293,9 +313,11 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     const V* vi = (p == 0) ? vin : ((p & 1) ? v0 : v1);
     K* ko = (p & 1) ? k1 : k0;
     V* vo = (p & 1) ? v1 : v0;
+    SortTimer t(s, st);
     hipLaunchKernelGGL((k_onesweep<K, V, RB, kSortNT, kSortIPT, PAY>), dim3(ntiles),
                        dim3(kSortNT), 0, st, ki, vi, ko, vo, n, (u32)(p * RB),
                        hist + p * R, s.status, s.tile_ctr + p, ntiles, epoch, s.err);
+    t.end(1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

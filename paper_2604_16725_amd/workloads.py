@@ -167,7 +167,8 @@ def tiny_plain(seed_round: int = 0):
 
 
 def read_path(n_keys: int = 1 << 26, batch: int = 1 << 20, range_len: int = 16,
-              zipf_s: float = 0.99, seed_round: int = 0, with_zipf: bool = True):
+              zipf_s: float = 0.99, seed_round: int = 0, with_zipf: bool = True,
+              with_updates: bool = False):
     """Read-path workload: u32 keys/values, node capacity 128.
 
     Bulk load ``n_keys`` distinct uniform keys.  Batches of ``batch`` ops:
@@ -176,6 +177,8 @@ def read_path(n_keys: int = 1 << 26, batch: int = 1 << 20, range_len: int = 16,
     uniform lo.  The Zipf variants draw present keys by Zipf(s) rank, ranks
     mapped to keys through the counter order of the keyed bijection (which
     scatters hot keys over the key space); Zipf lookups keep 10% absent keys.
+    With ``with_updates`` it also returns ``batch`` new keys (never present)
+    with values, for an insert batch followed by a delete of the same keys.
     """
     cfg = 1
     kb = 32
@@ -201,6 +204,10 @@ def read_path(n_keys: int = 1 << 26, batch: int = 1 << 20, range_len: int = 16,
         zhi = np.minimum(zlo + np.uint64(range_len - 1), np.uint64(0xFFFFFFFF))
         out.update(zipf_lookup=zl, zipf_successor=zs, zipf_range_lo=zlo.astype(np.uint32),
                    zipf_range_hi=zhi.astype(np.uint32))
+    if with_updates:
+        ins = ks.fresh(batch)
+        out.update(insert_keys=ins,
+                   insert_vals=values_for(ins, seed_for(cfg, seed_round + 1, STREAM_VALS), kb))
     return out
 
 
