@@ -12,6 +12,7 @@
 #include "flix_build.hpp"
 #include "flix_device.hpp"
 #include "flix_read.hpp"
+#include "flix_read2.hpp"
 #include "flix_sort.hpp"
 #include "flix_update.hpp"
 
@@ -134,6 +135,11 @@ int ensure_sort_capacity(flix_store* s, u64 items) {
   int rc = dev_alloc(&s->ss.status, words * sizeof(u64));
   if (rc) return rc;
   HIP_TRY(hipMemset(s->ss.status, 0, words * sizeof(u64)));
+  dev_free(&s->ss.status_cl);
+  u64 cwords = sort_cluster_words(items);
+  rc = dev_alloc(&s->ss.status_cl, cwords * sizeof(u64));
+  if (rc) return rc;
+  HIP_TRY(hipMemset(s->ss.status_cl, 0, cwords * sizeof(u64)));
   s->ss.epoch = 0;
   s->ss.max_items = items;
   return FLIX_OK;
@@ -229,13 +235,38 @@ struct ReadCfg;
 template <>
 struct ReadCfg<u32> {
   static constexpr int S = 512;
-  static constexpr int STAGE = 2560;
 };
 template <>
 struct ReadCfg<u64> {
-  static constexpr int S = 256;
-  static constexpr int STAGE = 2560;
+  static constexpr int S = 512;
 };
+
+template <typename K, int GL, int KPL>
+void launch_read2_k(const ReadArgs<K>& a, int op, u32 grid, hipStream_t st) {
+  constexpr int U = KPL >= 16 ? 2 : 4;
+  hipLaunchKernelGGL((k_read_apply2<K, 256, ReadCfg<K>::S, GL, KPL, U>), dim3(grid), dim3(256), 0,
+                     st, a, op);
+}
+
+// Lanes per bucket GL and keys per lane KPL = max(1, cap / GL).
+template <typename K>
+void launch_read2(const flix_store* s, const ReadArgs<K>& a, int op, u32 grid, hipStream_t st) {
+  const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
+  switch (s->gl * 100 + kpl) {
+    case 1601: launch_read2_k<K, 16, 1>(a, op, grid, st); break;
+    case 1602: launch_read2_k<K, 16, 2>(a, op, grid, st); break;
+    case 1604: launch_read2_k<K, 16, 4>(a, op, grid, st); break;
+    case 1608: launch_read2_k<K, 16, 8>(a, op, grid, st); break;
+    case 1616: launch_read2_k<K, 16, 16>(a, op, grid, st); break;
+    case 3201: launch_read2_k<K, 32, 1>(a, op, grid, st); break;
+    case 3202: launch_read2_k<K, 32, 2>(a, op, grid, st); break;
+    case 3204: launch_read2_k<K, 32, 4>(a, op, grid, st); break;
+    case 3208: launch_read2_k<K, 32, 8>(a, op, grid, st); break;
+    case 6401: launch_read2_k<K, 64, 1>(a, op, grid, st); break;
+    case 6402: launch_read2_k<K, 64, 2>(a, op, grid, st); break;
+    default: launch_read2_k<K, 64, 4>(a, op, grid, st); break;
+  }
+}
 
 template <typename K>
 int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void* out_v,
@@ -260,17 +291,9 @@ int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void
   a.counts = counts;
   a.maxpq = maxpq;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
-  constexpr int NT = 256;
-  constexpr int SS = ReadCfg<K>::S;
-  constexpr int ST = ReadCfg<K>::STAGE;
   hipEvent_t b;
   tm_begin(s, st, &b);
-  if (op == kOpLookup)
-    hipLaunchKernelGGL((k_read_apply<K, NT, SS, ST, kOpLookup>), dim3(grid), dim3(NT), 0, st, a);
-  else if (op == kOpSuccessor)
-    hipLaunchKernelGGL((k_read_apply<K, NT, SS, ST, kOpSuccessor>), dim3(grid), dim3(NT), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_read_apply<K, NT, SS, ST, kOpRange>), dim3(grid), dim3(NT), 0, st, a);
+  launch_read2<K>(s, a, op, (u32)grid, st);
   tm_end(s, st, F_READ, b);
   HIP_TRY(hipGetLastError());
   return FLIX_OK;
@@ -359,7 +382,7 @@ int update_batch(flix_store* s, bool insert, const void* keys, const void* vals,
   ua.work = s->work;
   ua.ctl = s->ctl;
   ua.status = &s->ctl->status;
-  u32 lds_items = insert ? upd_lds_items(s) : s->cap;
+  u32 lds_items = upd_lds_items(s);
   u64 items = std::min<u64>(n, s->nb);
   u32 gpb = kUpdNT / s->gl;
   u64 g2 = (items + 2 * gpb - 1) / (2 * gpb);
@@ -495,6 +518,7 @@ void destroy_all(flix_store* s) {
   dev_free(&s->work);
   dev_free(&s->ss.hist);
   dev_free(&s->ss.status);
+  dev_free(&s->ss.status_cl);
   dev_free(&s->ss.tile_ctr);
   dev_free(&s->ss.err);
   for (auto e : s->tm.pool) (void)hipEventDestroy(e);

@@ -1,0 +1,324 @@
+// Read batches, register-resident form (the default read kernel).
+//
+// Same flipped structure as flix_read.hpp (Section 3.3: every bucket pulls the
+// slice of the sorted batch that falls into (MKBA[i-1], MKBA[i]]), organised
+// for wave64 latency hiding:
+//   1. merge-path cut of "MKBA (+) sorted batch" into equal shares, found by a
+//      cooperative 128-ary search (three dependent rounds instead of ~21);
+//   2. one coalesced round of loads: the share's keys, their input positions,
+//      MKBA entries and node headers (and range upper bounds);
+//   3. every bucket takes its slice by upper_bound of its maxBucket in LDS;
+//   4. phase A: groups of GL lanes hold the live keys of U buckets at a time in
+//      registers (KPL keys per lane, 16-byte loads) and resolve each key of the
+//      slice with ballots: lookup match, successor / range lower and upper
+//      bounds inside the node; the result position goes to LDS;
+//   5. phase B: one lane per key loads the value(s) and writes the outputs,
+//      all keys of the share in flight at once.
+// Keys whose answer lies outside the single staged node (chained buckets, a
+// successor or range running past the node's end) take the global-memory path
+// of flix_read.hpp.
+#pragma once
+
+#include "flix_device.hpp"
+#include "flix_read.hpp"
+
+namespace flix {
+
+constexpr u32 kPosMiss = 0xFFFFu;   // lookup miss inside a single-node bucket
+constexpr u32 kPosSlow = 0xFFFEu;   // resolve on the global-memory path
+
+// Cooperative merge-path cut for the two diagonals d[0], d[1] of one
+// workgroup (NT == 256: threads 0..127 search d[0], 128..255 search d[1]).
+// Returns, for both diagonals, the number of batch keys among the first d
+// items of merge(keys, mkba) with ties to the keys.
+template <typename K>
+__device__ void coop_merge_path(const K* a, u32 na, const K* mk, u32 nm, const u64 d[2],
+                                u32* s_lo, u32* s_hi, u32* s_wc, u32* out) {
+  const u32 tid = threadIdx.x;
+  const u32 half = tid >> 7;
+  const u32 t = tid & 127;
+  if (t == 0) {
+    u64 dd = d[half];
+    s_lo[half] = dd > nm ? (u32)(dd - nm) : 0u;
+    s_hi[half] = dd < na ? (u32)dd : na;
+  }
+  __syncthreads();
+  for (int round = 0; round < 8; ++round) {
+    const u32 lo = s_lo[half], hi = s_hi[half];
+    const bool any = (s_lo[0] < s_hi[0]) || (s_lo[1] < s_hi[1]);
+    if (!any) break;
+    const u64 dd = d[half];
+    const u32 span = hi - lo;
+    u32 p = 0;
+    bool pred = false;
+    if (span > 0) {
+      p = span <= 128 ? lo + t : lo + (u32)(((u64)span * t) / 128u);
+      if (span > 128 || t < span) pred = a[p] <= mk[(u32)(dd - p - 1)];
+    }
+    u64 bal = wave_ballot(pred);
+    if ((tid & 63) == 0) s_wc[tid >> 6] = (u32)__popcll(bal);
+    __syncthreads();
+    if (t == 0 && span > 0) {
+      u32 c = s_wc[2 * half] + s_wc[2 * half + 1];
+      if (span <= 128) {
+        s_lo[half] = lo + c;
+        s_hi[half] = lo + c;
+      } else if (c == 0) {
+        s_hi[half] = lo;
+      } else {
+        u32 pl = lo + (u32)(((u64)span * (c - 1)) / 128u);
+        s_lo[half] = pl + 1;
+        if (c < 128) s_hi[half] = lo + (u32)(((u64)span * c) / 128u);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < 2) out[tid] = s_lo[tid];
+  __syncthreads();
+}
+
+template <typename K, int KPL>
+struct alignas(sizeof(K) * KPL >= 16 ? 16 : sizeof(K) * KPL) KeyVec {
+  K k[KPL];
+};
+
+template <typename K, int NT, int S, int GL, int KPL, int U>
+__global__ __launch_bounds__(NT) void k_read_apply2(ReadArgs<K> a, int op) {
+  static_assert(NT == 256, "merge-path search assumes 256 threads");
+  constexpr int NG = NT / GL;
+  __shared__ K s_q[S];
+  __shared__ K s_hi[S];
+  __shared__ u32 s_idx[S];
+  __shared__ u32 s_pos[S];       // (local bucket << 16) | position / code
+  __shared__ u32 s_cnt[S];       // range: results inside the node
+  __shared__ K s_mk[S];
+  __shared__ u32 s_e[S + 1];
+  __shared__ u32 s_hsz[S + 1];
+  __shared__ u32 s_hnx[S + 1];
+  __shared__ unsigned short s_tl[S + 1];
+  __shared__ u32 s_tmp[NT / 64 + 1];
+  __shared__ u32 s_lo[2], s_hiw[2], s_wc[4], s_cut[2], s_ntouch;
+
+  const u32 tid = threadIdx.x;
+  const u64 total = (u64)a.m + a.nb;
+  u64 d[2];
+  d[0] = (u64)blockIdx.x * a.share;
+  d[1] = d[0] + a.share < total ? d[0] + a.share : total;
+  coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
+  const u32 q0 = s_cut[0], q1 = s_cut[1];
+  const u32 b0 = (u32)(d[0] - q0), b1 = (u32)(d[1] - q1);
+  const u32 nq = q1 - q0;
+  if (nq == 0) return;
+  const u32 nbl = b1 - b0;
+
+  // One round of coalesced loads.
+  for (u32 j = tid; j < nq; j += NT) {
+    s_q[j] = a.skeys[q0 + j];
+    u32 ix = a.sidx[q0 + j];
+    s_idx[j] = ix;
+    if (op == kOpRange) s_hi[j] = a.hi[ix];
+  }
+  for (u32 i = tid; i <= nbl; i += NT) {
+    if (i < nbl) s_mk[i] = a.mkba[b0 + i];
+    u32 sz = 0, nx = kNil;
+    if (b0 + i < a.nb) {
+      NodeHdr h = a.hdr[b0 + i];
+      sz = h.size;
+      nx = h.next;
+    }
+    s_hsz[i] = sz;
+    s_hnx[i] = nx;
+  }
+  __syncthreads();
+
+  // Bound search: every bucket pulls its slice; compact the touched buckets.
+  constexpr u32 PER = (S + 1 + NT - 1) / NT;
+  u32 flags = 0, nt = 0;
+#pragma unroll
+  for (u32 r = 0; r < PER; ++r) {
+    u32 lb = tid * PER + r;
+    if (lb <= nbl) {
+      u32 e = (lb < nbl) ? upper_bound_idx<K>(s_q, 0u, nq, s_mk[lb]) : nq;
+      s_e[lb] = e;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (u32 r = 0; r < PER; ++r) {
+    u32 lb = tid * PER + r;
+    if (lb <= nbl) {
+      u32 s = lb ? s_e[lb - 1] : 0u;
+      if (s_e[lb] > s) {
+        flags |= 1u << r;
+        ++nt;
+      }
+    }
+  }
+  u32 ntot;
+  u32 w = block_exclusive_scan<NT>(nt, s_tmp, &ntot);
+#pragma unroll
+  for (u32 r = 0; r < PER; ++r)
+    if (flags & (1u << r)) s_tl[w++] = (unsigned short)(tid * PER + r);
+  if (tid == 0) s_ntouch = ntot;
+  __syncthreads();
+  const u32 ntouch = s_ntouch;
+
+  // Phase A: groups resolve positions inside single-node buckets.
+  {
+    const u32 gid = tid / GL;
+    const u32 gl = tid % GL;
+    const u32 gbase = (tid & 63) - gl;
+    const u64 gmask = (GL == 64) ? ~0ull : (((1ull << GL) - 1ull) << gbase);
+    for (u32 i0 = gid * U; i0 < ntouch; i0 += NG * U) {
+      KeyVec<K, KPL> kv[U];
+      u32 lbs[U], sizes[U];
+      bool single[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        u32 i = i0 + u;
+        lbs[u] = i < ntouch ? s_tl[i] : 0u;
+        sizes[u] = (i < ntouch) ? s_hsz[lbs[u]] : 0u;
+        single[u] = (i < ntouch) && s_hnx[lbs[u]] == kNil;
+        if (single[u] && gl * KPL < sizes[u]) {
+          const KeyVec<K, KPL>* src = reinterpret_cast<const KeyVec<K, KPL>*>(
+              a.nkeys + (u64)(b0 + lbs[u]) * a.cap + (u64)gl * KPL);
+          kv[u] = *src;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (i0 + u >= ntouch) break;
+        const u32 lb = lbs[u];
+        const u32 s = lb ? s_e[lb - 1] : 0u;
+        const u32 e = s_e[lb];
+        const u32 size = sizes[u];
+        if (!single[u]) {
+          for (u32 j = s + gl; j < e; j += GL) s_pos[j] = (lb << 16) | kPosSlow;
+          continue;
+        }
+        for (u32 j = s; j < e; ++j) {
+          const K x = s_q[j];
+          if (op == kOpLookup) {
+            int hit = -1;
+#pragma unroll
+            for (int k = 0; k < KPL; ++k)
+              if (gl * KPL + k < size && kv[u].k[k] == x) hit = k;
+            u64 bal = wave_ballot(hit >= 0) & gmask;
+            if (bal == 0) {
+              if (gl == 0) s_pos[j] = (lb << 16) | kPosMiss;
+            } else if (hit >= 0) {
+              s_pos[j] = (lb << 16) | (gl * KPL + (u32)hit);
+            }
+          } else {
+            // lower bound of x (and upper bound of hi for ranges)
+            u32 lt = 0, le = 0;
+            const K hi = (op == kOpRange) ? s_hi[j] : K(0);
+#pragma unroll
+            for (int k = 0; k < KPL; ++k) {
+              bool v = gl * KPL + k < size;
+              lt += (u32)__popcll(wave_ballot(v && kv[u].k[k] < x) & gmask);
+              if (op == kOpRange) le += (u32)__popcll(wave_ballot(v && kv[u].k[k] <= hi) & gmask);
+            }
+            if (gl == 0) {
+              u32 code;
+              if (op == kOpSuccessor) {
+                code = lt < size ? lt : kPosSlow;
+              } else {
+                if (x > hi) {
+                  code = 0;
+                  s_cnt[j] = 0;
+                } else if (le < size) {
+                  code = lt;
+                  s_cnt[j] = le > lt ? le - lt : 0u;
+                } else {
+                  code = kPosSlow;   // range may continue past this node
+                }
+              }
+              s_pos[j] = (lb << 16) | code;
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // Phase B: one lane per key.
+  const K NF = key_max<K>();
+  for (u32 j = tid; j < nq; j += NT) {
+    const u32 code = s_pos[j];
+    const u32 lb = code >> 16;
+    const u32 pos = code & 0xFFFFu;
+    u32 b = b0 + lb;
+    const u32 orig = s_idx[j];
+    const K x = s_q[j];
+    if (pos != kPosSlow) {
+      const u64 nb_ = (u64)b * a.cap;
+      if (op == kOpLookup) {
+        a.out_v[orig] = (pos == kPosMiss) ? NF : a.nvals[nb_ + pos];
+      } else if (op == kOpSuccessor) {
+        a.out_k[orig] = a.nkeys[nb_ + pos];
+        a.out_v[orig] = a.nvals[nb_ + pos];
+      } else {
+        const u32 cnt = s_cnt[j];
+        const u32 wn = cnt < a.maxpq ? cnt : a.maxpq;
+        const u64 ob = (u64)orig * a.maxpq;
+        for (u32 r = 0; r < wn; ++r) {
+          if (a.out_k) a.out_k[ob + r] = a.nkeys[nb_ + pos + r];
+          if (a.out_v) a.out_v[ob + r] = a.nvals[nb_ + pos + r];
+        }
+        a.counts[orig] = cnt;
+      }
+      continue;
+    }
+    // Global-memory path: walk the chain to the node holding x.
+    NodeHdr h;
+    u32 node = locate_node(a.hdr, b, (u64)x, &h);
+    const K* keys = a.nkeys + (u64)node * a.cap;
+    u32 p = lower_bound_idx<K>(keys, 0u, h.size, x);
+    if (op == kOpLookup) {
+      a.out_v[orig] = (p < h.size && keys[p] == x) ? a.nvals[(u64)node * a.cap + p] : NF;
+    } else if (op == kOpSuccessor) {
+      K rk = NF, rv = NF;
+      if (p < h.size) {
+        rk = keys[p];
+        rv = a.nvals[(u64)node * a.cap + p];
+      } else {
+        NodeHdr g;
+        u32 nn = next_nonempty(a.hdr, a.nb, &b, h, &g);
+        if (nn != kNil) {
+          rk = a.nkeys[(u64)nn * a.cap];
+          rv = a.nvals[(u64)nn * a.cap];
+        }
+      }
+      a.out_k[orig] = rk;
+      a.out_v[orig] = rv;
+    } else {
+      const K hi = s_hi[j];
+      u32 cnt = 0;
+      if (x <= hi) {
+        const u64 ob = (u64)orig * a.maxpq;
+        while (true) {
+          u32 ub = upper_bound_idx<K>(keys, p, h.size, hi);
+          for (u32 r = p; r < ub; ++r, ++cnt) {
+            if (cnt < a.maxpq) {
+              if (a.out_k) a.out_k[ob + cnt] = keys[r];
+              if (a.out_v) a.out_v[ob + cnt] = a.nvals[(u64)node * a.cap + r];
+            }
+          }
+          if (ub < h.size) break;
+          NodeHdr g;
+          u32 nn = next_nonempty(a.hdr, a.nb, &b, h, &g);
+          if (nn == kNil) break;
+          node = nn;
+          h = g;
+          keys = a.nkeys + (u64)node * a.cap;
+          p = 0;
+        }
+      }
+      a.counts[orig] = cnt;
+    }
+  }
+}
+
+}  // namespace flix

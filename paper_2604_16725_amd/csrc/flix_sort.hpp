@@ -65,6 +65,9 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
     if (sh[i]) atomicAdd(&hist[i], sh[i]);
 }
 
+constexpr u32 kSortCluster = 16;   // tiles per look-back cluster
+constexpr u32 kLookWindow = 16;    // statuses read per look-back round trip
+
 // Payload modes.
 constexpr int kPayNone = 0;    // keys only
 constexpr int kPayIndex = 1;   // payload is u32; vin == nullptr means "input index"
@@ -76,8 +79,8 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
                                                  K* __restrict__ kout, V* __restrict__ vout,
                                                  u32 n, u32 shift,
                                                  const u32* __restrict__ hist_p,
-                                                 u64* status, u32* tile_ctr, u32 ntiles,
-                                                 u32 epoch, u32* err) {
+                                                 u64* status, u64* status_cl, u32* tile_ctr,
+                                                 u32 ntiles, u32 epoch, u32* err) {
   constexpr int R = 1 << RB;
   constexpr int WAVES = NT / 64;
   constexpr int TILE = NT * IPT;
@@ -96,27 +99,18 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
   const u32 lane = tid & 63;
   const u32 w = tid >> 6;
 
-  if (tid == 0) {
-    s_tile = atomicAdd(tile_ctr, 1u);
-    s_trivial = 0;
-  }
+  // Tiles are numbered by workgroup id: workgroups are dispatched in id order,
+  // so every predecessor a tile waits on is resident or finished.  (A shared
+  // ticket counter would serialise 512+ same-address atomics per pass.)
+  if (tid == 0) s_trivial = 0;
   for (int i = tid; i < WAVES * R; i += NT) (&s_wc[0][0])[i] = 0;
   __syncthreads();
-  const u32 tile = s_tile;
-  if (tile >= ntiles) {   // ticket counter out of step: never expected
-    if (tid == 0) atomicOr(err, 2u);
-    return;
-  }
+  const u32 tile = blockIdx.x;
+  (void)tile_ctr;
+  (void)s_tile;
   const u32 tile0 = tile * (u32)TILE;
 
-  // Global exclusive digit offsets of this pass, and the trivial-pass test
-  // (all keys share one digit: the stable permutation is the identity).
-  u32 hcount = (tid < (u32)R) ? hist_p[tid] : 0u;
-  if (tid < (u32)R && hcount == n) s_trivial = 1;
-  u32 htotal;
-  u32 hexcl = block_exclusive_scan<NT>(hcount, s_tmp, &htotal);
-
-  // Load items (wave-striped).
+  // Load items (wave-striped) and this pass's digit counts in one round.
   K key[IPT];
   V pay[IPT];
 #pragma unroll
@@ -131,6 +125,13 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
       if (PAY != kPayNone) pay[k] = V(0);
     }
   }
+  u32 hcount = (tid < (u32)R) ? hist_p[tid] : 0u;
+
+  // Global exclusive digit offsets of this pass, and the trivial-pass test
+  // (all keys share one digit: the stable permutation is the identity).
+  if (tid < (u32)R && hcount == n) s_trivial = 1;
+  u32 htotal;
+  u32 hexcl = block_exclusive_scan<NT>(hcount, s_tmp, &htotal);
 
   if (s_trivial) {  // uniform across the grid: no look-back is needed
 #pragma unroll
@@ -184,30 +185,77 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
   u32 lstart = block_exclusive_scan<NT>(tid < (u32)R ? tot : 0u, s_tmp, &dummy);
   if (tid < (u32)R) {
     s_lstart[tid] = lstart;
-    // Decoupled look-back over preceding tiles for this digit.
+    // Two-level decoupled look-back for this digit.  Tiles form clusters of
+    // CL consecutive tiles; the last tile of a cluster also publishes the
+    // cluster's aggregate (or inclusive prefix) once it has read its cluster
+    // mates.  A tile sums the published counts of its cluster mates (nearest
+    // first, LB per round trip) and then those of earlier clusters, stopping
+    // at the first inclusive prefix, so the chain of dependent round trips
+    // stays short however many tiles the pass has.
     u32 excl = 0;
     if (tile > 0) {
-      u32 pt = tile - 1;
+      const u32 c = tile / kSortCluster;
+      const u32 cbeg = c * kSortCluster;
+      const bool last_of_cluster = (tile == cbeg + kSortCluster - 1);
+      bool done = false;
+      bool gave_up = false;
       u32 polls = 0;
-      while (true) {
-        u64 s = ld_agent(&status[(u64)pt * R + tid]);
-        u32 ep = (u32)(s >> 34);
-        u32 fl = (u32)(s >> 32) & 3u;
-        if (ep != epoch || fl == 0) {
+      // (1) cluster mates [cbeg, tile)
+      u32 pt = tile;
+      while (!done && pt > cbeg) {
+        u64 win[kLookWindow];
+#pragma unroll
+        for (u32 w = 0; w < kLookWindow; ++w)
+          win[w] = (w < pt - cbeg) ? ld_agent(&status[(u64)(pt - 1 - w) * R + tid]) : 0ull;
+        u32 used = 0;
+#pragma unroll
+        for (u32 w = 0; w < kLookWindow; ++w) {
+          if (done || w != used || w >= pt - cbeg) continue;
+          u64 s = win[w];
+          u32 fl = (u32)(s >> 32) & 3u;
+          if ((u32)(s >> 34) != epoch || fl == 0) continue;   // not published yet
+          excl += (u32)s;
+          ++used;
+          if (fl == kFlagPre) done = true;
+        }
+        pt -= used;
+        if (!done && used == 0) {
           // Bounded wait: a predecessor that never publishes is a bug, and the
           // kernel must still end; the error word reports it.
-          if (++polls > (1u << 22)) {
-            atomicOr(err, 1u);
-            break;
-          }
+          if (++polls > (1u << 22)) { atomicOr(err, 1u); gave_up = true; break; }
           __builtin_amdgcn_s_sleep(1);
-          continue;
         }
-        excl += (u32)s;
-        if (fl == kFlagPre || pt == 0) break;
-        --pt;
+      }
+      if (last_of_cluster && !gave_up)
+        st_agent(&status_cl[(u64)c * R + tid],
+                 pack_status(epoch, done ? kFlagPre : kFlagAgg, excl + tot));
+      // (2) earlier clusters [0, c)
+      u32 pc = c;
+      while (!done && !gave_up && pc > 0) {
+        u64 win[kLookWindow];
+#pragma unroll
+        for (u32 w = 0; w < kLookWindow; ++w)
+          win[w] = (w < pc) ? ld_agent(&status_cl[(u64)(pc - 1 - w) * R + tid]) : 0ull;
+        u32 used = 0;
+#pragma unroll
+        for (u32 w = 0; w < kLookWindow; ++w) {
+          if (done || w != used || w >= pc) continue;
+          u64 s = win[w];
+          u32 fl = (u32)(s >> 32) & 3u;
+          if ((u32)(s >> 34) != epoch || fl == 0) continue;
+          excl += (u32)s;
+          ++used;
+          if (fl == kFlagPre) done = true;
+        }
+        pc -= used;
+        if (!done && used == 0) {
+          if (++polls > (1u << 22)) { atomicOr(err, 1u); gave_up = true; break; }
+          __builtin_amdgcn_s_sleep(1);
+        }
       }
       st_agent(&status[(u64)tile * R + tid], pack_status(epoch, kFlagPre, excl + tot));
+      if (last_of_cluster && !gave_up)
+        st_agent(&status_cl[(u64)c * R + tid], pack_status(epoch, kFlagPre, excl + tot));
     }
     s_gbase[tid] = hexcl + excl;
   }
@@ -244,6 +292,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
 struct SortScratch {
   u32* hist = nullptr;      // [2][P*R] ping-pong histogram slots
   u64* status = nullptr;    // [max_tiles * R]
+  u64* status_cl = nullptr; // [max_tiles / cluster * R]
   u32* tile_ctr = nullptr;  // [16] per-pass tile ticket counters (cleared by k_radix_hist)
   u32* err = nullptr;       // sticky sort error bits (1: look-back wait gave up, 2: bad ticket)
   u32 epoch = 0;            // last epoch used
@@ -273,6 +322,9 @@ constexpr int kSortTile = kSortNT * kSortIPT;
 
 inline u64 sort_status_words(u64 max_items, int rb) {
   return ((max_items + kSortTile - 1) / kSortTile + 1) * (u64)(1 << rb);
+}
+inline u64 sort_cluster_words(u64 max_items) {
+  return ((max_items + kSortTile - 1) / kSortTile / kSortCluster + 2) * 256ull;
 }
 
 // Host driver: sorts n pairs from (kin, vin) using ping-pong buffers
@@ -306,6 +358,8 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     if (s.epoch >= (1u << 30) - 1u) {
       e = hipMemsetAsync(s.status, 0, sort_status_words(s.max_items, RB) * sizeof(u64), st);
       if (e != hipSuccess) return e;
+      e = hipMemsetAsync(s.status_cl, 0, sort_cluster_words(s.max_items) * sizeof(u64), st);
+      if (e != hipSuccess) return e;
       s.epoch = 0;
     }
     const u32 epoch = ++s.epoch;
@@ -316,7 +370,8 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     SortTimer t(s, st);
     hipLaunchKernelGGL((k_onesweep<K, V, RB, kSortNT, kSortIPT, PAY>), dim3(ntiles),
                        dim3(kSortNT), 0, st, ki, vi, ko, vo, n, (u32)(p * RB),
-                       hist + p * R, s.status, s.tile_ctr + p, ntiles, epoch, s.err);
+                       hist + p * R, s.status, s.status_cl, s.tile_ctr + p, ntiles, epoch,
+                       s.err);
     t.end(1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

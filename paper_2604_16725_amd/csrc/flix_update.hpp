@@ -217,11 +217,13 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// Reads of node data this kernel may have written earlier (coherent at agent
-// scope, so never served from a stale per-CU cache line).
+// Re-reads of node data that the same wave wrote earlier in this kernel.  The
+// writer and the reader are lanes of one wave, so a workgroup-scope fence
+// between them is enough; these loads are workgroup-scope atomics so the
+// compiler can neither cache nor reorder them across that fence.
 template <typename K>
 __device__ __forceinline__ K ld_fresh(const K* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ NodeHdr ld_hdr(const NodeHdr* p, bool fresh) {
   if (!fresh) return *p;
@@ -232,6 +234,33 @@ __device__ __forceinline__ NodeHdr ld_hdr(const NodeHdr* p, bool fresh) {
   h.size = (u32)w;
   h.next = (u32)(w >> 32);
   return h;
+}
+
+// Copy n consecutive items (keys and values) into LDS: every lane issues up
+// to four loads before the first LDS store, so one round trip covers 4*GL
+// items.  `fresh` marks data this wave wrote earlier in the kernel.
+template <typename K, int GL>
+__device__ __forceinline__ void stage_items(K* dk, K* dv, const K* sk, const K* sv, u32 n,
+                                            u32 lane, bool fresh) {
+  for (u32 i0 = 0; i0 < n; i0 += 4 * GL) {
+    K kk[4], vv[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const u32 i = i0 + r * GL + lane;
+      if (i < n) {
+        kk[r] = fresh ? ld_fresh(sk + i) : sk[i];
+        vv[r] = fresh ? ld_fresh(sv + i) : sv[i];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const u32 i = i0 + r * GL + lane;
+      if (i < n) {
+        dk[i] = kk[r];
+        dv[i] = vv[r];
+      }
+    }
+  }
 }
 
 template <typename K>
@@ -309,40 +338,45 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
     u32 j = w.s;
     u32 nodes_added = 0;
     while (j < w.e) {
-      const K first = a.skeys[j];
       bool broken = false;
-      while ((u64)first > hX.fence) {   // walk to the node holding `first`
-        if (hX.next == kNil) { broken = true; break; }
-        X = hX.next;
-        hX = ld_hdr(a.hdr + X, fresh);
+      if (hX.next != kNil) {   // chain: walk to the node holding skeys[j]
+        const K first = a.skeys[j];
+        while ((u64)first > hX.fence) {
+          if (hX.next == kNil) { broken = true; break; }
+          X = hX.next;
+          hX = ld_hdr(a.hdr + X, fresh);
+        }
       }
       if (broken || hX.size > a.cap) {   // never on a consistent store
         if (g.lane == 0) atomicCAS(a.status, 0u, kErrInternal);
         break;
       }
-      u32 j2 = upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence);
+      // the last node of a chain holds every remaining key of the slice
+      u32 j2 = (hX.next == kNil) ? w.e : upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence);
       if (j2 - j > a.chunk) j2 = j + a.chunk;
-      // stage node X
       const u32 sa = hX.size;
-      for (u32 i = g.lane; i < sa; i += GL) {
-        const u64 o = (u64)X * a.cap + i;
-        ak[i] = fresh ? ld_fresh(a.nkeys + o) : a.nkeys[o];
-        av[i] = fresh ? ld_fresh(a.nvals + o) : a.nvals[o];
-      }
-      // stage the chunk, keeping the last item of each equal-key run
+      // stage the chunk (loads first), keeping the last item of each
+      // equal-key run, then node X
       u32 tb = 0;
       for (u32 base = j; base < j2; base += GL) {
         u32 idx = base + g.lane;
         bool in = idx < j2;
-        K kk = in ? a.skeys[idx] : K(0);
-        bool live = in && (idx + 1 == a.m || a.skeys[idx + 1] != kk);
+        K kk = K(0), kn = K(0), vv = K(0);
+        if (in) {
+          kk = a.skeys[idx];
+          vv = a.svals[idx];
+          if (idx + 1 < a.m) kn = a.skeys[idx + 1];
+        }
+        bool live = in && (idx + 1 == a.m || kn != kk);
         u32 r = g.rank(live);
         if (live) {
           bk[tb + r] = kk;
-          bv[tb + r] = a.svals[idx];
+          bv[tb + r] = vv;
         }
         tb += g.count(live);
       }
+      stage_items<K, GL>(ak, av, a.nkeys + (u64)X * a.cap, a.nvals + (u64)X * a.cap, sa, g.lane,
+                         fresh);
       wave_lds_sync();
       if (tb == 0) {   // only shadowed duplicates in this chunk
         j = j2;
@@ -438,12 +472,14 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
         }
       }
       j = j2;
-      fresh = true;
-      // The next batch keys may fall into any piece: continue the walk from
-      // piece 0 (X) with coherent reads of what this group just wrote.
-      __threadfence();
+      if (j < w.e) {
+        // More keys for this bucket: they may fall into any piece, so the walk
+        // continues from piece 0 (X), reading what this wave just wrote.
+        fresh = true;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (k > 1) hX = ld_hdr(a.hdr + X, true);
+      }
       wave_lds_sync();
-      if (k > 1 && j < w.e) hX = ld_hdr(a.hdr + X, true);
     }
     if (nodes_added && g.lane == 0) a.bnodes[w.b] += nodes_added;
   }
@@ -470,8 +506,9 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
   __shared__ unsigned long long s_removed;
   Group<GL> g;
   const u32 gid = threadIdx.x / GL;
-  K* ak = reinterpret_cast<K*>(s_dyn) + (size_t)gid * 2 * lds_items;
-  K* av = ak + lds_items;
+  K* ak = reinterpret_cast<K*>(s_dyn) + (size_t)gid * 2 * lds_items;   // node keys [cap]
+  K* av = ak + lds_items;                                               // node values [cap]
+  K* bk = ak + a.cap;                                                   // slice keys [chunk]
   if (threadIdx.x == 0) s_removed = 0;
   __syncthreads();
   const u32 nitems = a.ctl->heavy_count;
@@ -490,7 +527,9 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
     u32 j = w.s;
     int freed = 0;
     while (true) {
-      u32 j2 = (j < w.e) ? upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence) : j;
+      // the last node of a chain takes every remaining key of the slice
+      u32 j2 = (j >= w.e) ? j
+               : (hX.next == kNil) ? w.e : upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence);
       const bool touched = j2 > j;
       const bool join = (P != kNil) &&
                         ((hP.size + hX.size <= f) || (p_is_head && hP.size == 0));
@@ -499,12 +538,27 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
         if (g.lane == 0) atomicCAS(a.status, 0u, kErrInternal);
         break;
       }
+      // the node's slice goes to LDS when it fits, else it is searched in place
+      const bool slice_lds = touched && (j2 - j) <= a.chunk;
+      if (slice_lds) {
+        for (u32 i0 = j; i0 < j2; i0 += 4 * GL) {
+          K kk[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            u32 i = i0 + r * GL + g.lane;
+            if (i < j2) kk[r] = a.skeys[i];
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            u32 i = i0 + r * GL + g.lane;
+            if (i < j2) bk[i - j] = kk[r];
+          }
+        }
+      }
       if (touched || join) {
         // stage X (X's data has not been written by this kernel)
-        for (u32 i = g.lane; i < sx; i += GL) {
-          ak[i] = a.nkeys[(u64)X * a.cap + i];
-          av[i] = a.nvals[(u64)X * a.cap + i];
-        }
+        stage_items<K, GL>(ak, av, a.nkeys + (u64)X * a.cap, a.nvals + (u64)X * a.cap, sx,
+                           g.lane, false);
         wave_lds_sync();
       }
       if (touched) {
@@ -517,8 +571,13 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
           if (i < sx) {
             kk = ak[i];
             vv = av[i];
-            u32 p = lower_bound_idx<K>(a.skeys, j, j2, kk);
-            keep = !(p < j2 && a.skeys[p] == kk);
+            if (slice_lds) {
+              u32 p = lower_bound_idx<K>(bk, 0u, j2 - j, kk);
+              keep = !(p < j2 - j && bk[p] == kk);
+            } else {
+              u32 p = lower_bound_idx<K>(a.skeys, j, j2, kk);
+              keep = !(p < j2 && a.skeys[p] == kk);
+            }
           }
           u32 dst = kept + g.rank(keep);
           kept += g.count(keep);
