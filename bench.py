@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
+                    help="first copy a MiB-sized device buffer 4 times (a plain copy kernel of "
+                         "known size, to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -121,6 +124,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration: 4 device copies of {args.calibrate_copy} MiB")
+        del src, dst
     n_keys, m = 1 << args.keys_log2, 1 << args.batch_log2
     t0 = time.time()
     wl = w.read_path(n_keys=n_keys, batch=m, with_zipf=not args.no_breakdown, with_updates=True)

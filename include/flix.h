@@ -171,6 +171,51 @@ int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_
  * "sort_pass" (one onesweep pass), "read_apply" (lookup/successor/range
  * bucket kernel), "slices" (update slice discovery and node budget),
  * "insert_apply", "delete_apply".  Enabling or disabling resets the sums. */
+/* ---- Persistent fused drain (a queue of mixed batches in one launch) ----
+ * One co-resident grid executes the batches in order with the same phases as
+ * the per-batch calls (sort, bound search, apply) separated by grid barriers,
+ * so a whole queue costs one launch (or one hipGraph replay).  Results are
+ * identical to issuing the batches one by one with the calls above. */
+#define FLIX_OP_LOOKUP 0
+#define FLIX_OP_SUCCESSOR 1
+#define FLIX_OP_RANGE 2
+#define FLIX_OP_INSERT 3
+#define FLIX_OP_DELETE 4
+typedef struct {
+  uint32_t op;            /* FLIX_OP_* */
+  uint32_t n;             /* operations in the batch, <= max_batch (0: skipped) */
+  uint32_t max_per_query; /* range only */
+  uint32_t reserved;      /* must be 0 */
+  const void* d_keys;     /* keys (range: lo) */
+  const void* d_aux;      /* insert: values; range: hi; otherwise NULL */
+  void* d_vals_out;       /* lookup / successor / range values */
+  void* d_keys_out;       /* successor / range keys (range: may be NULL) */
+  uint32_t* d_counts;     /* range counts */
+  void* reserved2;        /* must be NULL */
+} flix_batch;             /* 64 bytes */
+
+/* Execute nbatch batches in order in one persistent kernel launch on `stream`.
+ * h_batches (host) is validated like the per-batch calls; d_batches is the
+ * same array in device memory, read by the kernel.  d_timestamps (device,
+ * nbatch+1 entries, may be NULL) receives the device wall clock at the start
+ * and after each batch (rate: flix_drain_info).  Device-detected update
+ * errors behave as in flix_insert (batch cancelled, sticky status). */
+int flix_drain(flix_store* s, const flix_batch* h_batches, const flix_batch* d_batches,
+               uint32_t nbatch, uint64_t* d_timestamps, void* stream);
+
+/* Capture one flix_drain launch into an instantiated hipGraph (returned as an
+ * opaque hipGraphExec_t in *graph_exec).  Replays read the descriptor array in
+ * device memory again, so the caller may rewrite it between replays (same
+ * nbatch).  `stream` must not be the null stream.  Synchronizes. */
+int flix_drain_graph(flix_store* s, const flix_batch* h_batches, const flix_batch* d_batches,
+                     uint32_t nbatch, uint64_t* d_timestamps, void** graph_exec, void* stream);
+int flix_graph_launch(void* graph_exec, void* stream);
+int flix_graph_destroy(void* graph_exec);
+
+/* Workgroups of the co-resident drain grid (0 before the first drain) and the
+ * tick rate of the drain timestamps. */
+int flix_drain_info(flix_store* s, uint32_t* grid_blocks, uint64_t* timestamp_hz);
+
 /* Text describing the last HIP runtime error a call of this host thread hit
  * (which call and the runtime's message); "" if none.  Never NULL. */
 const char* flix_last_error(void);

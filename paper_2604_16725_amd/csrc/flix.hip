@@ -11,6 +11,7 @@
 #include "../../include/flix.h"
 #include "flix_build.hpp"
 #include "flix_device.hpp"
+#include "flix_drain.hpp"
 #include "flix_read.hpp"
 #include "flix_read2.hpp"
 #include "flix_sort.hpp"
@@ -59,6 +60,14 @@ struct flix_store {
   WorkItem* work = nullptr;           // [max_batch]
   SortScratch ss;
   Timing tm;
+  // persistent drain: its own look-back words, histogram slots and control
+  u64* d_status = nullptr;
+  u64* d_status_cl = nullptr;
+  u64 d_status_words = 0, d_cluster_words = 0;
+  u32* d_hist = nullptr;
+  DrainCtl* dctl = nullptr;
+  int drain_grid = 0;                 // co-resident workgroups of the drain kernel
+  size_t drain_shm = 0;
 };
 
 namespace {
@@ -368,6 +377,7 @@ int update_batch(flix_store* s, bool insert, const void* keys, const void* vals,
   HIP_TRY(hipGetLastError());
 
   UpdArgs<K> ua;
+  ua.mkba = (const K*)s->mkba;
   ua.skeys = (const K*)s->bk[r];
   ua.svals = insert ? (const K*)s->bp[r] : nullptr;
   ua.m = (u32)n;
@@ -520,10 +530,113 @@ void destroy_all(flix_store* s) {
   dev_free(&s->ss.status);
   dev_free(&s->ss.status_cl);
   dev_free(&s->ss.tile_ctr);
+  dev_free(&s->d_status);
+  dev_free(&s->d_status_cl);
+  dev_free(&s->d_hist);
+  dev_free(&s->dctl);
   dev_free(&s->ss.err);
   for (auto e : s->tm.pool) (void)hipEventDestroy(e);
   s->tm.pool.clear();
 }
+
+// ---- persistent drain -------------------------------------------------------
+template <typename K, int RB, int GL, int KPL>
+int drain_launch_t(flix_store* s, const DrainBatch* d_batches, u32 nbatch,
+                   unsigned long long* d_ts, hipStream_t st) {
+  const u32 lds_items = upd_lds_items(s);
+  size_t shm = DrainSmemSize<K, RB, GL, KPL>::fixed();
+  size_t upd = (size_t)(256 / GL) * 2 * lds_items * sizeof(K);
+  if (upd > shm) shm = upd;
+  auto kfn = k_drain<K, RB, GL, KPL>;
+  if (s->drain_grid == 0 || s->drain_shm != shm) {
+    if (shm > 65536)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 256, shm));
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (per_cu < 1) return FLIX_EINVAL;
+    s->drain_grid = per_cu * cus;
+    s->drain_shm = shm;
+  }
+  DrainArgs<K> a;
+  a.batches = d_batches;
+  a.nbatch = nbatch;
+  a.mkba = (const K*)s->mkba;
+  a.nb = s->nb;
+  a.hdr = s->hdr;
+  a.nkeys = (K*)s->nkeys;
+  a.nvals = (K*)s->nvals;
+  a.bnodes = s->bnodes;
+  a.free_ids = s->free_ids;
+  a.cap = s->cap;
+  a.pool = s->pool;
+  a.ctl = s->ctl;
+  a.bk[0] = (K*)s->bk[0];
+  a.bk[1] = (K*)s->bk[1];
+  a.bp[0] = s->bp[0];
+  a.bp[1] = s->bp[1];
+  a.hist = s->d_hist;
+  a.status = s->d_status;
+  a.status_cl = s->d_status_cl;
+  a.status_words = s->d_status_words;
+  a.cluster_words = s->d_cluster_words;
+  a.work = s->work;
+  a.lds_items = lds_items;
+  a.chunk = upd_chunk(s);
+  a.dctl = s->dctl;
+  a.tstamp = d_ts;
+  hipLaunchKernelGGL(kfn, dim3(s->drain_grid), dim3(256), shm, st, a);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
+template <typename K, int RB>
+int drain_launch_rb(flix_store* s, const DrainBatch* b, u32 nb, unsigned long long* ts,
+                    hipStream_t st) {
+  const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
+  switch (s->gl * 100 + kpl) {
+    case 1601: return drain_launch_t<K, RB, 16, 1>(s, b, nb, ts, st);
+    case 1602: return drain_launch_t<K, RB, 16, 2>(s, b, nb, ts, st);
+    case 1604: return drain_launch_t<K, RB, 16, 4>(s, b, nb, ts, st);
+    case 1608: return drain_launch_t<K, RB, 16, 8>(s, b, nb, ts, st);
+    case 1616: return drain_launch_t<K, RB, 16, 16>(s, b, nb, ts, st);
+    case 3201: return drain_launch_t<K, RB, 32, 1>(s, b, nb, ts, st);
+    case 3202: return drain_launch_t<K, RB, 32, 2>(s, b, nb, ts, st);
+    case 3204: return drain_launch_t<K, RB, 32, 4>(s, b, nb, ts, st);
+    case 3208: return drain_launch_t<K, RB, 32, 8>(s, b, nb, ts, st);
+    case 6401: return drain_launch_t<K, RB, 64, 1>(s, b, nb, ts, st);
+    case 6402: return drain_launch_t<K, RB, 64, 2>(s, b, nb, ts, st);
+    default: return drain_launch_t<K, RB, 64, 4>(s, b, nb, ts, st);
+  }
+}
+
+int drain_launch(flix_store* s, const DrainBatch* b, u32 nb, unsigned long long* ts,
+                 hipStream_t st) {
+  if (s->kb == 32)
+    return s->rb == 4 ? drain_launch_rb<u32, 4>(s, b, nb, ts, st)
+                      : drain_launch_rb<u32, 8>(s, b, nb, ts, st);
+  return s->rb == 4 ? drain_launch_rb<u64, 4>(s, b, nb, ts, st)
+                    : drain_launch_rb<u64, 8>(s, b, nb, ts, st);
+}
+
+int drain_validate(flix_store* s, const flix_batch* h, u32 nbatch) {
+  for (u32 i = 0; i < nbatch; ++i) {
+    const flix_batch& b = h[i];
+    if (b.op > FLIX_OP_DELETE) return FLIX_EINVAL;
+    if (b.n == 0) continue;
+    if (b.n > s->max_batch || !b.d_keys) return FLIX_EINVAL;
+    if ((b.op == FLIX_OP_INSERT || b.op == FLIX_OP_RANGE) && !b.d_aux) return FLIX_EINVAL;
+    if (b.op <= FLIX_OP_SUCCESSOR && !b.d_vals_out) return FLIX_EINVAL;
+    if (b.op == FLIX_OP_SUCCESSOR && !b.d_keys_out) return FLIX_EINVAL;
+    if (b.op == FLIX_OP_RANGE && !b.d_counts) return FLIX_EINVAL;
+  }
+  return FLIX_OK;
+}
+
+static_assert(sizeof(flix_batch) == sizeof(DrainBatch), "descriptor layouts must match");
 
 }  // namespace
 
@@ -585,6 +698,23 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
     destroy_all(s);
     delete s;
     return rc;
+  }
+  s->d_status_words = sort_status_words(mb, 8);
+  s->d_cluster_words = sort_cluster_words(mb);
+  if ((rc = dev_alloc(&s->d_status, s->d_status_words * 8)) ||
+      (rc = dev_alloc(&s->d_status_cl, s->d_cluster_words * 8)) ||
+      (rc = dev_alloc(&s->d_hist, 2 * 2048 * sizeof(u32))) ||
+      (rc = dev_alloc(&s->dctl, sizeof(DrainCtl)))) {
+    destroy_all(s);
+    delete s;
+    return rc;
+  }
+  if (hipMemset(s->d_status, 0, s->d_status_words * 8) != hipSuccess ||
+      hipMemset(s->d_status_cl, 0, s->d_cluster_words * 8) != hipSuccess ||
+      hipMemset(s->dctl, 0, sizeof(DrainCtl)) != hipSuccess) {
+    destroy_all(s);
+    delete s;
+    return FLIX_EHIP;
   }
   rc = s->kb == 32 ? bulk_load_t<u32>(s, nullptr, nullptr, 0, S(stream))
                    : bulk_load_t<u64>(s, nullptr, nullptr, 0, S(stream));
@@ -681,7 +811,11 @@ int flix_status(flix_store* s, void* stream) {
   HIP_TRY(hipMemsetAsync(&s->ctl->status, 0, sizeof(u32), S(stream)));
   HIP_TRY(hipMemsetAsync(s->ss.err, 0, sizeof(u32), S(stream)));
   HIP_TRY(hipStreamSynchronize(S(stream)));
-  if (v == 0 && se != 0) return FLIX_EINTERNAL;
+  u32 de = 0;
+  HIP_TRY(hipMemcpyAsync(&de, &s->dctl->err, sizeof(u32), hipMemcpyDeviceToHost, S(stream)));
+  HIP_TRY(hipMemsetAsync(&s->dctl->err, 0, sizeof(u32), S(stream)));
+  HIP_TRY(hipStreamSynchronize(S(stream)));
+  if (v == 0 && (se != 0 || de != 0)) return FLIX_EINTERNAL;
   return (int)v;
 }
 
@@ -815,6 +949,74 @@ int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_
 }
 
 const char* flix_last_error(void) { return g_last_error; }
+
+int flix_drain(flix_store* s, const flix_batch* h_batches, const flix_batch* d_batches,
+               uint32_t nbatch, uint64_t* d_timestamps, void* stream) {
+  if (!s) return FLIX_ESTATE;
+  (void)hipGetLastError();
+  if (nbatch == 0) return FLIX_OK;
+  if (!h_batches || !d_batches) return FLIX_EINVAL;
+  int rc = drain_validate(s, h_batches, nbatch);
+  if (rc) return rc;
+  return drain_launch(s, reinterpret_cast<const DrainBatch*>(d_batches), nbatch,
+                      reinterpret_cast<unsigned long long*>(d_timestamps), S(stream));
+}
+
+int flix_drain_graph(flix_store* s, const flix_batch* h_batches, const flix_batch* d_batches,
+                     uint32_t nbatch, uint64_t* d_timestamps, void** graph_exec, void* stream) {
+  if (!s) return FLIX_ESTATE;
+  if (!graph_exec || !stream) return FLIX_EINVAL;
+  (void)hipGetLastError();
+  *graph_exec = nullptr;
+  int rc = drain_validate(s, h_batches, nbatch);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  // size the grid outside the capture (occupancy queries are not captured)
+  if (s->drain_grid == 0) {
+    rc = drain_launch(s, reinterpret_cast<const DrainBatch*>(d_batches), 0, nullptr, st);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  rc = drain_launch(s, reinterpret_cast<const DrainBatch*>(d_batches), nbatch,
+                    reinterpret_cast<unsigned long long*>(d_timestamps), st);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(st, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return note_hip_error(e, "hipStreamEndCapture", __LINE__);
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return note_hip_error(e, "hipGraphInstantiate", __LINE__);
+  *graph_exec = ex;
+  return FLIX_OK;
+}
+
+int flix_graph_launch(void* graph_exec, void* stream) {
+  if (!graph_exec) return FLIX_EINVAL;
+  HIP_TRY(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(graph_exec), S(stream)));
+  return FLIX_OK;
+}
+
+int flix_graph_destroy(void* graph_exec) {
+  if (!graph_exec) return FLIX_EINVAL;
+  HIP_TRY(hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(graph_exec)));
+  return FLIX_OK;
+}
+
+int flix_drain_info(flix_store* s, uint32_t* grid_blocks, uint64_t* timestamp_hz) {
+  if (!s) return FLIX_ESTATE;
+  if (grid_blocks) *grid_blocks = (uint32_t)s->drain_grid;
+  if (timestamp_hz) {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    *timestamp_hz = (uint64_t)khz * 1000ull;
+  }
+  return FLIX_OK;
+}
 
 int flix_set_timing(flix_store* s, int enable) {
   if (!s) return FLIX_ESTATE;

@@ -1,0 +1,296 @@
+// Persistent fused drain: one co-resident grid executes a whole queue of
+// mixed-type batches (lookup, successor, range, insert, delete) in order.
+// Every batch runs the same phases as the per-batch launches (histogram,
+// onesweep passes, then the read kernel or slices + update kernel), with a
+// grid barrier between phases instead of a kernel boundary.  The queue lives
+// in device memory, so one launch (or one hipGraph replay) drains it, and the
+// batches can change between replays.
+//
+// Ordering and memory: a grid barrier is arrive (agent-scope release +
+// atomic) / wait (generation word) / agent-scope acquire.  Tiles of a pass are
+// walked in increasing order by every workgroup, so a tile only waits on
+// tiles that are resident or finished.  Look-back words carry an epoch from
+// a device counter that every drain advances, so nothing is cleared between
+// passes, drains or graph replays.
+#pragma once
+
+#include "flix_device.hpp"
+#include "flix_read2.hpp"
+#include "flix_sort.hpp"
+#include "flix_update.hpp"
+
+namespace flix {
+
+constexpr u32 kOpInsert = 3;
+constexpr u32 kOpDelete = 4;
+
+struct alignas(16) DrainBatch {
+  u32 op;
+  u32 n;
+  u32 maxpq;
+  u32 reserved;
+  const void* keys;   // keys (range: lo)
+  const void* aux;    // insert: values; range: hi
+  void* out_v;
+  void* out_k;
+  u32* counts;
+  void* reserved2;
+};
+
+struct DrainCtl {
+  u32 bar_count;     // arrivals at the current grid barrier
+  u32 bar_gen;       // barrier generation
+  u32 epoch;         // last look-back epoch used by a drain
+  u32 err;           // sticky: 1 barrier wait gave up, 2 look-back gave up
+  u32 pad[12];
+};
+
+template <typename K>
+struct DrainArgs {
+  const DrainBatch* batches;
+  u32 nbatch;
+  // store
+  const K* mkba;
+  u32 nb;
+  NodeHdr* hdr;
+  K* nkeys;
+  K* nvals;
+  u32* bnodes;
+  u32* free_ids;
+  u32 cap;
+  u32 pool;
+  Ctl* ctl;
+  // scratch
+  K* bk[2];
+  void* bp[2];
+  u32* hist;          // [2][P*R]
+  u64* status;
+  u64* status_cl;
+  u64 status_words;
+  u64 cluster_words;
+  WorkItem* work;
+  u32 lds_items;
+  u32 chunk;
+  DrainCtl* dctl;
+  unsigned long long* tstamp;   // [nbatch + 1]: start, then one per batch (may be null)
+};
+
+// Grid-wide barrier for a co-resident grid.  Bounded: a workgroup that waits
+// too long records an error and continues, so the kernel always ends.
+__device__ __forceinline__ void grid_sync(DrainCtl* c, u32 nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const u32 gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);   // this workgroup's writes before arriving
+    const u32 arrived = atomicAdd(&c->bar_count, 1u) + 1u;
+    if (arrived == nblocks) {
+      __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      u32 polls = 0;
+      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (++polls > (1u << 24)) {
+          atomicOr(&c->err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  }
+  __syncthreads();
+}
+
+template <typename K, int RB, int GL, int KPL>
+struct DrainSmemSize {
+  static constexpr int U = KPL >= 16 ? 2 : 4;
+  static constexpr size_t hist = sizeof(HistSmem<K, RB>);
+  static constexpr size_t pass_idx = sizeof(OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayIndex>);
+  static constexpr size_t pass_val = sizeof(OnesweepSmem<K, K, RB, kSortNT, kSortIPT, kPayValue>);
+  static constexpr size_t pass_none = sizeof(OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayNone>);
+  static constexpr size_t read = sizeof(ReadSmem<K, 512, 256>);
+  static constexpr size_t slices = sizeof(SliceSmem<K, (sizeof(K) == 4 ? 1024 : 512), 256>);
+  static constexpr size_t fixed() {
+    size_t m = hist;
+    m = m > pass_idx ? m : pass_idx;
+    m = m > pass_val ? m : pass_val;
+    m = m > pass_none ? m : pass_none;
+    m = m > read ? m : read;
+    m = m > slices ? m : slices;
+    return m;
+  }
+};
+
+template <typename K, int RB, int GL, int KPL>
+__global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
+  extern __shared__ unsigned char smem[];
+  __shared__ unsigned long long s_counter;
+  __shared__ u32 s_epoch;
+  constexpr int R = RadixShape<K, RB>::R;
+  constexpr int P = RadixShape<K, RB>::P;
+  constexpr int U = KPL >= 16 ? 2 : 4;
+  constexpr int SR = 512;                       // read share
+  constexpr int SS = sizeof(K) == 4 ? 1024 : 512;  // slice share
+  const u32 G = gridDim.x;
+  const u32 blk = blockIdx.x;
+  DrainCtl* dc = a.dctl;
+
+  // Epochs: every workgroup reads the base before anyone advances it (the
+  // advance happens after the final barrier).  Near wrap-around the status
+  // words are cleared first.
+  if (threadIdx.x == 0) s_epoch = __hip_atomic_load(&dc->epoch, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  u32 epoch = s_epoch;
+  const u32 need_epochs = a.nbatch * (u32)P + 1u;
+  if (epoch + need_epochs >= (1u << 30) - 1u) {
+    for (u64 i = (u64)blk * 256 + threadIdx.x; i < a.status_words; i += (u64)G * 256) a.status[i] = 0;
+    for (u64 i = (u64)blk * 256 + threadIdx.x; i < a.cluster_words; i += (u64)G * 256)
+      a.status_cl[i] = 0;
+    epoch = 0;
+  }
+  // both histogram slots start at zero
+  if (blk == 0)
+    for (int i = threadIdx.x; i < 2 * P * R; i += 256) a.hist[i] = 0;
+  if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[0] = wall_clock64();
+  grid_sync(dc, G);
+
+  for (u32 bi = 0; bi < a.nbatch; ++bi) {
+    const DrainBatch d = a.batches[bi];
+    const u32 n = d.n;
+    if (n == 0) {
+      if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[bi + 1] = wall_clock64();
+      continue;
+    }
+    const bool is_update = d.op >= kOpInsert;
+    u32* hist = a.hist + (bi & 1u) * (P * R);
+    if (is_update && blk == 0 && threadIdx.x == 0) {
+      a.ctl->need = 0;
+      a.ctl->call_err = 0;
+      a.ctl->heavy_count = 0;
+    }
+    // ---- histogram
+    radix_hist_part<K, RB>((const K*)d.keys, n, hist, blk, G,
+                           *reinterpret_cast<HistSmem<K, RB>*>(smem));
+    grid_sync(dc, G);
+    // ---- onesweep passes
+    const u32 ntiles = (n + kSortTile - 1) / kSortTile;
+    for (int p = 0; p < P; ++p) {
+      ++epoch;
+      const K* ki = (p == 0) ? (const K*)d.keys : a.bk[(p & 1) ? 0 : 1];
+      K* ko = a.bk[(p & 1) ? 1 : 0];
+      if (d.op == kOpInsert) {
+        PassArgs<K, K> pa;
+        pa.kin = ki;
+        pa.vin = (p == 0) ? (const K*)d.aux : (const K*)a.bp[(p & 1) ? 0 : 1];
+        pa.kout = ko;
+        pa.vout = (K*)a.bp[(p & 1) ? 1 : 0];
+        pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
+        pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
+        for (u32 t = blk; t < ntiles; t += G)
+          onesweep_tile<K, K, RB, kSortNT, kSortIPT, kPayValue>(
+              pa, t, *reinterpret_cast<OnesweepSmem<K, K, RB, kSortNT, kSortIPT, kPayValue>*>(smem));
+      } else if (d.op == kOpDelete) {
+        PassArgs<K, u32> pa;
+        pa.kin = ki; pa.vin = nullptr; pa.kout = ko; pa.vout = nullptr;
+        pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
+        pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
+        for (u32 t = blk; t < ntiles; t += G)
+          onesweep_tile<K, u32, RB, kSortNT, kSortIPT, kPayNone>(
+              pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayNone>*>(smem));
+      } else {
+        PassArgs<K, u32> pa;
+        pa.kin = ki;
+        pa.vin = (p == 0) ? nullptr : (const u32*)a.bp[(p & 1) ? 0 : 1];
+        pa.kout = ko;
+        pa.vout = (u32*)a.bp[(p & 1) ? 1 : 0];
+        pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
+        pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
+        for (u32 t = blk; t < ntiles; t += G)
+          onesweep_tile<K, u32, RB, kSortNT, kSortIPT, kPayIndex>(
+              pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayIndex>*>(smem));
+      }
+      grid_sync(dc, G);
+    }
+    const int r = ((P - 1) & 1) ? 1 : 0;
+    // the other histogram slot was last used by batch bi-1 and is next used by
+    // batch bi+1, after at least one more barrier
+    if (blk == 0)
+      for (int i = threadIdx.x; i < P * R; i += 256) a.hist[((bi + 1u) & 1u) * (P * R) + i] = 0;
+    // ---- apply
+    if (!is_update) {
+      ReadArgs<K> ra;
+      ra.skeys = a.bk[r];
+      ra.sidx = (const u32*)a.bp[r];
+      ra.m = n;
+      ra.mkba = a.mkba;
+      ra.nb = a.nb;
+      ra.hdr = a.hdr;
+      ra.nkeys = a.nkeys;
+      ra.nvals = a.nvals;
+      ra.cap = a.cap;
+      ra.share = SR;
+      ra.out_v = (K*)d.out_v;
+      ra.out_k = (K*)d.out_k;
+      ra.hi = (const K*)d.aux;
+      ra.counts = d.counts;
+      ra.maxpq = d.maxpq;
+      const u32 nshares = (u32)(((u64)n + a.nb + SR - 1) / SR);
+      for (u32 vb = blk; vb < nshares; vb += G) {
+        read_share<K, 256, SR, GL, KPL, U>(ra, (int)d.op, vb,
+                                          *reinterpret_cast<ReadSmem<K, SR, 256>*>(smem));
+        __syncthreads();
+      }
+    } else {
+      SliceArgs<K> sa;
+      sa.skeys = a.bk[r];
+      sa.svals = d.op == kOpInsert ? (const K*)a.bp[r] : nullptr;
+      sa.m = n;
+      sa.mkba = a.mkba;
+      sa.nb = a.nb;
+      sa.hdr = a.hdr;
+      sa.bnodes = a.bnodes;
+      sa.cap = a.cap;
+      sa.share = SS;
+      sa.work = a.work;
+      sa.ctl = a.ctl;
+      const u32 nshares = (u32)(((u64)n + a.nb + SS - 1) / SS);
+      for (u32 vb = blk; vb < nshares; vb += G) {
+        if (d.op == kOpInsert)
+          slices_share<K, 256, SS, true>(sa, vb, *reinterpret_cast<SliceSmem<K, SS, 256>*>(smem));
+        else
+          slices_share<K, 256, SS, false>(sa, vb, *reinterpret_cast<SliceSmem<K, SS, 256>*>(smem));
+      }
+      grid_sync(dc, G);
+      UpdArgs<K> ua;
+      ua.mkba = a.mkba;
+      ua.skeys = a.bk[r];
+      ua.svals = d.op == kOpInsert ? (const K*)a.bp[r] : nullptr;
+      ua.m = n;
+      ua.hdr = a.hdr;
+      ua.nkeys = a.nkeys;
+      ua.nvals = a.nvals;
+      ua.bnodes = a.bnodes;
+      ua.free_ids = a.free_ids;
+      ua.cap = a.cap;
+      ua.chunk = a.chunk;
+      ua.pool = a.pool;
+      ua.work = a.work;
+      ua.ctl = a.ctl;
+      ua.status = &a.ctl->status;
+      if (threadIdx.x == 0) s_counter = 0;
+      __syncthreads();
+      if (d.op == kOpInsert)
+        insert_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_counter);
+      else
+        delete_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_counter);
+    }
+    grid_sync(dc, G);
+    if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[bi + 1] = wall_clock64();
+  }
+  // every workgroup has read the epoch base long ago (first barrier)
+  if (blk == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&dc->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace flix

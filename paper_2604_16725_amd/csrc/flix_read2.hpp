@@ -82,27 +82,48 @@ struct alignas(sizeof(K) * KPL >= 16 ? 16 : sizeof(K) * KPL) KeyVec {
   K k[KPL];
 };
 
+template <typename K, int S, int NT>
+struct ReadSmem {
+  K q[S];
+  K hi[S];
+  u32 idx[S];
+  u32 pos[S];       // (local bucket << 16) | position / code
+  u32 cnt[S];       // range: results inside the node
+  K mk[S];
+  u32 e[S + 1];
+  u32 hsz[S + 1];
+  u32 hnx[S + 1];
+  unsigned short tl[S + 1];
+  u32 tmp[NT / 64 + 1];
+  u32 lo[2], hiw[2], wc[4], cut[2], ntouch;
+};
+
+// One share (workgroup-sized unit) of a read batch; `vb` is the share index.
 template <typename K, int NT, int S, int GL, int KPL, int U>
-__global__ __launch_bounds__(NT) void k_read_apply2(ReadArgs<K> a, int op) {
+__device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, NT>& sm) {
   static_assert(NT == 256, "merge-path search assumes 256 threads");
   constexpr int NG = NT / GL;
-  __shared__ K s_q[S];
-  __shared__ K s_hi[S];
-  __shared__ u32 s_idx[S];
-  __shared__ u32 s_pos[S];       // (local bucket << 16) | position / code
-  __shared__ u32 s_cnt[S];       // range: results inside the node
-  __shared__ K s_mk[S];
-  __shared__ u32 s_e[S + 1];
-  __shared__ u32 s_hsz[S + 1];
-  __shared__ u32 s_hnx[S + 1];
-  __shared__ unsigned short s_tl[S + 1];
-  __shared__ u32 s_tmp[NT / 64 + 1];
-  __shared__ u32 s_lo[2], s_hiw[2], s_wc[4], s_cut[2], s_ntouch;
+  K* s_q = sm.q;
+  K* s_hi = sm.hi;
+  u32* s_idx = sm.idx;
+  u32* s_pos = sm.pos;
+  u32* s_cnt = sm.cnt;
+  K* s_mk = sm.mk;
+  u32* s_e = sm.e;
+  u32* s_hsz = sm.hsz;
+  u32* s_hnx = sm.hnx;
+  unsigned short* s_tl = sm.tl;
+  u32* s_tmp = sm.tmp;
+  u32* s_lo = sm.lo;
+  u32* s_hiw = sm.hiw;
+  u32* s_wc = sm.wc;
+  u32* s_cut = sm.cut;
+  u32& s_ntouch = sm.ntouch;
 
   const u32 tid = threadIdx.x;
   const u64 total = (u64)a.m + a.nb;
   u64 d[2];
-  d[0] = (u64)blockIdx.x * a.share;
+  d[0] = (u64)vb * a.share;
   d[1] = d[0] + a.share < total ? d[0] + a.share : total;
   coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
   const u32 q0 = s_cut[0], q1 = s_cut[1];
@@ -319,6 +340,12 @@ __global__ __launch_bounds__(NT) void k_read_apply2(ReadArgs<K> a, int op) {
       a.counts[orig] = cnt;
     }
   }
+}
+
+template <typename K, int NT, int S, int GL, int KPL, int U>
+__global__ __launch_bounds__(NT) void k_read_apply2(ReadArgs<K> a, int op) {
+  __shared__ ReadSmem<K, S, NT> sm;
+  read_share<K, NT, S, GL, KPL, U>(a, op, blockIdx.x, sm);
 }
 
 }  // namespace flix

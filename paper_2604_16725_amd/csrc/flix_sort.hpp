@@ -42,20 +42,20 @@ __device__ __forceinline__ u32 digit_of(K k, u32 shift) {
 // Digit histograms of all passes in one read of the keys.  Block 0 also
 // clears `hist_next`, the histogram slot the next sort call will use.
 template <typename K, int RB>
-__global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, u32 n,
-                                                    u32* __restrict__ hist,
-                                                    u32* __restrict__ hist_next,
-                                                    u32* __restrict__ tile_ctr) {
+struct HistSmem {
+  u32 sh[RadixShape<K, RB>::P * RadixShape<K, RB>::R];
+};
+
+// Histogram part `part` of `nparts` (grid-stride over the keys).
+template <typename K, int RB>
+__device__ void radix_hist_part(const K* __restrict__ keys, u32 n, u32* __restrict__ hist,
+                                u32 part, u32 nparts, HistSmem<K, RB>& sm) {
   constexpr int R = RadixShape<K, RB>::R;
   constexpr int P = RadixShape<K, RB>::P;
-  __shared__ u32 sh[P * R];
+  u32* sh = sm.sh;
   for (int i = threadIdx.x; i < P * R; i += 256) sh[i] = 0;
-  if (blockIdx.x == 0 && hist_next != nullptr)
-    for (int i = threadIdx.x; i < P * R; i += 256) hist_next[i] = 0;
-  // per-pass tile tickets start at 0 (the passes run after this kernel)
-  if (blockIdx.x == 0 && threadIdx.x < (u32)P) tile_ctr[threadIdx.x] = 0;
   __syncthreads();
-  for (u32 i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+  for (u32 i = part * 256u + threadIdx.x; i < n; i += nparts * 256u) {
     K k = keys[i];
 #pragma unroll
     for (int p = 0; p < P; ++p) atomicAdd(&sh[p * R + digit_of<K, RB>(k, p * RB)], 1u);
@@ -63,6 +63,21 @@ __global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, 
   __syncthreads();
   for (int i = threadIdx.x; i < P * R; i += 256)
     if (sh[i]) atomicAdd(&hist[i], sh[i]);
+  __syncthreads();
+}
+
+template <typename K, int RB>
+__global__ __launch_bounds__(256) void k_radix_hist(const K* __restrict__ keys, u32 n,
+                                                    u32* __restrict__ hist,
+                                                    u32* __restrict__ hist_next,
+                                                    u32* __restrict__ tile_ctr) {
+  constexpr int R = RadixShape<K, RB>::R;
+  constexpr int P = RadixShape<K, RB>::P;
+  __shared__ HistSmem<K, RB> sm;
+  if (blockIdx.x == 0 && hist_next != nullptr)
+    for (int i = threadIdx.x; i < P * R; i += 256) hist_next[i] = 0;
+  (void)tile_ctr;
+  radix_hist_part<K, RB>(keys, n, hist, blockIdx.x, gridDim.x, sm);
 }
 
 constexpr u32 kSortCluster = 16;   // tiles per look-back cluster
@@ -74,40 +89,66 @@ constexpr int kPayIndex = 1;   // payload is u32; vin == nullptr means "input in
 constexpr int kPayValue = 2;   // payload read from vin
 
 template <typename K, typename V, int RB, int NT, int IPT, int PAY>
-__global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
-                                                 const V* __restrict__ vin,
-                                                 K* __restrict__ kout, V* __restrict__ vout,
-                                                 u32 n, u32 shift,
-                                                 const u32* __restrict__ hist_p,
-                                                 u64* status, u64* status_cl, u32* tile_ctr,
-                                                 u32 ntiles, u32 epoch, u32* err) {
+struct OnesweepSmem {
+  K k[NT * IPT];
+  V v[PAY == kPayNone ? 1 : NT * IPT];
+  u32 wc[NT / 64][1 << RB];
+  u32 lstart[1 << RB];
+  u32 gbase[1 << RB];
+  u32 tmp[NT / 64 + 1];
+  u32 trivial;
+};
+
+template <typename K, typename V>
+struct PassArgs {
+  const K* kin;
+  const V* vin;
+  K* kout;
+  V* vout;
+  u32 n;
+  u32 shift;
+  const u32* hist_p;
+  u64* status;
+  u64* status_cl;
+  u32 epoch;
+  u32* err;
+};
+
+// One tile of one onesweep pass.  Tiles must be processed so that every tile
+// a tile waits on is resident or finished: in a plain launch tile = workgroup
+// id (workgroups are dispatched in id order); in a persistent grid every
+// workgroup walks its tiles in increasing order.
+template <typename K, typename V, int RB, int NT, int IPT, int PAY>
+__device__ void onesweep_tile(const PassArgs<K, V>& pa, u32 tile,
+                              OnesweepSmem<K, V, RB, NT, IPT, PAY>& sm) {
   constexpr int R = 1 << RB;
   constexpr int WAVES = NT / 64;
   constexpr int TILE = NT * IPT;
   static_assert(R <= NT, "one look-back thread per digit");
-
-  __shared__ K s_k[TILE];
-  __shared__ V s_v[PAY == kPayNone ? 1 : TILE];
-  __shared__ u32 s_wc[WAVES][R];
-  __shared__ u32 s_lstart[R];
-  __shared__ u32 s_gbase[R];
-  __shared__ u32 s_tmp[NT / 64 + 1];
-  __shared__ u32 s_tile;
-  __shared__ u32 s_trivial;
+  const K* __restrict__ kin = pa.kin;
+  const V* __restrict__ vin = pa.vin;
+  K* __restrict__ kout = pa.kout;
+  V* __restrict__ vout = pa.vout;
+  const u32 n = pa.n, shift = pa.shift, epoch = pa.epoch;
+  const u32* __restrict__ hist_p = pa.hist_p;
+  u64* status = pa.status;
+  u64* status_cl = pa.status_cl;
+  u32* err = pa.err;
+  K* s_k = sm.k;
+  V* s_v = sm.v;
+  auto& s_wc = sm.wc;
+  u32* s_lstart = sm.lstart;
+  u32* s_gbase = sm.gbase;
+  u32* s_tmp = sm.tmp;
+  u32& s_trivial = sm.trivial;
 
   const u32 tid = threadIdx.x;
   const u32 lane = tid & 63;
   const u32 w = tid >> 6;
 
-  // Tiles are numbered by workgroup id: workgroups are dispatched in id order,
-  // so every predecessor a tile waits on is resident or finished.  (A shared
-  // ticket counter would serialise 512+ same-address atomics per pass.)
   if (tid == 0) s_trivial = 0;
   for (int i = tid; i < WAVES * R; i += NT) (&s_wc[0][0])[i] = 0;
   __syncthreads();
-  const u32 tile = blockIdx.x;
-  (void)tile_ctr;
-  (void)s_tile;
   const u32 tile0 = tile * (u32)TILE;
 
   // Load items (wave-striped) and this pass's digit counts in one round.
@@ -142,6 +183,7 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
         if (PAY != kPayNone) vout[idx] = pay[k];
       }
     }
+    __syncthreads();
     return;
   }
 
@@ -286,6 +328,13 @@ __global__ __launch_bounds__(NT) void k_onesweep(const K* __restrict__ kin,
       if (PAY != kPayNone) vout[g] = s_v[i];
     }
   }
+  __syncthreads();
+}
+
+template <typename K, typename V, int RB, int NT, int IPT, int PAY>
+__global__ __launch_bounds__(NT) void k_onesweep(PassArgs<K, V> pa) {
+  __shared__ OnesweepSmem<K, V, RB, NT, IPT, PAY> sm;
+  onesweep_tile<K, V, RB, NT, IPT, PAY>(pa, blockIdx.x, sm);
 }
 
 // Scratch shared by every sort call of one store.
@@ -367,11 +416,21 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     const V* vi = (p == 0) ? vin : ((p & 1) ? v0 : v1);
     K* ko = (p & 1) ? k1 : k0;
     V* vo = (p & 1) ? v1 : v0;
+    PassArgs<K, V> pa;
+    pa.kin = ki;
+    pa.vin = vi;
+    pa.kout = ko;
+    pa.vout = vo;
+    pa.n = n;
+    pa.shift = (u32)(p * RB);
+    pa.hist_p = hist + p * R;
+    pa.status = s.status;
+    pa.status_cl = s.status_cl;
+    pa.epoch = epoch;
+    pa.err = s.err;
     SortTimer t(s, st);
     hipLaunchKernelGGL((k_onesweep<K, V, RB, kSortNT, kSortIPT, PAY>), dim3(ntiles),
-                       dim3(kSortNT), 0, st, ki, vi, ko, vo, n, (u32)(p * RB),
-                       hist + p * R, s.status, s.status_cl, s.tile_ctr + p, ntiles, epoch,
-                       s.err);
+                       dim3(kSortNT), 0, st, pa);
     t.end(1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

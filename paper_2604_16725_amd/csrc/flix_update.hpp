@@ -25,10 +25,12 @@ constexpr u32 kErrInval = 0xFFFFFFFFu;   // -1
 constexpr u32 kErrNomem = 0xFFFFFFFEu;   // -2
 constexpr u32 kErrInternal = 0xFFFFFFFBu;  // -5: internal consistency check failed
 
-// Work item: bucket and its slice [s, e) of the sorted batch.
+// Work item: bucket and its slice [s, e) of the sorted batch, plus the head
+// node's size with kSingleNode set when the bucket is that one node.
 struct alignas(16) WorkItem {
-  u32 b, s, e, pad;
+  u32 b, s, e, head;
 };
+constexpr u32 kSingleNode = 0x80000000u;
 
 template <typename K>
 struct SliceArgs {
@@ -45,24 +47,38 @@ struct SliceArgs {
   Ctl* ctl;
 };
 
+template <typename K, int S, int NT>
+struct SliceSmem {
+  K q[S + 1];
+  K mk[S];
+  u32 e[S + 1];
+  u32 live[S + 1];   // exclusive prefix of live flags
+  u32 tmp[NT / 64 + 1];
+  u32 part[4];
+  u32 wbase;
+  unsigned long long need;
+  u32 bad;
+  u32 gstart;
+};
+
 template <typename K, int NT, int S, bool INSERT>
-__global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
-  __shared__ K s_q[S + 1];
-  __shared__ K s_mk[S];
-  __shared__ u32 s_e[S + 1];
-  __shared__ u32 s_live[S + 1];   // exclusive prefix of live flags
-  __shared__ u32 s_tmp[NT / 64 + 1];
-  __shared__ u32 s_part[4];
-  __shared__ u32 s_wbase;
-  __shared__ unsigned long long s_need;
-  __shared__ u32 s_bad;
-  __shared__ u32 s_gstart;
+__device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>& sm) {
+  K* s_q = sm.q;
+  K* s_mk = sm.mk;
+  u32* s_e = sm.e;
+  u32* s_live = sm.live;
+  u32* s_tmp = sm.tmp;
+  u32* s_part = sm.part;
+  u32& s_wbase = sm.wbase;
+  unsigned long long& s_need = sm.need;
+  u32& s_bad = sm.bad;
+  u32& s_gstart = sm.gstart;
 
   const u32 tid = threadIdx.x;
   const u64 total = (u64)a.m + a.nb;
-  const u64 d0 = (u64)blockIdx.x * a.share;
+  const u64 d0 = (u64)vb * a.share;
   const u64 d1 = d0 + a.share < total ? d0 + a.share : total;
-  if (blockIdx.x == 0 && tid == 0) a.ctl->free_snapshot = a.ctl->free_top;
+  if (vb == 0 && tid == 0) a.ctl->free_snapshot = a.ctl->free_top;
   if (tid == 0) {
     u32 q0 = merge_path_keys(a.skeys, a.m, a.mkba, a.nb, d0);
     s_part[0] = q0;
@@ -81,7 +97,10 @@ __global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
   const u32 nbl = b1 - b0;
   // A bucket is emitted by the share that holds its maxBucket entry, with its
   // whole slice; only local bucket 0 can have keys in earlier shares.
-  if (nbl == 0) return;
+  if (nbl == 0) {
+    __syncthreads();
+    return;
+  }
   if (tid == 0) {
     s_gstart = (b0 == 0) ? 0u : upper_bound_idx<K>(a.skeys, 0u, q0, a.mkba[b0 - 1]);
   }
@@ -132,27 +151,31 @@ __global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
   constexpr u32 PERB = (S + NT - 1) / NT;
   u32 cnt = 0;
   unsigned long long need = 0;
+  u32 info[PERB];   // head size | kSingleNode, passed to the apply kernel
 #pragma unroll
   for (u32 r = 0; r < PERB; ++r) {
     u32 lb = tid * PERB + r;
+    info[r] = 0;
     if (lb < nbl) {
       u32 s = lb ? q0 + s_e[lb - 1] : gstart;
       u32 e = q0 + s_e[lb];
       if (e > s) {
         ++cnt;
+        const u32 b = b0 + lb;
+        const NodeHdr h = a.hdr[b];
+        const bool single = h.next == kNil;
+        info[r] = h.size | (single ? kSingleNode : 0u);
         if (INSERT) {
           // live keys inside this share, plus (bucket 0 only) every key before
           // q0 counted as live: an upper bound is all the budget needs
           u32 sl = lb ? s_e[lb - 1] : 0u;
           u32 t = s_live[e - q0] - s_live[sl] + (lb ? 0u : q0 - gstart);
-          u32 b = b0 + lb;
-          u32 bn = a.bnodes[b];
           u32 f = a.cap / 2;
-          if (bn == 1) {
-            u32 sa = a.hdr[b].size;
-            u64 c = (u64)sa + t;
+          if (single) {
+            u64 c = (u64)h.size + t;
             if (c > a.cap) need += c / f - 1;
           } else {
+            u32 bn = a.bnodes[b];
             need += (u64)(bn < t ? bn : t) + t / f;
           }
         }
@@ -176,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
         it.b = b0 + lb;
         it.s = s;
         it.e = e;
-        it.pad = 0;
+        it.head = info[r];
         a.work[w++] = it;
       }
     }
@@ -185,6 +208,13 @@ __global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
     if (s_need) atomicAdd((unsigned long long*)&a.ctl->need, s_need);
     if (s_bad) atomicExch(&a.ctl->call_err, kErrInval);
   }
+  __syncthreads();
+}
+
+template <typename K, int NT, int S, bool INSERT>
+__global__ __launch_bounds__(NT) void k_slices(SliceArgs<K> a) {
+  __shared__ SliceSmem<K, S, NT> sm;
+  slices_share<K, NT, S, INSERT>(a, blockIdx.x, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -265,6 +295,7 @@ __device__ __forceinline__ void stage_items(K* dk, K* dv, const K* sk, const K* 
 
 template <typename K>
 struct UpdArgs {
+  const K* mkba;
   const K* skeys;
   const K* svals;
   u32 m;
@@ -280,6 +311,16 @@ struct UpdArgs {
   Ctl* ctl;
   u32* status;        // sticky status word (== &ctl->status)
 };
+
+// Header write that leaves the fence alone when the caller never loaded it.
+__device__ __forceinline__ void write_hdr(NodeHdr* p, const NodeHdr& h, bool with_fence) {
+  if (with_fence) {
+    *p = h;
+  } else {
+    p->size = h.size;
+    p->next = h.next;
+  }
+}
 
 // Position of merged item `pos` among k pieces of c items: piece p covers
 // [floor(p*c/k), floor((p+1)*c/k)).
@@ -303,11 +344,12 @@ __device__ __forceinline__ u32 piece_of(u32 pos, u32 c, u32 k) {
 // the free list and are linked after X; every piece but the last is fenced by
 // its last key and the last one keeps X's fence and link.
 // ---------------------------------------------------------------------------
+// Insert work of workgroup `blk` of `nblk` (groups stride over the work list).
+// `s_dyn`: per-group LDS regions; `s_added`: one workgroup-shared counter.
 template <typename K, int GL, int NT>
-__global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items) {
-  extern __shared__ unsigned char s_dyn[];
+__device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nblk,
+                             unsigned char* s_dyn, unsigned long long& s_added) {
   constexpr int GPB = NT / GL;
-  __shared__ unsigned long long s_added;
   Group<GL> g;
   const u32 gid = threadIdx.x / GL;
   K* gk = reinterpret_cast<K*>(s_dyn) + (size_t)gid * 2 * lds_items;  // keys region
@@ -321,19 +363,34 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
   const Ctl* ctl = a.ctl;
   bool abort_all = ctl->call_err != 0 || ctl->need > ctl->free_snapshot;
   if (abort_all) {
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->call_err == 0)
+    if (blk == 0 && threadIdx.x == 0 && ctl->call_err == 0)
       atomicCAS(a.status, 0u, kErrNomem);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ctl->call_err != 0)
+    if (blk == 0 && threadIdx.x == 0 && ctl->call_err != 0)
       atomicCAS(a.status, 0u, ctl->call_err);
+    __syncthreads();
     return;
   }
   const u32 nitems = ctl->heavy_count;
   const u32 f = a.cap / 2;
   u64 added = 0;
-  for (u32 it = blockIdx.x * GPB + gid; it < nitems; it += gridDim.x * GPB) {
-    const WorkItem w = a.work[it];
+  const u32 stride = nblk * GPB;
+  u32 it = blk * GPB + gid;
+  WorkItem wnext;
+  if (it < nitems) wnext = a.work[it];
+  for (; it < nitems; it += stride) {
+    const WorkItem w = wnext;
+    if (it + stride < nitems) wnext = a.work[it + stride];   // prefetch
     u32 X = w.b;
-    NodeHdr hX = a.hdr[X];
+    NodeHdr hX;
+    bool fence_known = true;
+    if (w.head & kSingleNode) {   // single-node bucket: header from the work item
+      hX.size = w.head & ~kSingleNode;
+      hX.next = kNil;
+      hX.fence = 0;
+      fence_known = false;
+    } else {
+      hX = a.hdr[X];
+    }
     bool fresh = false;   // this group has written nodes of this bucket: read coherently
     u32 j = w.s;
     u32 nodes_added = 0;
@@ -397,6 +454,10 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
       u32 k = 1;
       u32 base_id = 0;
       if (c > a.cap) {
+        if (!fence_known) {   // a single node's fence is its bucket's maxBucket
+          hX.fence = (u64)a.mkba[w.b];
+          fence_known = true;
+        }
         k = c / f;
         if (g.lane == 0) base_id = atomicSub(&a.ctl->free_top, k - 1);
         base_id = g.bcast(base_id, 0);
@@ -477,7 +538,10 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
         // continues from piece 0 (X), reading what this wave just wrote.
         fresh = true;
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        if (k > 1) hX = ld_hdr(a.hdr + X, true);
+        if (k > 1) {
+          hX = ld_hdr(a.hdr + X, true);
+          fence_known = true;
+        }
       }
       wave_lds_sync();
     }
@@ -487,6 +551,14 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
   if (g.lane == 0 && added) atomicAdd(&s_added, added);
   __syncthreads();
   if (threadIdx.x == 0 && s_added) atomicAdd((unsigned long long*)&a.ctl->nkeys, s_added);
+  __syncthreads();
+}
+
+template <typename K, int GL, int NT>
+__global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items) {
+  extern __shared__ unsigned char s_dyn[];
+  __shared__ unsigned long long s_added;
+  insert_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, s_added);
 }
 
 // ---------------------------------------------------------------------------
@@ -500,10 +572,9 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
 // (Section 4.4 step 5).  The head node is never freed.
 // ---------------------------------------------------------------------------
 template <typename K, int GL, int NT>
-__global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items) {
-  extern __shared__ unsigned char s_dyn[];
+__device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nblk,
+                             unsigned char* s_dyn, unsigned long long& s_removed) {
   constexpr int GPB = NT / GL;
-  __shared__ unsigned long long s_removed;
   Group<GL> g;
   const u32 gid = threadIdx.x / GL;
   K* ak = reinterpret_cast<K*>(s_dyn) + (size_t)gid * 2 * lds_items;   // node keys [cap]
@@ -514,16 +585,31 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
   const u32 nitems = a.ctl->heavy_count;
   const u32 f = a.cap / 2;
   u64 removed = 0;
-  for (u32 it = blockIdx.x * GPB + gid; it < nitems; it += gridDim.x * GPB) {
-    const WorkItem w = a.work[it];
+  const u32 stride = nblk * GPB;
+  u32 it = blk * GPB + gid;
+  WorkItem wnext;
+  if (it < nitems) wnext = a.work[it];
+  for (; it < nitems; it += stride) {
+    const WorkItem w = wnext;
+    if (it + stride < nitems) wnext = a.work[it + stride];   // prefetch
     // predecessor state (P), kept in registers; P == kNil before the head
     u32 P = kNil;
     NodeHdr hP;
     hP.fence = 0; hP.size = 0; hP.next = kNil;
     bool p_dirty = false;
     bool p_is_head = false;
+    bool p_fence_known = true;
     u32 X = w.b;
-    NodeHdr hX = a.hdr[X];
+    NodeHdr hX;
+    bool x_fence_known = true;
+    if (w.head & kSingleNode) {   // single-node bucket: header from the work item
+      hX.size = w.head & ~kSingleNode;
+      hX.next = kNil;
+      hX.fence = 0;
+      x_fence_known = false;
+    } else {
+      hX = a.hdr[X];
+    }
     u32 j = w.s;
     int freed = 0;
     while (true) {
@@ -602,6 +688,7 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
         hP.fence = hX.fence;
         hP.next = hX.next;
         p_dirty = true;
+        p_fence_known = true;
         if (g.lane == 0) {
           u32 pos = atomicAdd(&a.ctl->free_top, 1u);
           a.free_ids[pos] = X;
@@ -615,11 +702,12 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
           }
           hX.size = sx;
         }
-        if (P != kNil && p_dirty && g.lane == 0) a.hdr[P] = hP;
+        if (P != kNil && p_dirty && g.lane == 0) write_hdr(a.hdr + P, hP, p_fence_known);
         P = X;
         hP = hX;
         p_dirty = touched;
         p_is_head = (X == w.b);
+        p_fence_known = x_fence_known;
       }
       wave_lds_sync();
       j = j2;
@@ -629,14 +717,23 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
       if (!more) break;
       X = nxt;
       hX = a.hdr[X];
+      x_fence_known = true;
     }
-    if (P != kNil && p_dirty && g.lane == 0) a.hdr[P] = hP;
+    if (P != kNil && p_dirty && g.lane == 0) write_hdr(a.hdr + P, hP, p_fence_known);
     if (freed && g.lane == 0) a.bnodes[w.b] -= (u32)freed;
   }
   if (g.lane == 0 && removed) atomicAdd(&s_removed, removed);
   __syncthreads();
   if (threadIdx.x == 0 && s_removed)
     atomicAdd((unsigned long long*)&a.ctl->nkeys, (unsigned long long)(0ull - s_removed));
+  __syncthreads();
+}
+
+template <typename K, int GL, int NT>
+__global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items) {
+  extern __shared__ unsigned char s_dyn[];
+  __shared__ unsigned long long s_removed;
+  delete_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, s_removed);
 }
 
 }  // namespace flix
