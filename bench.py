@@ -109,6 +109,29 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     return fam
 
 
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain copy),
+    or None when the kernel's sources no longer hash to what was measured."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "read_path_step_hbm_counters.md")
+    try:
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        rec = json.loads(m.group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec.get("kernel") != kernel:
+        return None
+    h = hashlib.sha256()
+    for fn in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2604_16725_amd", "csrc", fn), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -226,8 +249,9 @@ def main():
     dom = max(per_fam, key=lambda k: per_fam[k]["ms_per_step"])
     ach = per_fam[dom]["alg_GBps"]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": counter_traffic(dom),
                 "alg_bytes_per_launch": model[dom] / per_fam[dom]["launches_per_step"],
+                "traffic_unit": "HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE)",
                 "avg_launch_us": round(per_fam[dom]["avg_launch_us"], 2)}
 
     # -- per-operation breakdown (each call timed alone with events) --------

@@ -588,6 +588,7 @@ int drain_launch_t(flix_store* s, const DrainBatch* d_batches, u32 nbatch,
   a.chunk = upd_chunk(s);
   a.dctl = s->dctl;
   a.tstamp = d_ts;
+  a.max_batch = (u32)s->max_batch;
   hipLaunchKernelGGL(kfn, dim3(s->drain_grid), dim3(256), shm, st, a);
   HIP_TRY(hipGetLastError());
   return FLIX_OK;

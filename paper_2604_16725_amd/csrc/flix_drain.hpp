@@ -73,6 +73,7 @@ struct DrainArgs {
   u32 chunk;
   DrainCtl* dctl;
   unsigned long long* tstamp;   // [nbatch + 1]: start, then one per batch (may be null)
+  u32 max_batch;
 };
 
 // Grid-wide barrier for a co-resident grid.  Bounded: a workgroup that waits
@@ -87,9 +88,12 @@ __device__ __forceinline__ void grid_sync(DrainCtl* c, u32 nblocks) {
       __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     } else {
+      // Bounded wait; once any barrier has failed (the grid was not fully
+      // resident) no later barrier waits, so the kernel ends promptly.
       u32 polls = 0;
       while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        if (++polls > (1u << 24)) {
+        if (__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) break;
+        if (++polls > (1u << 20)) {
           atomicOr(&c->err, 1u);
           break;
         }
@@ -155,15 +159,22 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
   if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[0] = wall_clock64();
   grid_sync(dc, G);
 
+  u32 nz = 0;   // batches processed so far: selects the histogram slot
   for (u32 bi = 0; bi < a.nbatch; ++bi) {
     const DrainBatch d = a.batches[bi];
     const u32 n = d.n;
+    if (n > a.max_batch || d.op > kOpDelete) {   // rewritten descriptor out of range
+      if (blk == 0 && threadIdx.x == 0) atomicOr(&dc->err, 4u);
+      continue;
+    }
     if (n == 0) {
       if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[bi + 1] = wall_clock64();
       continue;
     }
     const bool is_update = d.op >= kOpInsert;
-    u32* hist = a.hist + (bi & 1u) * (P * R);
+    const u32 slot = nz & 1u;
+    ++nz;
+    u32* hist = a.hist + slot * (P * R);
     if (is_update && blk == 0 && threadIdx.x == 0) {
       a.ctl->need = 0;
       a.ctl->call_err = 0;
@@ -177,14 +188,20 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
     for (int p = 0; p < P; ++p) {
       ++epoch;
-      const K* ki = (p == 0) ? (const K*)d.keys : a.bk[(p & 1) ? 0 : 1];
-      K* ko = a.bk[(p & 1) ? 1 : 0];
+      // constant indices only: a runtime index into the argument arrays
+      // would move them to scratch memory
+      K* const bk0 = a.bk[0];
+      K* const bk1 = a.bk[1];
+      void* const bp0 = a.bp[0];
+      void* const bp1 = a.bp[1];
+      const K* ki = (p == 0) ? (const K*)d.keys : ((p & 1) ? bk0 : bk1);
+      K* ko = (p & 1) ? bk1 : bk0;
       if (d.op == kOpInsert) {
         PassArgs<K, K> pa;
         pa.kin = ki;
-        pa.vin = (p == 0) ? (const K*)d.aux : (const K*)a.bp[(p & 1) ? 0 : 1];
+        pa.vin = (p == 0) ? (const K*)d.aux : (const K*)((p & 1) ? bp0 : bp1);
         pa.kout = ko;
-        pa.vout = (K*)a.bp[(p & 1) ? 1 : 0];
+        pa.vout = (K*)((p & 1) ? bp1 : bp0);
         pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
         pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
         for (u32 t = blk; t < ntiles; t += G)
@@ -201,9 +218,9 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
       } else {
         PassArgs<K, u32> pa;
         pa.kin = ki;
-        pa.vin = (p == 0) ? nullptr : (const u32*)a.bp[(p & 1) ? 0 : 1];
+        pa.vin = (p == 0) ? nullptr : (const u32*)((p & 1) ? bp0 : bp1);
         pa.kout = ko;
-        pa.vout = (u32*)a.bp[(p & 1) ? 1 : 0];
+        pa.vout = (u32*)((p & 1) ? bp1 : bp0);
         pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
         pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
         for (u32 t = blk; t < ntiles; t += G)
@@ -213,10 +230,10 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
       grid_sync(dc, G);
     }
     const int r = ((P - 1) & 1) ? 1 : 0;
-    // the other histogram slot was last used by batch bi-1 and is next used by
-    // batch bi+1, after at least one more barrier
+    // the other histogram slot was last used by the previous batch and is
+    // next used by the following one, after at least one more barrier
     if (blk == 0)
-      for (int i = threadIdx.x; i < P * R; i += 256) a.hist[((bi + 1u) & 1u) * (P * R) + i] = 0;
+      for (int i = threadIdx.x; i < P * R; i += 256) a.hist[(slot ^ 1u) * (P * R) + i] = 0;
     // ---- apply
     if (!is_update) {
       ReadArgs<K> ra;

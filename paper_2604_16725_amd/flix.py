@@ -49,6 +49,26 @@ class FlixStats(ctypes.Structure):
     ]
 
 
+class FlixBatch(ctypes.Structure):
+    """One descriptor of a drained queue (layout of flix_batch in flix.h)."""
+    _fields_ = [
+        ("op", ctypes.c_uint32),
+        ("n", ctypes.c_uint32),
+        ("max_per_query", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("d_keys", ctypes.c_void_p),
+        ("d_aux", ctypes.c_void_p),
+        ("d_vals_out", ctypes.c_void_p),
+        ("d_keys_out", ctypes.c_void_p),
+        ("d_counts", ctypes.c_void_p),
+        ("reserved2", ctypes.c_void_p),
+    ]
+
+
+OP_LOOKUP, OP_SUCCESSOR, OP_RANGE, OP_INSERT, OP_DELETE = 0, 1, 2, 3, 4
+OPS = {"lookup": OP_LOOKUP, "successor": OP_SUCCESSOR, "range": OP_RANGE,
+       "insert": OP_INSERT, "delete": OP_DELETE}
+
 _lib = None
 
 
@@ -80,6 +100,11 @@ def load_library(path: str = LIB_PATH):
         "flix_copy_layout": (i32, [vp, vp, vp, vp, vp, vp, ctypes.POINTER(u64), vp]),
         "flix_sort_pairs": (i32, [vp, vp, u64, vp, vp, vp]),
         "flix_last_error": (ctypes.c_char_p, []),
+        "flix_drain": (i32, [vp, vp, vp, u32, vp, vp]),
+        "flix_drain_graph": (i32, [vp, vp, vp, u32, vp, ctypes.POINTER(vp), vp]),
+        "flix_graph_launch": (i32, [vp, vp]),
+        "flix_graph_destroy": (i32, [vp]),
+        "flix_drain_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64)]),
         "flix_set_timing": (i32, [vp, i32]),
         "flix_kernel_time": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
@@ -254,6 +279,48 @@ class Store:
                                            _stream(stream)), "flix_sort_pairs")
         return ko, io
 
+    # -- persistent drain -----------------------------------------------------
+    def make_batches(self, batches):
+        """Host descriptor array from a list of dicts: op (name or code), keys,
+        aux (insert values / range hi), out_v, out_k, counts, max_per_query."""
+        arr = (FlixBatch * len(batches))()
+        for i, b in enumerate(batches):
+            op = OPS[b["op"]] if isinstance(b["op"], str) else int(b["op"])
+            keys = b.get("keys")
+            n = 0 if keys is None else keys.numel()
+            arr[i] = FlixBatch(op, n, int(b.get("max_per_query", 0)), 0,
+                               _ptr(keys).value, _ptr(b.get("aux")).value,
+                               _ptr(b.get("out_v")).value, _ptr(b.get("out_k")).value,
+                               _ptr(b.get("counts")).value, None)
+        return arr
+
+    def _dev_descriptors(self, arr, dev=None):
+        raw = bytes(arr)
+        host = self.torch.frombuffer(bytearray(raw), dtype=self.torch.uint8)
+        if dev is None:
+            return host.cuda()
+        dev.copy_(host)
+        return dev
+
+    def drain(self, batches, timestamps=None, stream=None):
+        """Run the batches in order in one persistent kernel launch."""
+        arr = self.make_batches(batches)
+        dev = self._dev_descriptors(arr)
+        self._drain_keep = dev   # alive until the next drain
+        rc = self.lib.flix_drain(self.h, ctypes.byref(arr), _ptr(dev), len(batches),
+                                 _ptr(timestamps), _stream(stream))
+        self._chk(rc, "flix_drain")
+
+    def drain_graph(self, batches, timestamps=None, stream=None):
+        """Capture a drain of these batches in a hipGraph; see DrainGraph."""
+        return DrainGraph(self, batches, timestamps, stream)
+
+    def drain_info(self):
+        g, hz = ctypes.c_uint32(), ctypes.c_uint64()
+        self._chk(self.lib.flix_drain_info(self.h, ctypes.byref(g), ctypes.byref(hz)),
+                  "flix_drain_info")
+        return int(g.value), int(hz.value)
+
     def set_timing(self, on: bool):
         self._chk(self.lib.flix_set_timing(self.h, 1 if on else 0), "flix_set_timing")
 
@@ -263,3 +330,48 @@ class Store:
         self._chk(self.lib.flix_kernel_time(self.h, family.encode(), ctypes.byref(ms),
                                             ctypes.byref(n)), "flix_kernel_time")
         return ms.value, int(n.value)
+
+
+class DrainGraph:
+    """An instantiated hipGraph holding one drain launch.  `update(batches)`
+    rewrites the device descriptors (same count) for the next replay."""
+
+    def __init__(self, store, batches, timestamps=None, stream=None):
+        self.store = store
+        self.n = len(batches)
+        self.stream = stream
+        arr = store.make_batches(batches)
+        self.dev = store._dev_descriptors(arr)
+        store.torch.cuda.synchronize()
+        ex = ctypes.c_void_p()
+        rc = store.lib.flix_drain_graph(store.h, ctypes.byref(arr), _ptr(self.dev), self.n,
+                                        _ptr(timestamps), ctypes.byref(ex), _stream(stream))
+        if rc != FLIX_OK:
+            raise FlixError(rc, "flix_drain_graph")
+        self.ex = ex
+
+    def update(self, batches):
+        if len(batches) != self.n:
+            raise ValueError("a graph replays a fixed number of batches")
+        mb = self.store.cfg.max_batch
+        for b in batches:
+            if b.get("keys") is not None and b["keys"].numel() > mb:
+                raise ValueError("batch larger than max_batch")
+        arr = self.store.make_batches(batches)
+        self.store._dev_descriptors(arr, self.dev)
+
+    def launch(self, stream=None):
+        rc = self.store.lib.flix_graph_launch(self.ex, _stream(stream or self.stream))
+        if rc != FLIX_OK:
+            raise FlixError(rc, "flix_graph_launch")
+
+    def close(self):
+        if getattr(self, "ex", None):
+            self.store.lib.flix_graph_destroy(self.ex)
+            self.ex = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
