@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--radix-bits", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the mixed-batch stream (persistent drain vs plain launches)")
+    ap.add_argument("--nbatch", type=int, default=4096, help="batches in the mixed stream")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first copy a MiB-sized device buffer 4 times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -130,6 +133,68 @@ def counter_traffic(kernel):
     if h.hexdigest() != rec["sources_sha256"]:
         return None
     return rec["traffic_bytes_per_launch"]
+
+
+def batching_compare(args):
+    """The mixed-batch stream on a 2^keys_log2 u32 store: one ABI call per
+    batch versus the persistent drain replayed from a hipGraph.  Both start
+    from the same bulk load; their outputs and final contents must agree."""
+    import torch
+    from paper_2604_16725_amd import autotune, flix
+    from paper_2604_16725_amd.batching import DeviceStream, PersistentRun, run_plain, summarize
+    from paper_2604_16725_amd.workloads import BatchStream
+
+    cfg = autotune.tuned_config()
+    t0 = time.time()
+    stream = BatchStream(n_keys=1 << args.keys_log2, nbatch=args.nbatch)
+    ds = DeviceStream(stream)
+    log(f"[bench] mixed stream: {ds.n} batches, {ds.total_ops} ops resident "
+        f"({time.time() - t0:.1f}s)")
+    cs = torch.cuda.Stream()
+    res = {}
+    with torch.cuda.stream(cs):
+        st = flix.Store(key_bits=32, capacity=cfg["capacity"], lanes=cfg["lanes"],
+                        radix_bits=cfg["radix_bits"], max_batch=1 << 20)
+        outs_p, outs_g = ds.outputs(), ds.outputs()
+        plain = None
+        for rep in range(2):
+            st.bulk_load(ds.build_keys, ds.build_vals)
+            wall, svc = run_plain(st, ds, outs_p, events=(rep == 0))
+            if rep == 0:
+                plain = summarize(wall, svc, ds.total_ops)
+            else:
+                plain["Mops_s"] = round(ds.total_ops / wall / 1e6, 1)
+                plain["wall_ms"] = round(wall * 1e3, 3)
+        if st.status() != 0:
+            raise RuntimeError("device error in the plain stream")
+        dump_p = st.dump()
+        log(f"[bench] plain: {plain}")
+        run = PersistentRun(st, ds, outs_g, cs)
+        pers = None
+        for rep in range(2):
+            st.bulk_load(ds.build_keys, ds.build_vals)
+            wall, svc = run.run()
+            cur = summarize(wall, svc, ds.total_ops)
+            if pers is None or cur["Mops_s"] > pers["Mops_s"]:
+                pers = cur
+        if st.status() != 0:
+            raise RuntimeError("device error in the persistent stream")
+        dump_g = st.dump()
+        log(f"[bench] persistent: {pers}")
+        same = (torch.equal(outs_p[0], outs_g[0]) and torch.equal(outs_p[1], outs_g[1])
+                and torch.equal(dump_p[0], dump_g[0]) and torch.equal(dump_p[1], dump_g[1]))
+        res = {"workload": f"{ds.n} mixed batches, sizes floor(2^U) U~U[8,20], 70/10/10/10 "
+                           f"lookup/successor/insert/delete, 2^{args.keys_log2} u32 keys",
+               "ops": ds.total_ops, "store": cfg, "drain_workgroups": st.drain_info()[0],
+               "plain": plain, "persistent_graph": pers,
+               "speedup_Mops": round(pers["Mops_s"] / plain["Mops_s"], 3),
+               "p99_ratio_plain_over_persistent": round(plain["p99_us"] / pers["p99_us"], 3),
+               "results_identical": bool(same)}
+        run.close()
+        st.close()
+    if not res["results_identical"]:
+        raise RuntimeError("persistent and plain results differ")
+    return res
 
 
 def main():
@@ -289,6 +354,9 @@ def main():
         if st.status() != 0:
             raise RuntimeError("device error during breakdown")
 
+    st.close()
+    batching = None if args.no_batching else batching_compare(args)
+
     # -- CPU baseline: the oracle on a bounded sample -----------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -334,9 +402,9 @@ def main():
         "ms_per_step_without_kernel_events": round(ms_step_noev, 4),
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_fam.items()},
         "breakdown": breakdown,
+        "batching": batching,
     }
     print(json.dumps(out), flush=True)
-    st.close()
 
 
 if __name__ == "__main__":

@@ -216,6 +216,49 @@ int flix_graph_destroy(void* graph_exec);
  * tick rate of the drain timestamps. */
 int flix_drain_info(flix_store* s, uint32_t* grid_blocks, uint64_t* timestamp_hz);
 
+/* ---- Epochs: coalesced mixed requests (the serving form) ----
+ * An epoch is a group of requests merged into three lists: lookups, ranges
+ * and updates.  Its order is defined as follows (the paper only has
+ * single-type batches): every read of the epoch observes the store as it was
+ * before the epoch; then the updates take effect, and for each key the entry
+ * that comes LAST in d_update_keys decides: a value equal to the reserved
+ * all-ones pattern deletes the key, any other value upserts it.
+ *
+ * Two slots let one epoch be prepared while the previous one is applied:
+ * flix_epoch_prepare sorts the epoch's three lists into the slot and folds
+ * the updates (it reads only the epoch's inputs, never the store), and
+ * flix_epoch_apply runs the bucket kernels of the prepared slot: lookups,
+ * ranges (as flix_lookup / flix_range), then the folded deletes and upserts.
+ * The caller orders the two streams with events: a slot's apply after its
+ * prepare, a slot's next prepare after its previous apply, and all applies
+ * in epoch order on one stream.  apply must get the same descriptor as the
+ * prepare of that slot (EINVAL otherwise).  All buffers are device memory
+ * owned by the caller and must stay valid until the apply completes.
+ * Errors: EINVAL for a slot >= FLIX_EPOCH_SLOTS, counts above max_batch,
+ * null buffers with a non-zero count, reserved != 0.  Device-detected
+ * ENOMEM cancels the epoch's upserts (its deletes have been applied) and
+ * sets the sticky status.  The first call allocates the slots' scratch. */
+#define FLIX_EPOCH_SLOTS 2
+typedef struct {
+  uint64_t n_lookup;
+  const void* d_lookup_keys;   /* [n_lookup] */
+  void* d_lookup_vals;         /* [n_lookup] out: value or all-ones */
+  uint64_t n_range;
+  uint32_t range_max;          /* result slots per range */
+  uint32_t reserved;           /* must be 0 */
+  const void* d_range_lo;      /* [n_range] */
+  const void* d_range_hi;      /* [n_range] */
+  uint32_t* d_range_counts;    /* [n_range] out: keys in [lo, hi] */
+  void* d_range_keys;          /* [n_range * range_max] out, may be NULL */
+  void* d_range_vals;          /* [n_range * range_max] out, may be NULL */
+  uint64_t n_update;
+  const void* d_update_keys;   /* [n_update] in request order */
+  const void* d_update_vals;   /* [n_update] all-ones = delete */
+} flix_epoch;
+
+int flix_epoch_prepare(flix_store* s, uint32_t slot, const flix_epoch* e, void* stream);
+int flix_epoch_apply(flix_store* s, uint32_t slot, const flix_epoch* e, void* stream);
+
 /* Text describing the last HIP runtime error a call of this host thread hit
  * (which call and the runtime's message); "" if none.  Never NULL. */
 const char* flix_last_error(void);

@@ -106,6 +106,35 @@ class Oracle:
                             _ptr(counts), _ptr(ko), _ptr(vo))
         return counts, ko, vo
 
+    def apply_epoch(self, lookup_keys, range_lo, range_hi, range_max: int, update_keys,
+                    update_vals):
+        """One epoch of mixed requests, in the order the serving form defines
+        (the paper itself only has single-type batches): every lookup and
+        range sees the map as it was before the epoch; then the updates take
+        effect one after another in array order, where a value equal to the
+        all-ones pattern deletes the key and any other value sets it.
+
+        The sequential application is folded per key (a plain dict keeps the
+        last entry of each key), then applied as one delete batch and one
+        insert batch, which touch disjoint keys.
+        Returns (lookup values, range counts, range values [n, range_max]).
+        """
+        lv = self.lookup(lookup_keys)
+        rc, _, rv = self.range(range_lo, range_hi, range_max)
+        tomb = (1 << self.key_bits) - 1
+        last = {}
+        for k, v in zip(np.asarray(update_keys).tolist(), np.asarray(update_vals).tolist()):
+            last[k] = v
+        dels = [k for k, v in last.items() if v == tomb]
+        ups = [(k, v) for k, v in last.items() if v != tomb]
+        if dels:
+            self.delete(np.array(dels, dtype=self.dtype))
+        if ups:
+            rc_ins = self.insert(np.array([k for k, _ in ups], dtype=self.dtype),
+                                 np.array([v for _, v in ups], dtype=self.dtype))
+            assert rc_ins == 0
+        return lv, rc, rv
+
     def size(self) -> int:
         return int(self._lib.orc_size(self._h))
 

@@ -1,0 +1,112 @@
+"""Autotuner for the batching form.
+
+Sweeps node capacity x lanes per bucket x radix digit width over a prefix of
+the mixed-batch stream (uneven batches of 2^8..2^20 lookup / successor /
+insert / delete operations on a 2^26-key u32 store), drained by the
+persistent kernel from a hipGraph, and ranks the points by throughput.  The
+prior is the paper's own sweep of node size and threads per block for the
+insert kernels (Section 6, the heat-map study); this sweep covers the knobs
+that exist in this design instead.
+
+Every point must produce the same results as the first one (the semantics do
+not depend on the layout); a point that differs stops the sweep.
+
+    python -m paper_2604_16725_amd.autotune [--prefix 512] [--out PATH]
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_PATH = os.path.join(HERE, "tuning", "batching_mi355x.json")
+GRID = {"capacity": (32, 64, 128, 256), "lanes": (16, 32, 64), "radix_bits": (4, 8)}
+FALLBACK = {"capacity": 128, "lanes": 16, "radix_bits": 8}
+
+
+def tuned_config(path: str = DEFAULT_PATH) -> dict:
+    """The best point of a saved sweep, else the untuned default."""
+    try:
+        with open(path) as f:
+            best = json.load(f)["best"]
+        return {k: int(best[k]) for k in FALLBACK}
+    except (OSError, KeyError, ValueError):
+        return dict(FALLBACK)
+
+
+def sweep(n_keys: int = 1 << 26, nbatch: int = 4096, prefix: int = 512, reps: int = 2,
+          grid: dict = GRID, with_plain: bool = False, log=print):
+    import torch
+    from . import flix
+    from .batching import DeviceStream, PersistentRun, run_plain, summarize
+    from .workloads import BatchStream
+
+    stream = BatchStream(n_keys=n_keys, nbatch=nbatch)
+    ds = DeviceStream(stream, limit=prefix)
+    log(f"[autotune] {ds.n} batches, {ds.total_ops} ops resident")
+    ref = None
+    points = []
+    cs = torch.cuda.Stream()
+    with torch.cuda.stream(cs):
+        for cap, gl, rb in itertools.product(grid["capacity"], grid["lanes"], grid["radix_bits"]):
+            st = flix.Store(key_bits=32, capacity=cap, lanes=gl, radix_bits=rb, max_batch=1 << 20)
+            outs = ds.outputs()
+            run = PersistentRun(st, ds, outs, cs)
+            best_wall, best_svc = None, None
+            for _ in range(reps):
+                st.bulk_load(ds.build_keys, ds.build_vals)
+                wall, svc = run.run()
+                if best_wall is None or wall < best_wall:
+                    best_wall, best_svc = wall, svc
+            if st.status() != 0:
+                raise RuntimeError(f"device error at capacity {cap} lanes {gl} radix {rb}")
+            if ref is None:
+                ref = (outs[0].clone(), outs[1].clone())
+            elif not (torch.equal(ref[0], outs[0]) and torch.equal(ref[1], outs[1])):
+                raise RuntimeError(f"results differ at capacity {cap} lanes {gl} radix {rb}")
+            pt = {"capacity": cap, "lanes": gl, "radix_bits": rb, "grid_blocks": st.drain_info()[0]}
+            pt["persistent"] = summarize(best_wall, best_svc, ds.total_ops)
+            if with_plain:
+                st.bulk_load(ds.build_keys, ds.build_vals)
+                pt["plain"] = summarize(*run_plain(st, ds, outs), ds.total_ops)
+            points.append(pt)
+            log(f"[autotune] cap {cap:3d} lanes {gl:2d} radix {rb}: "
+                f"{pt['persistent']['Mops_s']} Mops/s, p99 {pt['persistent'].get('p99_us')} us")
+            run.close()
+            st.close()
+            del outs
+    best = max(points, key=lambda p: p["persistent"]["Mops_s"])
+    return {"workload": f"mixed batch stream prefix: {ds.n} of {nbatch} batches "
+                        f"({ds.total_ops} ops), sizes 2^8..2^20 log-uniform, 70/10/10/10 "
+                        f"lookup/successor/insert/delete, {n_keys} u32 keys",
+            "device": torch.cuda.get_device_name(0),
+            "measured": time.strftime("%Y-%m-%d"),
+            "points": points,
+            "best": {k: best[k] for k in ("capacity", "lanes", "radix_bits")}
+            | {"Mops_s": best["persistent"]["Mops_s"]}}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="sweep the batching-form layout knobs")
+    ap.add_argument("--keys-log2", type=int, default=26)
+    ap.add_argument("--prefix", type=int, default=512, help="batches of the stream to run")
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--with-plain", action="store_true")
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    a = ap.parse_args(argv)
+    res = sweep(n_keys=1 << a.keys_log2, prefix=a.prefix, reps=a.reps, with_plain=a.with_plain,
+                log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    with open(a.out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res["best"]), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -12,6 +12,7 @@
 #include "flix_build.hpp"
 #include "flix_device.hpp"
 #include "flix_drain.hpp"
+#include "flix_epoch.hpp"
 #include "flix_read.hpp"
 #include "flix_read2.hpp"
 #include "flix_sort.hpp"
@@ -36,6 +37,28 @@ struct Timing {
 };
 
 }  // namespace
+
+// Scratch of one epoch slot: the sorted read lists, the sorted and folded
+// update lists and a sort scratch of its own, so that one slot can be
+// prepared while another slot's epoch is applied.
+struct EpochSlot {
+  u64 cap = 0;                         // items per list
+  void* lk[2] = {nullptr, nullptr};    // lookups: keys, original index
+  void* lp[2] = {nullptr, nullptr};
+  void* rk[2] = {nullptr, nullptr};    // ranges: lo, original index
+  void* rp[2] = {nullptr, nullptr};
+  void* uk[2] = {nullptr, nullptr};    // updates: keys, values
+  void* up[2] = {nullptr, nullptr};
+  void* ins_k = nullptr;               // folded upserts (sorted, distinct)
+  void* ins_v = nullptr;
+  void* del_k = nullptr;               // folded deletes (sorted, distinct)
+  u32* bsum = nullptr;                 // [2][blocks] fold block counts
+  u32* counts = nullptr;               // [0] upserts, [1] deletes, [2..3] spare
+  SortScratch ss;
+  int rl = 0, rr = 0, ru = 0;          // which ping-pong buffer holds each sorted list
+  bool prepared = false;
+  u64 n_lookup = 0, n_range = 0, n_update = 0;
+};
 
 struct flix_store {
   flix_config cfg{};
@@ -68,6 +91,8 @@ struct flix_store {
   DrainCtl* dctl = nullptr;
   int drain_grid = 0;                 // co-resident workgroups of the drain kernel
   size_t drain_shm = 0;
+  // epoch slots (allocated by the first epoch call)
+  EpochSlot* ep[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -277,15 +302,13 @@ void launch_read2(const flix_store* s, const ReadArgs<K>& a, int op, u32 grid, h
   }
 }
 
+// Bucket kernel over an already sorted read list (keys + original index).
 template <typename K>
-int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void* out_v,
-               const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
-  int r;
-  int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r);
-  if (rc) return rc;
+int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u64 n, void* out_k,
+                      void* out_v, const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
   ReadArgs<K> a;
-  a.skeys = (const K*)s->bk[r];
-  a.sidx = (const u32*)s->bp[r];
+  a.skeys = skeys;
+  a.sidx = sidx;
   a.m = (u32)n;
   a.mkba = (const K*)s->mkba;
   a.nb = s->nb;
@@ -308,6 +331,16 @@ int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void
   return FLIX_OK;
 }
 
+template <typename K>
+int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void* out_v,
+               const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
+  int r;
+  int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r);
+  if (rc) return rc;
+  return read_apply_sorted<K>(s, op, (const K*)s->bk[r], (const u32*)s->bp[r], n, out_k, out_v, hi,
+                              counts, maxpq, st);
+}
+
 // ---- update path ------------------------------------------------------------
 template <typename K>
 struct SliceCfg;
@@ -325,37 +358,54 @@ constexpr int kUpdNT = 256;
 u32 upd_chunk(const flix_store* s) { return std::max<u32>(s->cap, 64u); }
 u32 upd_lds_items(const flix_store* s) { return s->cap + upd_chunk(s); }
 
+// m_dev: null for a list of host-known length n; otherwise the length is read
+// from device memory and n is its upper bound (grid sizing only).
 template <typename K, int GL>
 void launch_update(flix_store* s, bool insert, const UpdArgs<K>& a, u32 grid, hipStream_t st,
-                   u32 lds_items) {
+                   u32 lds_items, const u32* m_dev) {
   size_t shm = (size_t)(kUpdNT / GL) * 2 * lds_items * sizeof(K);
-  static size_t attr_set[2] = {0, 0};
-  if (shm > 65536 && shm > attr_set[insert ? 1 : 0]) {
-    hipError_t e = hipFuncSetAttribute(
-        insert ? reinterpret_cast<const void*>(&k_insert_apply<K, GL, kUpdNT>)
-               : reinterpret_cast<const void*>(&k_delete_apply<K, GL, kUpdNT>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (e == hipSuccess) attr_set[insert ? 1 : 0] = shm;
+  static size_t attr_set[4] = {0, 0, 0, 0};
+  const int which = (insert ? 1 : 0) + (m_dev ? 2 : 0);
+  if (shm > 65536 && shm > attr_set[which]) {
+    const void* fn;
+    switch (which) {
+      case 0: fn = reinterpret_cast<const void*>(&k_delete_apply<K, GL, kUpdNT>); break;
+      case 1: fn = reinterpret_cast<const void*>(&k_insert_apply<K, GL, kUpdNT>); break;
+      case 2: fn = reinterpret_cast<const void*>(&k_delete_counted<K, GL, kUpdNT>); break;
+      default: fn = reinterpret_cast<const void*>(&k_insert_counted<K, GL, kUpdNT>); break;
+    }
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e == hipSuccess) attr_set[which] = shm;
     (void)hipGetLastError();
   }
-  if (insert)
-    hipLaunchKernelGGL((k_insert_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
-                       lds_items);
-  else
-    hipLaunchKernelGGL((k_delete_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
-                       lds_items);
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL((k_delete_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
+                         lds_items);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_insert_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
+                         lds_items);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_delete_counted<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
+                         lds_items, m_dev);
+      break;
+    default:
+      hipLaunchKernelGGL((k_insert_counted<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
+                         lds_items, m_dev);
+      break;
+  }
 }
 
+// Slice discovery and the bucket kernel over an already sorted update list
+// (the per-call counters must have been reset on the stream before).
 template <typename K>
-int update_batch(flix_store* s, bool insert, const void* keys, const void* vals, u64 n,
-                 hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
-  int r;
-  int rc = sort_batch<K>(s, keys, vals, n, insert ? kPayValue : kPayNone, st, &r);
-  if (rc) return rc;
+int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* svals, u64 n,
+                        const u32* m_dev, hipStream_t st) {
   SliceArgs<K> sa;
-  sa.skeys = (const K*)s->bk[r];
-  sa.svals = insert ? (const K*)s->bp[r] : nullptr;
+  sa.skeys = skeys;
+  sa.svals = insert ? svals : nullptr;
   sa.m = (u32)n;
   sa.mkba = (const K*)s->mkba;
   sa.nb = s->nb;
@@ -369,17 +419,24 @@ int update_batch(flix_store* s, bool insert, const void* keys, const void* vals,
   u64 grid = ((u64)n + s->nb + sa.share - 1) / sa.share;
   hipEvent_t b;
   tm_begin(s, st, &b);
-  if (insert)
-    hipLaunchKernelGGL((k_slices<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa);
-  else
-    hipLaunchKernelGGL((k_slices<K, 256, SS, false>), dim3(grid), dim3(256), 0, st, sa);
+  if (m_dev) {
+    if (insert)
+      hipLaunchKernelGGL((k_slices_counted<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa, m_dev);
+    else
+      hipLaunchKernelGGL((k_slices_counted<K, 256, SS, false>), dim3(grid), dim3(256), 0, st, sa, m_dev);
+  } else {
+    if (insert)
+      hipLaunchKernelGGL((k_slices<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa);
+    else
+      hipLaunchKernelGGL((k_slices<K, 256, SS, false>), dim3(grid), dim3(256), 0, st, sa);
+  }
   tm_end(s, st, F_PRE, b);
   HIP_TRY(hipGetLastError());
 
   UpdArgs<K> ua;
   ua.mkba = (const K*)s->mkba;
-  ua.skeys = (const K*)s->bk[r];
-  ua.svals = insert ? (const K*)s->bp[r] : nullptr;
+  ua.skeys = skeys;
+  ua.svals = insert ? svals : nullptr;
   ua.m = (u32)n;
   ua.hdr = s->hdr;
   ua.nkeys = (K*)s->nkeys;
@@ -400,12 +457,165 @@ int update_batch(flix_store* s, bool insert, const void* keys, const void* vals,
   if (g2 > 16384) g2 = 16384;
   tm_begin(s, st, &b);
   switch (s->gl) {
-    case 16: launch_update<K, 16>(s, insert, ua, (u32)g2, st, lds_items); break;
-    case 32: launch_update<K, 32>(s, insert, ua, (u32)g2, st, lds_items); break;
-    default: launch_update<K, 64>(s, insert, ua, (u32)g2, st, lds_items); break;
+    case 16: launch_update<K, 16>(s, insert, ua, (u32)g2, st, lds_items, m_dev); break;
+    case 32: launch_update<K, 32>(s, insert, ua, (u32)g2, st, lds_items, m_dev); break;
+    default: launch_update<K, 64>(s, insert, ua, (u32)g2, st, lds_items, m_dev); break;
   }
   tm_end(s, st, insert ? F_INSERT : F_DELETE, b);
   HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
+template <typename K>
+int update_batch(flix_store* s, bool insert, const void* keys, const void* vals, u64 n,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+  int r;
+  int rc = sort_batch<K>(s, keys, vals, n, insert ? kPayValue : kPayNone, st, &r);
+  if (rc) return rc;
+  return update_apply_sorted<K>(s, insert, (const K*)s->bk[r],
+                                insert ? (const K*)s->bp[r] : nullptr, n, nullptr, st);
+}
+
+// ---- epochs -----------------------------------------------------------------
+void free_slot(EpochSlot* e) {
+  for (int i = 0; i < 2; ++i) {
+    dev_free(&e->lk[i]); dev_free(&e->lp[i]);
+    dev_free(&e->rk[i]); dev_free(&e->rp[i]);
+    dev_free(&e->uk[i]); dev_free(&e->up[i]);
+  }
+  dev_free(&e->ins_k); dev_free(&e->ins_v); dev_free(&e->del_k);
+  dev_free(&e->bsum); dev_free(&e->counts);
+  dev_free(&e->ss.hist); dev_free(&e->ss.status); dev_free(&e->ss.status_cl);
+  dev_free(&e->ss.tile_ctr); dev_free(&e->ss.err);
+}
+
+int alloc_slot(flix_store* s, EpochSlot* e) {
+  const u64 n = s->max_batch;
+  const u64 K = s->ksz;
+  const u64 nblk = (n + kCompactTile - 1) / kCompactTile;
+  int rc;
+  for (int i = 0; i < 2; ++i) {
+    if ((rc = dev_alloc(&e->lk[i], n * K)) || (rc = dev_alloc(&e->lp[i], n * 4)) ||
+        (rc = dev_alloc(&e->rk[i], n * K)) || (rc = dev_alloc(&e->rp[i], n * 4)) ||
+        (rc = dev_alloc(&e->uk[i], n * K)) || (rc = dev_alloc(&e->up[i], n * K)))
+      return rc;
+  }
+  if ((rc = dev_alloc(&e->ins_k, n * K)) || (rc = dev_alloc(&e->ins_v, n * K)) ||
+      (rc = dev_alloc(&e->del_k, n * K)) || (rc = dev_alloc(&e->bsum, 2 * nblk * 4)) ||
+      (rc = dev_alloc(&e->counts, 16)))
+    return rc;
+  const u64 words = sort_status_words(n, 8);
+  const u64 cwords = sort_cluster_words(n);
+  if ((rc = dev_alloc(&e->ss.hist, 2 * 2048 * sizeof(u32))) ||
+      (rc = dev_alloc(&e->ss.status, words * 8)) || (rc = dev_alloc(&e->ss.status_cl, cwords * 8)) ||
+      (rc = dev_alloc(&e->ss.tile_ctr, 64)) || (rc = dev_alloc(&e->ss.err, 16)))
+    return rc;
+  HIP_TRY(hipMemset(e->ss.hist, 0, 2 * 2048 * sizeof(u32)));
+  HIP_TRY(hipMemset(e->ss.status, 0, words * 8));
+  HIP_TRY(hipMemset(e->ss.status_cl, 0, cwords * 8));
+  HIP_TRY(hipMemset(e->ss.tile_ctr, 0, 64));
+  HIP_TRY(hipMemset(e->ss.err, 0, 16));
+  HIP_TRY(hipMemset(e->counts, 0, 16));
+  e->ss.max_items = n;
+  e->ss.epoch = 0;
+  e->ss.parity = 0;
+  e->cap = n;
+  return FLIX_OK;
+}
+
+int ensure_slots(flix_store* s) {
+  if (s->ep[0]) return FLIX_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  for (int i = 0; i < 2; ++i) {
+    EpochSlot* e = new (std::nothrow) EpochSlot;
+    if (!e) return FLIX_ENOMEM;
+    int rc = alloc_slot(s, e);
+    if (rc) {
+      free_slot(e);
+      delete e;
+      for (int j = 0; j < i; ++j) {
+        free_slot(s->ep[j]);
+        delete s->ep[j];
+        s->ep[j] = nullptr;
+      }
+      return rc;
+    }
+    s->ep[i] = e;
+  }
+  return FLIX_OK;
+}
+
+template <typename K, int RB>
+int epoch_prepare_rb(EpochSlot* es, const flix_epoch* e, hipStream_t st) {
+  hipError_t err = hipSuccess;
+  if (e->n_lookup)
+    err = radix_sort<K, u32, RB, kPayIndex>((const K*)e->d_lookup_keys, nullptr, (K*)es->lk[0],
+                                            (u32*)es->lp[0], (K*)es->lk[1], (u32*)es->lp[1],
+                                            (u32)e->n_lookup, es->ss, st, &es->rl);
+  if (err == hipSuccess && e->n_range)
+    err = radix_sort<K, u32, RB, kPayIndex>((const K*)e->d_range_lo, nullptr, (K*)es->rk[0],
+                                            (u32*)es->rp[0], (K*)es->rk[1], (u32*)es->rp[1],
+                                            (u32)e->n_range, es->ss, st, &es->rr);
+  if (err == hipSuccess && e->n_update)
+    err = radix_sort<K, K, RB, kPayValue>((const K*)e->d_update_keys, (const K*)e->d_update_vals,
+                                          (K*)es->uk[0], (K*)es->up[0], (K*)es->uk[1],
+                                          (K*)es->up[1], (u32)e->n_update, es->ss, st, &es->ru);
+  if (err != hipSuccess) return note_hip_error(err, "epoch sort", __LINE__);
+  if (e->n_update) {
+    const u64 n = e->n_update;
+    const u32 nblk = (u32)((n + kCompactTile - 1) / kCompactTile);
+    const K* sk = (const K*)es->uk[es->ru];
+    const K* sv = (const K*)es->up[es->ru];
+    u32* bi = es->bsum;
+    u32* bd = es->bsum + nblk;
+    hipLaunchKernelGGL((k_fold_count<K>), dim3(nblk), dim3(kCompactNT), 0, st, sk, sv, n, bi, bd);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bi, nblk, es->counts);
+    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bd, nblk, es->counts + 1);
+    hipLaunchKernelGGL((k_fold_scatter<K>), dim3(nblk), dim3(kCompactNT), 0, st, sk, sv, n, bi, bd,
+                       (K*)es->ins_k, (K*)es->ins_v, (K*)es->del_k);
+    HIP_TRY(hipGetLastError());
+  }
+  return FLIX_OK;
+}
+
+template <typename K>
+int epoch_apply_t(flix_store* s, EpochSlot* es, const flix_epoch* e, hipStream_t st) {
+  int rc;
+  if (e->n_lookup &&
+      (rc = read_apply_sorted<K>(s, kOpLookup, (const K*)es->lk[es->rl], (const u32*)es->lp[es->rl],
+                                 e->n_lookup, nullptr, e->d_lookup_vals, nullptr, nullptr, 0, st)))
+    return rc;
+  if (e->n_range &&
+      (rc = read_apply_sorted<K>(s, kOpRange, (const K*)es->rk[es->rr], (const u32*)es->rp[es->rr],
+                                 e->n_range, e->d_range_keys, e->d_range_vals, e->d_range_hi,
+                                 e->d_range_counts, e->range_max, st)))
+    return rc;
+  if (e->n_update) {
+    // the folded lists hold distinct keys, so deletes and upserts commute;
+    // deletes go first and return nodes to the free list
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+    if ((rc = update_apply_sorted<K>(s, false, (const K*)es->del_k, nullptr, e->n_update,
+                                     es->counts + 1, st)))
+      return rc;
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+    if ((rc = update_apply_sorted<K>(s, true, (const K*)es->ins_k, (const K*)es->ins_v,
+                                     e->n_update, es->counts, st)))
+      return rc;
+  }
+  return FLIX_OK;
+}
+
+int epoch_validate(flix_store* s, uint32_t slot, const flix_epoch* e) {
+  if (!s) return FLIX_ESTATE;
+  if (!e || slot >= 2) return FLIX_EINVAL;
+  if (e->reserved != 0) return FLIX_EINVAL;
+  if (e->n_lookup > s->max_batch || e->n_range > s->max_batch || e->n_update > s->max_batch)
+    return FLIX_EINVAL;
+  if (e->n_lookup && (!e->d_lookup_keys || !e->d_lookup_vals)) return FLIX_EINVAL;
+  if (e->n_range && (!e->d_range_lo || !e->d_range_hi || !e->d_range_counts)) return FLIX_EINVAL;
+  if (e->n_range && e->range_max && !e->d_range_vals && !e->d_range_keys) return FLIX_EINVAL;
+  if (e->n_update && (!e->d_update_keys || !e->d_update_vals)) return FLIX_EINVAL;
   return FLIX_OK;
 }
 
@@ -537,6 +747,13 @@ void destroy_all(flix_store* s) {
   dev_free(&s->ss.err);
   for (auto e : s->tm.pool) (void)hipEventDestroy(e);
   s->tm.pool.clear();
+  for (int i = 0; i < 2; ++i) {
+    if (s->ep[i]) {
+      free_slot(s->ep[i]);
+      delete s->ep[i];
+      s->ep[i] = nullptr;
+    }
+  }
 }
 
 // ---- persistent drain -------------------------------------------------------
@@ -816,6 +1033,14 @@ int flix_status(flix_store* s, void* stream) {
   HIP_TRY(hipMemcpyAsync(&de, &s->dctl->err, sizeof(u32), hipMemcpyDeviceToHost, S(stream)));
   HIP_TRY(hipMemsetAsync(&s->dctl->err, 0, sizeof(u32), S(stream)));
   HIP_TRY(hipStreamSynchronize(S(stream)));
+  for (int i = 0; i < 2; ++i) {
+    if (!s->ep[i]) continue;
+    u32 x = 0;
+    HIP_TRY(hipMemcpyAsync(&x, s->ep[i]->ss.err, sizeof(u32), hipMemcpyDeviceToHost, S(stream)));
+    HIP_TRY(hipMemsetAsync(s->ep[i]->ss.err, 0, sizeof(u32), S(stream)));
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    se |= x;
+  }
   if (v == 0 && (se != 0 || de != 0)) return FLIX_EINTERNAL;
   return (int)v;
 }
@@ -950,6 +1175,39 @@ int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_
 }
 
 const char* flix_last_error(void) { return g_last_error; }
+
+int flix_epoch_prepare(flix_store* s, uint32_t slot, const flix_epoch* e, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int rc = epoch_validate(s, slot, e);
+  if (rc) return rc;
+  if ((rc = ensure_slots(s))) return rc;
+  EpochSlot* es = s->ep[slot];
+  es->prepared = false;
+  hipStream_t st = S(stream);
+  if (s->kb == 32)
+    rc = s->rb == 4 ? epoch_prepare_rb<u32, 4>(es, e, st) : epoch_prepare_rb<u32, 8>(es, e, st);
+  else
+    rc = s->rb == 4 ? epoch_prepare_rb<u64, 4>(es, e, st) : epoch_prepare_rb<u64, 8>(es, e, st);
+  if (rc) return rc;
+  es->prepared = true;
+  es->n_lookup = e->n_lookup;
+  es->n_range = e->n_range;
+  es->n_update = e->n_update;
+  return FLIX_OK;
+}
+
+int flix_epoch_apply(flix_store* s, uint32_t slot, const flix_epoch* e, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int rc = epoch_validate(s, slot, e);
+  if (rc) return rc;
+  EpochSlot* es = s->ep[slot];
+  if (!es || !es->prepared || es->n_lookup != e->n_lookup || es->n_range != e->n_range ||
+      es->n_update != e->n_update)
+    return FLIX_EINVAL;
+  es->prepared = false;
+  hipStream_t st = S(stream);
+  return s->kb == 32 ? epoch_apply_t<u32>(s, es, e, st) : epoch_apply_t<u64>(s, es, e, st);
+}
 
 int flix_drain(flix_store* s, const flix_batch* h_batches, const flix_batch* d_batches,
                uint32_t nbatch, uint64_t* d_timestamps, void* stream) {

@@ -65,6 +65,27 @@ class FlixBatch(ctypes.Structure):
     ]
 
 
+class FlixEpoch(ctypes.Structure):
+    """One coalesced epoch (layout of flix_epoch in flix.h)."""
+    _fields_ = [
+        ("n_lookup", ctypes.c_uint64),
+        ("d_lookup_keys", ctypes.c_void_p),
+        ("d_lookup_vals", ctypes.c_void_p),
+        ("n_range", ctypes.c_uint64),
+        ("range_max", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("d_range_lo", ctypes.c_void_p),
+        ("d_range_hi", ctypes.c_void_p),
+        ("d_range_counts", ctypes.c_void_p),
+        ("d_range_keys", ctypes.c_void_p),
+        ("d_range_vals", ctypes.c_void_p),
+        ("n_update", ctypes.c_uint64),
+        ("d_update_keys", ctypes.c_void_p),
+        ("d_update_vals", ctypes.c_void_p),
+    ]
+
+
+EPOCH_SLOTS = 2
 OP_LOOKUP, OP_SUCCESSOR, OP_RANGE, OP_INSERT, OP_DELETE = 0, 1, 2, 3, 4
 OPS = {"lookup": OP_LOOKUP, "successor": OP_SUCCESSOR, "range": OP_RANGE,
        "insert": OP_INSERT, "delete": OP_DELETE}
@@ -106,6 +127,8 @@ def load_library(path: str = LIB_PATH):
         "flix_graph_destroy": (i32, [vp]),
         "flix_drain_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64)]),
         "flix_set_timing": (i32, [vp, i32]),
+        "flix_epoch_prepare": (i32, [vp, u32, ctypes.POINTER(FlixEpoch), vp]),
+        "flix_epoch_apply": (i32, [vp, u32, ctypes.POINTER(FlixEpoch), vp]),
         "flix_kernel_time": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(u64)]),
     }
@@ -320,6 +343,28 @@ class Store:
         self._chk(self.lib.flix_drain_info(self.h, ctypes.byref(g), ctypes.byref(hz)),
                   "flix_drain_info")
         return int(g.value), int(hz.value)
+
+    # -- epochs (serving form) -------------------------------------------------
+    def make_epoch(self, lookup_keys=None, lookup_vals=None, range_lo=None, range_hi=None,
+                   range_max: int = 0, range_counts=None, range_keys=None, range_vals=None,
+                   update_keys=None, update_vals=None, n_lookup=None, n_range=None,
+                   n_update=None):
+        """An epoch descriptor over device tensors.  Counts default to the
+        tensors' lengths; pass them to use a prefix of larger buffers."""
+        n = lambda t, c: (0 if t is None else t.numel()) if c is None else int(c)
+        return FlixEpoch(n(lookup_keys, n_lookup), _ptr(lookup_keys).value,
+                         _ptr(lookup_vals).value, n(range_lo, n_range), int(range_max), 0,
+                         _ptr(range_lo).value, _ptr(range_hi).value, _ptr(range_counts).value,
+                         _ptr(range_keys).value, _ptr(range_vals).value, n(update_keys, n_update),
+                         _ptr(update_keys).value, _ptr(update_vals).value)
+
+    def epoch_prepare(self, slot: int, ep: FlixEpoch, stream=None):
+        self._chk(self.lib.flix_epoch_prepare(self.h, slot, ctypes.byref(ep), _stream(stream)),
+                  "flix_epoch_prepare")
+
+    def epoch_apply(self, slot: int, ep: FlixEpoch, stream=None):
+        self._chk(self.lib.flix_epoch_apply(self.h, slot, ctypes.byref(ep), _stream(stream)),
+                  "flix_epoch_apply")
 
     def set_timing(self, on: bool):
         self._chk(self.lib.flix_set_timing(self.h, 1 if on else 0), "flix_set_timing")

@@ -51,23 +51,31 @@ def _fmix64(x: np.ndarray) -> np.ndarray:
 
 
 def _round_fn16(r: np.ndarray, k: int) -> np.ndarray:
-    t = (r ^ np.uint64(k)) & M32
-    t = (t * np.uint64(0x45D9F3B)) & M32
-    t ^= t >> np.uint64(16)
-    t = (t * np.uint64(0x45D9F3B)) & M32
-    t ^= t >> np.uint64(16)
-    return t & np.uint64(0xFFFF)
+    """Feistel round function on uint32 arrays (arithmetic mod 2^32)."""
+    t = r ^ np.uint32(k)
+    t *= np.uint32(0x45D9F3B)
+    t ^= t >> np.uint32(16)
+    t *= np.uint32(0x45D9F3B)
+    t ^= t >> np.uint32(16)
+    return t & np.uint32(0xFFFF)
 
 
 def perm32(counters, seed: int) -> np.ndarray:
-    """Keyed bijection of [0, 2^32): counters -> distinct uint32 keys."""
-    c = np.asarray(counters, dtype=np.uint64) & M32
-    left = c >> np.uint64(16)
-    right = c & np.uint64(0xFFFF)
-    for i in range(4):
-        k = _splitmix64_scalar(seed * 8 + i) & 0xFFFFFFFF
-        left, right = right, left ^ _round_fn16(right, k)
-    return ((left << np.uint64(16)) | right).astype(np.uint32)
+    """Keyed bijection of [0, 2^32): counters -> distinct uint32 keys.
+
+    Evaluated in cache-sized chunks with uint32 arithmetic."""
+    c = np.asarray(counters, dtype=np.uint64).reshape(-1)
+    out = np.empty(c.shape, np.uint32)
+    keys = [_splitmix64_scalar(seed * 8 + i) & 0xFFFFFFFF for i in range(4)]
+    chunk = 1 << 18
+    for s in range(0, c.size, chunk):
+        cc = (c[s:s + chunk] & M32).astype(np.uint32)
+        left = cc >> np.uint32(16)
+        right = cc & np.uint32(0xFFFF)
+        for k in keys:
+            left, right = right, left ^ _round_fn16(right, k)
+        out[s:s + chunk] = (left << np.uint32(16)) | right
+    return out.reshape(np.shape(counters))
 
 
 def perm64(counters, seed: int) -> np.ndarray:
@@ -275,3 +283,141 @@ class UpdateHeavy:
             rng.shuffle(dele)
         self.present = np.setdiff1d(self.present, dele, assume_unique=True)
         return ins, ins_v, dele
+
+
+class BatchStream:
+    """Mixed-batch stream for the batching form: u32 keys/values.
+
+    Bulk load ``n_keys`` distinct uniform keys, then ``nbatch`` batches whose
+    sizes are floor(2^U) with U uniform on [log2_min, log2_max] and whose
+    types are drawn lookup/successor/insert/delete with probabilities ``mix``.
+    Keys follow the read-path recipe: lookups are 90% bulk-loaded keys
+    (uniform with replacement) and 10% absent keys, successors are uniform,
+    inserts are new keys, deletes are bulk-loaded keys (uniform with
+    replacement; a key already deleted is a no-op).
+
+    Sizes and types are drawn up front; batch i is generated from its own
+    seed, so any batch can be regenerated alone (``batch(i)``).
+    """
+
+    OPS = ("lookup", "successor", "insert", "delete")
+
+    def __init__(self, n_keys: int = 1 << 26, nbatch: int = 4096, log2_min: float = 8.0,
+                 log2_max: float = 20.0, mix=(0.7, 0.1, 0.1, 0.1), seed_round: int = 0):
+        self.cfg = 3
+        self.kb = 32
+        self.n_keys = n_keys
+        self.nbatch = nbatch
+        self.seed_round = seed_round
+        self.ks = KeySpace(32, seed_for(self.cfg, seed_round, STREAM_KEYS))
+        self.build_keys = self.ks.build(n_keys)
+        self.build_vals = values_for(self.build_keys, seed_for(self.cfg, seed_round, STREAM_VALS), 32)
+        rng = np.random.default_rng(seed_for(self.cfg, seed_round, STREAM_OTHER))
+        u = rng.uniform(log2_min, log2_max, nbatch)
+        self.sizes = np.floor(np.exp2(u)).astype(np.int64)
+        self.ops = rng.choice(4, nbatch, p=np.asarray(mix, dtype=np.float64))
+        ins = np.where(self.ops == 2, self.sizes, 0)
+        self.fresh_base = n_keys + np.concatenate([[0], np.cumsum(ins)[:-1]])
+        absent = np.where(self.ops == 0, self.sizes - (self.sizes * 9) // 10, 0)
+        self.absent_base = np.concatenate([[0], np.cumsum(absent)[:-1]])
+
+    @property
+    def total_ops(self) -> int:
+        return int(self.sizes.sum())
+
+    def _rng(self, i: int, stream: int) -> np.random.Generator:
+        return np.random.default_rng([seed_for(self.cfg, self.seed_round, stream), int(i)])
+
+    def batch(self, i: int):
+        """(op name, keys, values or None) of batch i."""
+        op = self.OPS[int(self.ops[i])]
+        m = int(self.sizes[i])
+        rng = self._rng(i, STREAM_ORDER)
+        seed = self.ks.seed
+        if op == "lookup":
+            n_hit = (m * 9) // 10
+            top = np.uint64(1 << 31)
+            c = top + np.uint64(self.absent_base[i]) + np.arange(m - n_hit, dtype=np.uint64)
+            keys = np.concatenate([self.build_keys[rng.integers(0, self.n_keys, n_hit)],
+                                   perm32(c, seed)])
+            rng.shuffle(keys)
+            return op, keys, None
+        if op == "successor":
+            return op, rng.integers(0, 1 << 32, m, dtype=np.uint64).astype(np.uint32), None
+        if op == "insert":
+            c = np.uint64(self.fresh_base[i]) + np.arange(m, dtype=np.uint64)
+            keys = perm32(c, seed)
+            rng.shuffle(keys)
+            vals = values_for(keys, seed_for(self.cfg, self.seed_round, STREAM_VALS) ^ (int(i) + 1 << 12),
+                              32)
+            return op, keys, vals
+        return op, self.build_keys[rng.integers(0, self.n_keys, m)], None
+
+
+class ServingWorkload:
+    """Open-loop serving workload: u64 keys/values.
+
+    Bulk load ``n_keys`` distinct keys.  ``n_req`` requests, each of
+    floor(4096^U) operations (U uniform on [0, 1), so 1..4096, log-uniform),
+    every operation drawn lookup / range / insert / delete with ``mix``:
+    lookups hit a bulk-loaded key 90% of the time (else an absent key), a
+    range starts at a uniformly chosen bulk-loaded key and ends at the key
+    L-1 ranks later in the bulk-loaded order (L uniform on ``range_len``),
+    inserts write new keys, deletes remove bulk-loaded keys (with replacement).
+
+    Operations are flat arrays (``ops``: 0 lookup, 1 range, 2 insert,
+    3 delete; ``keys``; ``aux``: range hi or insert value) cut by
+    ``offsets``.  ``gaps`` are unit-rate exponential inter-arrival gaps;
+    ``arrivals(rate)`` scales them to a request rate.
+    """
+
+    LOOKUP, RANGE, INSERT, DELETE = 0, 1, 2, 3
+
+    def __init__(self, n_keys: int = 1 << 25, n_req: int = 20000, mix=(0.8, 0.05, 0.075, 0.075),
+                 range_len=(8, 64), max_ops: int = 4096, seed_round: int = 0):
+        self.cfg = 4
+        self.kb = 64
+        self.n_keys = n_keys
+        self.n_req = n_req
+        self.range_max = int(range_len[1])
+        ks = KeySpace(64, seed_for(self.cfg, seed_round, STREAM_KEYS))
+        self.build_keys = ks.build(n_keys)
+        self.build_vals = values_for(self.build_keys, seed_for(self.cfg, seed_round, STREAM_VALS), 64)
+        sorted_build = np.sort(self.build_keys)
+        rng = np.random.default_rng(seed_for(self.cfg, seed_round, STREAM_ORDER))
+        u = rng.random(n_req)
+        self.sizes = np.maximum(np.floor(np.power(float(max_ops), u)), 1).astype(np.int64)
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)])
+        total = int(self.offsets[-1])
+        self.ops = rng.choice(4, total, p=np.asarray(mix, dtype=np.float64)).astype(np.uint8)
+        keys = np.zeros(total, dtype=np.uint64)
+        aux = np.zeros(total, dtype=np.uint64)
+        il = np.nonzero(self.ops == self.LOOKUP)[0]
+        hit = rng.random(il.size) < 0.9
+        keys[il[hit]] = self.build_keys[rng.integers(0, n_keys, int(hit.sum()))]
+        keys[il[~hit]] = ks.absent(int((~hit).sum()))
+        ir = np.nonzero(self.ops == self.RANGE)[0]
+        rank = rng.integers(0, n_keys, ir.size)
+        ln = rng.integers(int(range_len[0]), int(range_len[1]) + 1, ir.size)
+        keys[ir] = sorted_build[rank]
+        aux[ir] = sorted_build[np.minimum(rank + ln - 1, n_keys - 1)]
+        ii = np.nonzero(self.ops == self.INSERT)[0]
+        keys[ii] = ks.fresh(ii.size)
+        aux[ii] = values_for(keys[ii], seed_for(self.cfg, seed_round + 1, STREAM_VALS), 64)
+        idl = np.nonzero(self.ops == self.DELETE)[0]
+        keys[idl] = self.build_keys[rng.integers(0, n_keys, idl.size)]
+        self.keys, self.aux = keys, aux
+        self.range_ordinal = np.full(total, -1, dtype=np.int64)
+        self.range_ordinal[ir] = np.arange(ir.size)
+        self.n_ranges = ir.size
+        self.gaps = np.random.default_rng(seed_for(self.cfg, seed_round, STREAM_OTHER)).exponential(
+            1.0, n_req)
+
+    @property
+    def total_ops(self) -> int:
+        return int(self.offsets[-1])
+
+    def arrivals(self, rate: float) -> np.ndarray:
+        """Arrival times (s) at ``rate`` requests per second, first at 0."""
+        t = np.cumsum(self.gaps) / float(rate)
+        return t - t[0]

@@ -1,0 +1,183 @@
+"""The serving form on the GPU: the epoch calls against the oracle's epoch
+order (reads before updates, last update of a key wins, all-ones deletes),
+two slots prepared and applied on two streams, the request loop with the
+GPU backend against a replay of its admitted epochs, and results of probe
+requests identical alone and in the mix."""
+import numpy as np
+import pytest
+
+from gpu_helpers import assert_same_contents, ktype, log, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+
+
+def _rand_epoch(rng, kb, universe, nl, nr, nu, p_del=0.3):
+    tomb = (1 << kb) - 1
+    kt = ktype(kb)
+    lk = rng.choice(universe, nl).astype(kt)
+    lo = rng.choice(universe, nr).astype(kt)
+    span = np.uint64(1 << (kb - 10))
+    hi = np.minimum(lo.astype(np.uint64) + span, np.uint64(tomb)).astype(kt)
+    uk = rng.choice(universe, nu).astype(kt)
+    uv = rng.integers(0, tomb, nu, dtype=np.uint64).astype(kt)
+    uv[rng.random(nu) < p_del] = kt(tomb)
+    return lk, lo, hi, uk, uv
+
+
+@pytest.mark.parametrize("kb,cap,rb", [(32, 64, 8), (64, 128, 8), (64, 32, 4)])
+def test_epochs_two_slots_vs_oracle(kb, cap, rb):
+    import torch
+    from oracle.oracle import Oracle
+    from paper_2604_16725_amd.flix import Store
+    rng = np.random.default_rng(kb * 1000 + cap + rb)
+    kt = ktype(kb)
+    tomb = (1 << kb) - 1
+    universe = rng.integers(0, tomb, 1 << 14, dtype=np.uint64).astype(kt)
+    universe[:4] = [0, 1, tomb - 1, tomb]
+    base = np.unique(rng.choice(universe, 6000))
+    bv = rng.integers(0, tomb, base.size, dtype=np.uint64).astype(kt)
+    st = Store(key_bits=kb, capacity=cap, lanes=16, radix_bits=rb, max_batch=1 << 14)
+    st.bulk_load(to_dev(base), to_dev(bv))
+    o = Oracle(kb)
+    o.bulk_load(base, bv)
+    RM = 8
+    s_prep, s_apply = torch.cuda.Stream(), torch.cuda.Stream()
+    ev_prep = [torch.cuda.Event(), torch.cuda.Event()]
+    ev_done = [torch.cuda.Event(), torch.cuda.Event()]
+    pending = []
+    sizes = [(0, 0, 0), (300, 0, 0), (0, 50, 0), (0, 0, 700), (1000, 40, 900),
+             (5000, 200, 4000), (1, 1, 1), (2000, 0, 3000), (0, 0, 1 << 14), (800, 100, 50)]
+    for t, (nl, nr, nu) in enumerate(sizes):
+        slot = t % 2
+        if t >= 2:
+            ev_done[slot].synchronize()
+        lk, lo, hi, uk, uv = _rand_epoch(rng, kb, universe, nl, nr, nu)
+        with torch.cuda.stream(s_prep):
+            d = [to_dev(a) if a.size else None for a in (lk, lo, hi, uk, uv)]
+            out_v = torch.zeros(max(nl, 1), dtype=st.dtype, device="cuda")
+            rc = torch.zeros(max(nr, 1), dtype=torch.int32, device="cuda")
+            rv = torch.zeros(max(nr * RM, 1), dtype=st.dtype, device="cuda")
+        s_prep.synchronize()
+        ep = st.make_epoch(lookup_keys=d[0], lookup_vals=out_v, n_lookup=nl, range_lo=d[1],
+                           range_hi=d[2], range_max=RM, range_counts=rc, range_vals=rv,
+                           n_range=nr, update_keys=d[3], update_vals=d[4], n_update=nu)
+        st.epoch_prepare(slot, ep, stream=s_prep)
+        ev_prep[slot].record(s_prep)
+        s_apply.wait_event(ev_prep[slot])
+        st.epoch_apply(slot, ep, stream=s_apply)
+        ev_done[slot].record(s_apply)
+        elv, erc, erv = o.apply_epoch(lk, lo, hi, RM, uk, uv)
+        pending.append((t, out_v, rc, rv, elv, erc, erv, d, ep))
+        if t % 2 == 1 or t == len(sizes) - 1:
+            s_apply.synchronize()
+            for (tt, ov, c, v, elv, erc, erv, _, _) in pending:
+                n_l, n_r = elv.size, erc.size
+                assert np.array_equal(to_host(ov, kb)[:n_l], elv), f"epoch {tt} lookups"
+                gc = c.cpu().numpy().view(np.uint32)[:n_r]
+                assert np.array_equal(gc, erc), f"epoch {tt} range counts"
+                m = np.arange(RM)[None, :] < np.minimum(erc, RM)[:, None]
+                gv = to_host(v, kb)[:n_r * RM].reshape(n_r, RM)
+                assert np.array_equal(gv[m], erv[m]), f"epoch {tt} range values"
+            pending.clear()
+            assert st.status() == 0
+            assert_same_contents(st, o, kb, f"after epoch {t}")
+    # apply without a matching prepare is rejected
+    from paper_2604_16725_amd.flix import FlixError
+    with pytest.raises(FlixError):
+        st.epoch_apply(0, st.make_epoch())
+    st.close()
+
+
+def _serving_case(n_keys, n_req, rate, coalesce, max_ops=4096):
+    from oracle.oracle import Oracle
+    from paper_2604_16725_amd import serve
+    from paper_2604_16725_amd.flix import Store
+    from paper_2604_16725_amd.workloads import ServingWorkload
+    wl = ServingWorkload(n_keys=n_keys, n_req=n_req, max_ops=max_ops)
+    st = Store(key_bits=64, capacity=128, lanes=16, radix_bits=8, max_batch=1 << 16)
+    st.bulk_load(to_dev(wl.build_keys), to_dev(wl.build_vals))
+    be = serve.GpuBackend(st, 1 << 16, wl.range_max)
+    tomb = (1 << 64) - 1
+    run = serve.Engine(be, 1 << 16, 64 << 30, coalesce=coalesce).run(
+        wl, wl.arrivals(rate), tomb, 8, wl.range_max)
+    assert st.status() == 0
+    log(f"served {run['completed']} requests in {len(run['epochs'])} epochs, "
+        f"{serve.summary(run, wl, rate)}")
+    assert run["completed"] == n_req
+    o = Oracle(64)
+    o.bulk_load(wl.build_keys, wl.build_vals)
+    res = run["results"]
+    RM = wl.range_max
+    for e, ids in enumerate(run["epochs"]):
+        ep = serve.EpochLists(wl, ids, tomb)
+        lv, rc, rv = o.apply_epoch(ep.lookup_keys, ep.range_lo, ep.range_hi, RM,
+                                   ep.update_keys, ep.update_vals)
+        assert np.array_equal(res.lookup[ep.flat_lookup], lv), f"epoch {e} lookups"
+        if ep.range_ord.size:
+            assert np.array_equal(res.range_count[ep.range_ord], rc), f"epoch {e} counts"
+            m = np.arange(RM)[None, :] < np.minimum(rc, RM)[:, None]
+            assert np.array_equal(res.range_vals[ep.range_ord][m], rv[m]), f"epoch {e} values"
+    assert_same_contents(st, o, 64, "after the run")
+    st.close()
+    return wl, run
+
+
+def test_serving_loop_vs_replay():
+    _serving_case(n_keys=1 << 16, n_req=400, rate=5e3, coalesce=True)
+
+
+def test_plain_form_vs_replay():
+    _serving_case(n_keys=1 << 16, n_req=120, rate=5e3, coalesce=False)
+
+
+def test_serving_full_size_store_vs_replay():
+    _serving_case(n_keys=1 << 25, n_req=300, rate=2e4, coalesce=True)
+
+
+def test_probe_requests_same_alone_and_in_mix():
+    from paper_2604_16725_amd import serve
+    from paper_2604_16725_amd.flix import Store
+    from paper_2604_16725_amd.workloads import ServingWorkload
+    wl = ServingWorkload(n_keys=1 << 16, n_req=300, max_ops=1024, seed_round=1)
+    upd = wl.ops >= serve.INSERT
+    written = np.sort(wl.keys[upd])
+    probes = []
+    for i in range(wl.n_req):
+        a, b = int(wl.offsets[i]), int(wl.offsets[i + 1])
+        ops = wl.ops[a:b]
+        if np.any(ops >= serve.INSERT):
+            continue
+        lo = wl.keys[a:b]
+        hi = np.where(ops == serve.RANGE, wl.aux[a:b], lo)
+        if np.all(np.searchsorted(written, lo, "left") == np.searchsorted(written, hi, "right")):
+            probes.append(i)
+    assert len(probes) >= 10
+    tomb = (1 << 64) - 1
+    st = Store(key_bits=64, capacity=64, lanes=16, radix_bits=8, max_batch=1 << 16)
+    st.bulk_load(to_dev(wl.build_keys), to_dev(wl.build_vals))
+    be = serve.GpuBackend(st, 1 << 16, wl.range_max)
+    mix = serve.Engine(be, 1 << 16, 64 << 30).run(wl, wl.arrivals(2e4), tomb, 8,
+                                                  wl.range_max)["results"]
+    assert st.status() == 0
+    for i in probes[:10]:
+        st.bulk_load(to_dev(wl.build_keys), to_dev(wl.build_vals))
+        ep = serve.EpochLists(wl, [i], tomb)
+        h = be.submit(0, ep)
+        be.buf[0]["ev_done"].synchronize()
+        lv, rc, rv = be.results(h)
+        assert np.array_equal(mix.lookup[ep.flat_lookup], lv), f"probe {i} lookups"
+        if ep.range_ord.size:
+            assert np.array_equal(mix.range_count[ep.range_ord], rc), f"probe {i} counts"
+            RM = wl.range_max
+            m = np.arange(RM)[None, :] < np.minimum(rc, RM)[:, None]
+            got = mix.range_vals[ep.range_ord]
+            assert np.array_equal(got[m], rv.reshape(-1, RM)[m]), f"probe {i} values"
+    st.close()

@@ -333,3 +333,43 @@ def _reserved(cls):
     o = cls(32)
     o.bulk_load([5], [1])
     assert o.insert([9], [_mx(32)]) == -1
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_epoch_order_vs_sequential_replay(kb):
+    """An epoch's reads see the map before the epoch; its updates equal
+    applying them one at a time in array order (all-ones value = delete).
+    Pinned against a plain dict replayed op by op."""
+    tomb = (1 << kb) - 1
+    dt = np.uint32 if kb == 32 else np.uint64
+    for seed in range(300):
+        rng = random.Random(seed * 7 + kb)
+        universe = [0, 1, 2, 5, 9, 17, 40, tomb - 1, tomb] + [rng.randrange(0, 64) for _ in range(8)]
+        base = {k: rng.randrange(0, tomb) for k in rng.sample(universe, 6)}
+        o = Oracle(kb)
+        ks = sorted(base)
+        o.bulk_load(np.array(ks, dtype=dt), np.array([base[k] for k in ks], dtype=dt))
+        look = [rng.choice(universe) for _ in range(6)]
+        lo = [rng.choice(universe) for _ in range(3)]
+        hi = [min(x + rng.randrange(0, 20), tomb) for x in lo]
+        uk = [rng.choice(universe) for _ in range(rng.randrange(0, 12))]
+        uv = [tomb if rng.random() < 0.4 else rng.randrange(0, tomb) for _ in uk]
+        lv, rc, rv = o.apply_epoch(np.array(look, dtype=dt), np.array(lo, dtype=dt),
+                                   np.array(hi, dtype=dt), 4, np.array(uk, dtype=dt),
+                                   np.array(uv, dtype=dt))
+        # reads: the map before the epoch
+        for q, got in zip(look, lv.tolist()):
+            assert got == base.get(q, tomb)
+        for i, (a, b) in enumerate(zip(lo, hi)):
+            inside = sorted(k for k in base if a <= k <= b)
+            assert rc[i] == len(inside)
+            assert rv[i, :min(len(inside), 4)].tolist() == [base[k] for k in inside[:4]]
+        # updates: sequential replay
+        ref = dict(base)
+        for k, v in zip(uk, uv):
+            if v == tomb:
+                ref.pop(k, None)
+            else:
+                ref[k] = v
+        gk, gv = o.dump()
+        assert gk.tolist() == sorted(ref) and gv.tolist() == [ref[k] for k in sorted(ref)]

@@ -74,3 +74,35 @@ def test_update_heavy_rounds_small():
     s = np.sort(ins)
     assert np.sum(np.diff(s) == 1) >= ins.size - 8  # 8 runs of consecutive keys
     assert np.unique(dele).size == dele.size
+
+
+def test_batch_stream_small():
+    s = w.BatchStream(n_keys=1 << 14, nbatch=400, log2_max=12.0)
+    assert s.sizes.min() >= 256 and s.sizes.max() <= 1 << 12
+    frac = np.bincount(s.ops, minlength=4) / s.nbatch
+    assert abs(frac[0] - 0.7) < 0.08 and all(abs(f - 0.1) < 0.05 for f in frac[1:])
+    build = set(s.build_keys.tolist())
+    seen_new = set()
+    for i in range(s.nbatch):
+        op, k, v = s.batch(i)
+        assert k.dtype == np.uint32 and k.size == s.sizes[i]
+        op2, k2, v2 = s.batch(i)          # each batch regenerates alone, identically
+        assert op2 == op and np.array_equal(k, k2)
+        if op == "insert":
+            ks = set(k.tolist())
+            assert len(ks) == k.size and not (ks & build) and not (ks & seen_new)
+            seen_new |= ks
+            assert np.all(v != np.uint32(0xFFFFFFFF))
+        elif op == "lookup":
+            hits = np.isin(k, s.build_keys).sum()
+            assert hits == (k.size * 9) // 10
+        elif op == "delete":
+            assert np.all(np.isin(k, s.build_keys))
+
+
+def test_tuned_config_fallback(tmp_path):
+    from paper_2604_16725_amd import autotune
+    assert autotune.tuned_config(str(tmp_path / "missing.json")) == autotune.FALLBACK
+    p = tmp_path / "t.json"
+    p.write_text('{"best": {"capacity": 64, "lanes": 32, "radix_bits": 4, "Mops_s": 1.0}}')
+    assert autotune.tuned_config(str(p)) == {"capacity": 64, "lanes": 32, "radix_bits": 4}
