@@ -50,6 +50,10 @@ def parse():
     ap.add_argument("--no-batching", action="store_true",
                     help="skip the mixed-batch stream (persistent drain vs plain launches)")
     ap.add_argument("--nbatch", type=int, default=4096, help="batches in the mixed stream")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving comparison (request loop vs plain per-request form)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-keys-log2", type=int, default=25)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first copy a MiB-sized device buffer 4 times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -141,7 +145,8 @@ def batching_compare(args):
     from the same bulk load; their outputs and final contents must agree."""
     import torch
     from paper_2604_16725_amd import autotune, flix
-    from paper_2604_16725_amd.batching import DeviceStream, PersistentRun, run_plain, summarize
+    from paper_2604_16725_amd.batching import (DeviceStream, PersistentRun, pool_bytes_for,
+                                               run_plain, summarize)
     from paper_2604_16725_amd.workloads import BatchStream
 
     cfg = autotune.tuned_config()
@@ -154,7 +159,8 @@ def batching_compare(args):
     res = {}
     with torch.cuda.stream(cs):
         st = flix.Store(key_bits=32, capacity=cfg["capacity"], lanes=cfg["lanes"],
-                        radix_bits=cfg["radix_bits"], max_batch=1 << 20)
+                        radix_bits=cfg["radix_bits"], max_batch=1 << 20,
+                        pool_bytes=pool_bytes_for(stream, cfg["capacity"]))
         outs_p, outs_g = ds.outputs(), ds.outputs()
         plain = None
         for rep in range(2):
@@ -195,6 +201,57 @@ def batching_compare(args):
     if not res["results_identical"]:
         raise RuntimeError("persistent and plain results differ")
     return res
+
+
+def serving_compare(args):
+    """Open-loop Poisson arrivals on a 2^serve_keys_log2 u64 store: the
+    coalescing request loop (two pipelined epoch slots) against the plain
+    form (every request its own epoch, one at a time), at 0.2..0.95 of the
+    plain form's saturation rate, measured first with all requests queued
+    at time 0.  Each run starts from the same bulk load."""
+    import torch
+    from paper_2604_16725_amd import flix, serve
+    from paper_2604_16725_amd.workloads import ServingWorkload
+
+    t0 = time.time()
+    wl = ServingWorkload(n_keys=1 << args.serve_keys_log2, n_req=args.serve_requests)
+    log(f"[bench] serving workload: {wl.n_req} requests, {wl.total_ops} ops "
+        f"({time.time() - t0:.1f}s)")
+    E = 1 << 16
+    budget = 64 << 30
+    tomb = (1 << 64) - 1
+    st = flix.Store(key_bits=64, capacity=128, lanes=16, radix_bits=8, max_batch=E)
+    bk = torch.from_numpy(wl.build_keys.view(np.int64)).cuda()
+    bv = torch.from_numpy(wl.build_vals.view(np.int64)).cuda()
+    be = serve.GpuBackend(st, E, wl.range_max)
+
+    def one(rate, coalesce):
+        st.bulk_load(bk, bv)
+        torch.cuda.synchronize()
+        arr = np.zeros(wl.n_req) if rate is None else wl.arrivals(rate)
+        run = serve.Engine(be, E, budget, coalesce=coalesce).run(wl, arr, tomb, 8, wl.range_max)
+        if st.status() != 0:
+            raise RuntimeError("device error in the serving runs")
+        return run
+
+    one(None, False)                               # warm-up (slot scratch, kernels)
+    sat = one(None, False)
+    sat_rate = sat["completed"] / sat["span_s"]
+    log(f"[bench] plain form saturation: {sat_rate:.0f} requests/s")
+    rows = []
+    for frac in (0.2, 0.4, 0.6, 0.8, 0.95):
+        rate = frac * sat_rate
+        row = {"load": frac, "rate_req_s": round(rate, 1)}
+        for name, coalesce in (("plain", False), ("serving", True)):
+            row[name] = serve.summary(one(rate, coalesce), wl)
+        log(f"[bench] load {frac}: plain {row['plain']}, serving {row['serving']}")
+        rows.append(row)
+    st.close()
+    return {"workload": f"{wl.n_req} requests per rate, 1..4096 ops each (log-uniform), "
+                        f"80/5/7.5/7.5 lookup/range/insert/delete, ranges of 8..64 keys, "
+                        f"2^{args.serve_keys_log2} u64 keys, Poisson arrivals",
+            "epoch_capacity_ops": E, "budget_bytes": budget,
+            "plain_saturation_req_s": round(sat_rate, 1), "rates": rows}
 
 
 def main():
@@ -356,6 +413,7 @@ def main():
 
     st.close()
     batching = None if args.no_batching else batching_compare(args)
+    serving = None if args.no_serving else serving_compare(args)
 
     # -- CPU baseline: the oracle on a bounded sample -----------------------
     cpu = None
@@ -403,6 +461,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_fam.items()},
         "breakdown": breakdown,
         "batching": batching,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

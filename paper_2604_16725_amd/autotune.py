@@ -41,13 +41,14 @@ def tuned_config(path: str = DEFAULT_PATH) -> dict:
 
 
 def sweep(n_keys: int = 1 << 26, nbatch: int = 4096, prefix: int = 512, reps: int = 2,
-          grid: dict = GRID, with_plain: bool = False, log=print):
+          grid: dict = GRID, with_plain: bool = False, log2_max: float = 20.0, log=print):
     import torch
     from . import flix
-    from .batching import DeviceStream, PersistentRun, run_plain, summarize
+    from .batching import DeviceStream, PersistentRun, pool_bytes_for, run_plain, summarize
     from .workloads import BatchStream
 
-    stream = BatchStream(n_keys=n_keys, nbatch=nbatch)
+    stream = BatchStream(n_keys=n_keys, nbatch=nbatch, log2_max=log2_max)
+    max_batch = 1 << int(np.ceil(log2_max))
     ds = DeviceStream(stream, limit=prefix)
     log(f"[autotune] {ds.n} batches, {ds.total_ops} ops resident")
     ref = None
@@ -55,7 +56,8 @@ def sweep(n_keys: int = 1 << 26, nbatch: int = 4096, prefix: int = 512, reps: in
     cs = torch.cuda.Stream()
     with torch.cuda.stream(cs):
         for cap, gl, rb in itertools.product(grid["capacity"], grid["lanes"], grid["radix_bits"]):
-            st = flix.Store(key_bits=32, capacity=cap, lanes=gl, radix_bits=rb, max_batch=1 << 20)
+            st = flix.Store(key_bits=32, capacity=cap, lanes=gl, radix_bits=rb, max_batch=max_batch,
+                            pool_bytes=pool_bytes_for(stream, cap, max_batch, limit=prefix))
             outs = ds.outputs()
             run = PersistentRun(st, ds, outs, cs)
             best_wall, best_svc = None, None
@@ -64,8 +66,9 @@ def sweep(n_keys: int = 1 << 26, nbatch: int = 4096, prefix: int = 512, reps: in
                 wall, svc = run.run()
                 if best_wall is None or wall < best_wall:
                     best_wall, best_svc = wall, svc
-            if st.status() != 0:
-                raise RuntimeError(f"device error at capacity {cap} lanes {gl} radix {rb}")
+            rc = st.status()
+            if rc != 0:
+                raise RuntimeError(f"device status {rc} at capacity {cap} lanes {gl} radix {rb}")
             if ref is None:
                 ref = (outs[0].clone(), outs[1].clone())
             elif not (torch.equal(ref[0], outs[0]) and torch.equal(ref[1], outs[1])):

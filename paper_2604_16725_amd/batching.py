@@ -18,6 +18,18 @@ from . import flix
 OP_CODE = {"lookup": 0, "successor": 1, "range": 2, "insert": 3, "delete": 4}
 
 
+def pool_bytes_for(stream, capacity: int, max_batch: int = 1 << 20, key_bytes: int = 4,
+                   limit: int | None = None) -> int:
+    """Node pool for a store that bulk-loads the stream's keys and takes all of
+    its inserts: twice the nodes the keys fill at the bulk-load fill (half the
+    capacity), plus the per-call headroom the library reserves by default."""
+    n = stream.nbatch if limit is None else min(limit, stream.nbatch)
+    ins = int(stream.sizes[:n][stream.ops[:n] == 2].sum())
+    f = capacity // 2
+    nodes = 2 * (-(-(stream.n_keys + ins) // f)) + 2 * (-(-max_batch // f)) + 64
+    return nodes * (capacity * 2 * key_bytes + 16)
+
+
 class DeviceStream:
     """The first ``limit`` batches of a workload stream, resident in HBM.
 

@@ -14,8 +14,8 @@ the store as it was before the epoch, then the epoch's updates take effect
 with the last update of a key winning.  The plain form runs every request
 alone as its own epoch, one after the other.
 
-The engine talks to a backend (``GpuBackend`` here; the tests add a fake one
-over the oracle with a simulated clock), so its coalescing, admission and
+The engine talks to a backend (``GpuBackend`` here; the tests add a CPU one
+with a simulated clock), so its coalescing, admission and
 accounting logic runs on any machine.
 """
 from __future__ import annotations

@@ -72,8 +72,8 @@ def _run(n_keys, nbatch, prefix, log2_max, cap, lanes, rb):
         log("persistent form (graph), two replays from the same bulk load")
         run = PersistentRun(st, ds, outs_g, cs)
         for rep in range(2):
-            outs_g[0].fill_(0)
-            outs_g[1].fill_(0)
+            outs_g[0].fill_(-1)
+            outs_g[1].fill_(-1)
             st.bulk_load(ds.build_keys, ds.build_vals)
             wall, svc = run.run()
             assert st.status() == 0
@@ -100,7 +100,7 @@ def test_stream_full_size_prefix_vs_oracle():
 
 def test_autotune_small_grid(tmp_path):
     from paper_2604_16725_amd import autotune
-    res = autotune.sweep(n_keys=1 << 16, nbatch=24, prefix=24, reps=1,
+    res = autotune.sweep(n_keys=1 << 16, nbatch=24, prefix=24, reps=1, log2_max=14.0,
                          grid={"capacity": (32, 128), "lanes": (16, 64), "radix_bits": (4, 8)},
                          with_plain=True, log=log)
     assert len(res["points"]) == 8
