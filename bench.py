@@ -104,15 +104,25 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     fam["read_apply"] = look + succ + rng
 
     ins = wl["insert_keys"]
+    bi = np.searchsorted(mkba, ins, side="left")
     ti = touched(ins)
-    per_bucket = np.bincount(np.searchsorted(mkba, ins, side="left"), minlength=nb)[ti]
+    per_bucket = np.bincount(bi, minlength=nb)[ti]
     node = size_of[ti] * (kbytes + vbytes)
+    # slot of the smallest new key in its node: items before it keep their
+    # slots, so only the suffix from there on is written (insert), and the
+    # same suffix moves back when those keys are deleted again
+    mins = np.full(nb, np.iinfo(np.uint64).max, dtype=np.uint64)
+    np.minimum.at(mins, bi, ins.astype(np.uint64))
+    fill = int(size_of[0])
+    first = np.searchsorted(build_sorted, mins[ti].astype(build_sorted.dtype)) - ti * fill
+    first = np.clip(first, 0, size_of[ti])
     fam["slices"] = 2 * (nb * kbytes + m * kbytes + ti.size * (16 + 4 + 16)) + m * vbytes
     fam["insert_apply"] = float(ti.size * 16 + m * (kbytes + vbytes) + node.sum()
-                                + (node + per_bucket * (kbytes + vbytes)).sum() + ti.size * 16)
+                                + ((size_of[ti] + per_bucket - first) * (kbytes + vbytes)).sum()
+                                + ti.size * 16)
     node_after = (size_of[ti] + per_bucket) * (kbytes + vbytes)
     fam["delete_apply"] = float(ti.size * 16 + m * kbytes + node_after.sum()
-                                + node.sum() + ti.size * 16)
+                                + ((size_of[ti] - first) * (kbytes + vbytes)).sum() + ti.size * 16)
     return fam
 
 

@@ -12,10 +12,8 @@
 //      registers (KPL keys per lane, 16-byte loads) and resolve each key of the
 //      slice with ballots: lookup match, successor / range lower and upper
 //      bounds inside the node; the result position goes to LDS;
-//      a lookup or successor answered there is written by the lane that
-//      holds the matching key, which loads the value right away;
-//   5. phase B: one lane per remaining key (ranges and the slow path) loads
-//      the value(s) and writes the outputs, all of them in flight at once.
+//   5. phase B: one lane per key loads the value(s) and writes the outputs,
+//      all keys of the share in flight at once.
 // Keys whose answer lies outside the single staged node (chained buckets, a
 // successor or range running past the node's end) take the global-memory path
 // of flix_read.hpp.
@@ -28,7 +26,6 @@ namespace flix {
 
 constexpr u32 kPosMiss = 0xFFFFu;   // lookup miss inside a single-node bucket
 constexpr u32 kPosSlow = 0xFFFEu;   // resolve on the global-memory path
-constexpr u32 kPosDone = 0xFFFDu;   // answered and written in phase A
 
 // Cooperative merge-path cut for the two diagonals d[0], d[1] of one
 // workgroup (NT == 256: threads 0..127 search d[0], 128..255 search d[1]).
@@ -220,7 +217,6 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
           for (u32 j = s + gl; j < e; j += GL) s_pos[j] = (lb << 16) | kPosSlow;
           continue;
         }
-        const u64 nbase = (u64)(b0 + lb) * a.cap;
         for (u32 j = s; j < e; ++j) {
           const K x = s_q[j];
           if (op == kOpLookup) {
@@ -230,29 +226,10 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
               if (gl * KPL + k < size && kv[u].k[k] == x) hit = k;
             u64 bal = wave_ballot(hit >= 0) & gmask;
             if (bal == 0) {
-              if (gl == 0) a.out_v[s_idx[j]] = key_max<K>();
+              if (gl == 0) s_pos[j] = (lb << 16) | kPosMiss;
             } else if (hit >= 0) {
-              a.out_v[s_idx[j]] = a.nvals[nbase + gl * KPL + (u32)hit];
+              s_pos[j] = (lb << 16) | (gl * KPL + (u32)hit);
             }
-            if (gl == 0) s_pos[j] = kPosDone;
-          } else if (op == kOpSuccessor) {
-            // lower bound of x inside the node; the lane holding it answers
-            u32 lt = 0;
-#pragma unroll
-            for (int k = 0; k < KPL; ++k)
-              lt += (u32)__popcll(wave_ballot(gl * KPL + k < size && kv[u].k[k] < x) & gmask);
-            if (lt < size) {
-              if (lt / KPL == gl) {
-                K rk = kv[u].k[0];
-#pragma unroll
-                for (int k = 1; k < KPL; ++k)
-                  if (lt % KPL == (u32)k) rk = kv[u].k[k];
-                const u32 orig = s_idx[j];
-                a.out_k[orig] = rk;
-                a.out_v[orig] = a.nvals[nbase + lt];
-              }
-            }
-            if (gl == 0) s_pos[j] = lt < size ? kPosDone : ((lb << 16) | kPosSlow);
           } else {
             // lower bound of x (and upper bound of hi for ranges)
             u32 lt = 0, le = 0;
@@ -265,7 +242,9 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
             }
             if (gl == 0) {
               u32 code;
-              {
+              if (op == kOpSuccessor) {
+                code = lt < size ? lt : kPosSlow;
+              } else {
                 if (x > hi) {
                   code = 0;
                   s_cnt[j] = 0;
@@ -285,13 +264,12 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
   }
   __syncthreads();
 
-  // Phase B: one lane per key not answered in phase A.
+  // Phase B: one lane per key.
   const K NF = key_max<K>();
   for (u32 j = tid; j < nq; j += NT) {
     const u32 code = s_pos[j];
     const u32 lb = code >> 16;
     const u32 pos = code & 0xFFFFu;
-    if (pos == kPosDone) continue;
     u32 b = b0 + lb;
     const u32 orig = s_idx[j];
     const K x = s_q[j];

@@ -412,8 +412,21 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       u32 j2 = (hX.next == kNil) ? w.e : upper_bound_idx<K>(a.skeys, j, w.e, (K)hX.fence);
       if (j2 - j > a.chunk) j2 = j + a.chunk;
       const u32 sa = hX.size;
-      // stage the chunk (loads first), keeping the last item of each
-      // equal-key run, then node X
+      // One round trip for the node and the chunk: the node's first 4*GL
+      // items are loaded into registers before the chunk is staged (keeping
+      // the last item of each equal-key run), then written to LDS.
+      const K* nsk = a.nkeys + (u64)X * a.cap;
+      const K* nsv = a.nvals + (u64)X * a.cap;
+      const u32 first = sa < 4u * GL ? sa : 4u * GL;
+      K nk[4], nv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const u32 i = r * GL + g.lane;
+        if (i < first) {
+          nk[r] = fresh ? ld_fresh(nsk + i) : nsk[i];
+          nv[r] = fresh ? ld_fresh(nsv + i) : nsv[i];
+        }
+      }
       u32 tb = 0;
       for (u32 base = j; base < j2; base += GL) {
         u32 idx = base + g.lane;
@@ -432,8 +445,17 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         }
         tb += g.count(live);
       }
-      stage_items<K, GL>(ak, av, a.nkeys + (u64)X * a.cap, a.nvals + (u64)X * a.cap, sa, g.lane,
-                         fresh);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const u32 i = r * GL + g.lane;
+        if (i < first) {
+          ak[i] = nk[r];
+          av[i] = nv[r];
+        }
+      }
+      if (sa > first)
+        stage_items<K, GL>(ak + first, av + first, nsk + first, nsv + first, sa - first, g.lane,
+                           fresh);
       wave_lds_sync();
       if (tb == 0) {   // only shadowed duplicates in this chunk
         j = j2;
@@ -483,7 +505,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
           pos = i - (drop_before + g.rank(drop)) + p;
         }
         drop_before += g.count(drop);
-        if (i < sa && !drop) {
+        if (i < sa && !drop && !(k == 1 && pos == i)) {   // an item that keeps its slot stays
           u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
           u32 node = pc == 0 ? X : a.free_ids[base_id - pc];
           u32 slot = pos - piece_start(pc, c, k);
@@ -626,6 +648,13 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       }
       // the node's slice goes to LDS when it fits, else it is searched in place
       const bool slice_lds = touched && (j2 - j) <= a.chunk;
+      // One round trip for the slice's first 4*GL keys and the node's first
+      // 4*GL items (X's data has not been written by this kernel).
+      const bool stage_x = touched || join;
+      const K* xsk = a.nkeys + (u64)X * a.cap;
+      const K* xsv = a.nvals + (u64)X * a.cap;
+      const u32 first = stage_x ? (sx < 4u * GL ? sx : 4u * GL) : 0u;
+      K nk[4], nv[4];
       if (slice_lds) {
         for (u32 i0 = j; i0 < j2; i0 += 4 * GL) {
           K kk[4];
@@ -634,19 +663,47 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
             u32 i = i0 + r * GL + g.lane;
             if (i < j2) kk[r] = a.skeys[i];
           }
+          if (i0 == j) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const u32 i = r * GL + g.lane;
+              if (i < first) {
+                nk[r] = xsk[i];
+                nv[r] = xsv[i];
+              }
+            }
+          }
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             u32 i = i0 + r * GL + g.lane;
             if (i < j2) bk[i - j] = kk[r];
           }
         }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const u32 i = r * GL + g.lane;
+          if (i < first) {
+            nk[r] = xsk[i];
+            nv[r] = xsv[i];
+          }
+        }
       }
-      if (touched || join) {
-        // stage X (X's data has not been written by this kernel)
-        stage_items<K, GL>(ak, av, a.nkeys + (u64)X * a.cap, a.nvals + (u64)X * a.cap, sx,
-                           g.lane, false);
+      if (stage_x) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const u32 i = r * GL + g.lane;
+          if (i < first) {
+            ak[i] = nk[r];
+            av[i] = nv[r];
+          }
+        }
+        if (sx > first)
+          stage_items<K, GL>(ak + first, av + first, xsk + first, xsv + first, sx - first, g.lane,
+                             false);
         wave_lds_sync();
       }
+      u32 first_gone = sx;   // slot of the first removed item: earlier slots stay
       if (touched) {
         // mark + compact in LDS (survivors only move left)
         u32 kept = 0;
@@ -665,6 +722,8 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
               keep = !(p < j2 && a.skeys[p] == kk);
             }
           }
+          const u64 gone = g.ballot(i < sx && !keep);
+          if (gone && first_gone == sx) first_gone = i0 + (u32)__builtin_ctzll(gone >> g.gbase);
           u32 dst = kept + g.rank(keep);
           kept += g.count(keep);
           if (keep) {
@@ -696,7 +755,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         ++freed;
       } else {
         if (touched) {
-          for (u32 i = g.lane; i < sx; i += GL) {
+          for (u32 i = first_gone + g.lane; i < sx; i += GL) {
             a.nkeys[(u64)X * a.cap + i] = ak[i];
             a.nvals[(u64)X * a.cap + i] = av[i];
           }

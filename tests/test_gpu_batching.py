@@ -93,6 +93,19 @@ def test_stream_reduced_radix4_lanes64():
     _run(n_keys=1 << 17, nbatch=64, prefix=None, log2_max=13.0, cap=32, lanes=64, rb=4)
 
 
+@pytest.mark.parametrize("cap,lanes,rb", [(c, g, r) for c in (32, 128) for g in (16, 64)
+                                           for r in (4, 8)])
+def test_stream_small_store_grid_vs_oracle(cap, lanes, rb):
+    _run(n_keys=1 << 16, nbatch=24, prefix=None, log2_max=14.0, cap=cap, lanes=lanes, rb=rb)
+
+
+@pytest.mark.parametrize("cap,lanes,rb", [(32, 16, 4), (128, 16, 4), (256, 32, 8)])
+def test_stream_batches_larger_than_store_vs_oracle(cap, lanes, rb):
+    """Batches of up to 2^20 operations on a 2^16-key store: long chains,
+    multi-piece splits, chunked merges and emptied buckets."""
+    _run(n_keys=1 << 16, nbatch=24, prefix=None, log2_max=20.0, cap=cap, lanes=lanes, rb=rb)
+
+
 def test_stream_full_size_prefix_vs_oracle():
     n = int(os.environ.get("FLIX_STREAM_PREFIX", "64"))
     _run(n_keys=1 << 26, nbatch=4096, prefix=n, log2_max=20.0, cap=128, lanes=16, rb=8)
