@@ -194,7 +194,7 @@ typedef struct {
   void* reserved2;        /* must be NULL */
 } flix_batch;             /* 64 bytes */
 
-/* Execute nbatch batches in order in one persistent kernel launch on `stream`.
+/* Execute nbatch (<= 2^24) batches in order in one persistent kernel launch on `stream`.
  * h_batches (host) is validated like the per-batch calls; d_batches is the
  * same array in device memory, read by the kernel.  d_timestamps (device,
  * nbatch+1 entries, may be NULL) receives the device wall clock at the start
@@ -206,7 +206,9 @@ int flix_drain(flix_store* s, const flix_batch* h_batches, const flix_batch* d_b
 /* Capture one flix_drain launch into an instantiated hipGraph (returned as an
  * opaque hipGraphExec_t in *graph_exec).  Replays read the descriptor array in
  * device memory again, so the caller may rewrite it between replays (same
- * nbatch).  `stream` must not be the null stream.  Synchronizes. */
+ * nbatch), and they read the store's current layout, so bulk loads between
+ * replays are allowed (ordered on the stream like any other call).  The store
+ * must outlive the graph.  `stream` must not be the null stream.  Synchronizes. */
 int flix_drain_graph(flix_store* s, const flix_batch* h_batches, const flix_batch* d_batches,
                      uint32_t nbatch, uint64_t* d_timestamps, void** graph_exec, void* stream);
 int flix_graph_launch(void* graph_exec, void* stream);

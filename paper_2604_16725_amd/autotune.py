@@ -56,6 +56,7 @@ def sweep(n_keys: int = 1 << 26, nbatch: int = 4096, prefix: int = 512, reps: in
     cs = torch.cuda.Stream()
     with torch.cuda.stream(cs):
         for cap, gl, rb in itertools.product(grid["capacity"], grid["lanes"], grid["radix_bits"]):
+            log(f"[autotune] start cap {cap} lanes {gl} radix {rb}")
             st = flix.Store(key_bits=32, capacity=cap, lanes=gl, radix_bits=rb, max_batch=max_batch,
                             pool_bytes=pool_bytes_for(stream, cap, max_batch, limit=prefix))
             outs = ds.outputs()

@@ -91,6 +91,7 @@ struct flix_store {
   DrainCtl* dctl = nullptr;
   int drain_grid = 0;                 // co-resident workgroups of the drain kernel
   size_t drain_shm = 0;
+  StoreLayout* d_layout = nullptr;    // layout record read by drains (graph replays)
   // epoch slots (allocated by the first epoch call)
   EpochSlot* ep[2] = {nullptr, nullptr};
 };
@@ -322,6 +323,8 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   a.hi = (const K*)hi;
   a.counts = counts;
   a.maxpq = maxpq;
+  a.pool = s->pool;
+  a.err = &s->ctl->status;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
   hipEvent_t b;
   tm_begin(s, st, &b);
@@ -620,8 +623,25 @@ int epoch_validate(flix_store* s, uint32_t slot, const flix_epoch* e) {
 }
 
 // ---- bulk load --------------------------------------------------------------
+// Rewrite the device layout record that drains read (after every change of
+// the directory or the pool).  Synchronous: the store is idle at this point.
+int publish_layout(flix_store* s) {
+  if (!s->d_layout) return FLIX_OK;
+  StoreLayout L{};
+  L.mkba = s->mkba;
+  L.hdr = s->hdr;
+  L.nkeys = s->nkeys;
+  L.nvals = s->nvals;
+  L.bnodes = s->bnodes;
+  L.free_ids = s->free_ids;
+  L.nb = s->nb;
+  L.pool = s->pool;
+  HIP_TRY(hipMemcpy(s->d_layout, &L, sizeof(L), hipMemcpyHostToDevice));
+  return FLIX_OK;
+}
+
 template <typename K>
-int bulk_load_t(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t st) {
+int bulk_load_body(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t st) {
   if (n > 0xFFFFFFF0ull) return FLIX_EINVAL;
   // reserved value check before anything changes
   if (n) {
@@ -714,6 +734,16 @@ int bulk_load_t(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t 
   return FLIX_OK;
 }
 
+// Bulk load, then the layout record, also after a failure part way (the
+// directory or the pool may have been reallocated already).
+template <typename K>
+int bulk_load_t(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t st) {
+  const int rc = bulk_load_body<K>(s, keys, vals, n, st);
+  (void)hipStreamSynchronize(st);
+  const int rp = publish_layout(s);
+  return rc ? rc : rp;
+}
+
 int check_args(flix_store* s, u64 n, std::initializer_list<const void*> ptrs) {
   if (!s) return FLIX_ESTATE;
   if (n == 0) return 1;  // no-op
@@ -744,6 +774,7 @@ void destroy_all(flix_store* s) {
   dev_free(&s->d_status_cl);
   dev_free(&s->d_hist);
   dev_free(&s->dctl);
+  dev_free(&s->d_layout);
   dev_free(&s->ss.err);
   for (auto e : s->tm.pool) (void)hipEventDestroy(e);
   s->tm.pool.clear();
@@ -781,15 +812,8 @@ int drain_launch_t(flix_store* s, const DrainBatch* d_batches, u32 nbatch,
   DrainArgs<K> a;
   a.batches = d_batches;
   a.nbatch = nbatch;
-  a.mkba = (const K*)s->mkba;
-  a.nb = s->nb;
-  a.hdr = s->hdr;
-  a.nkeys = (K*)s->nkeys;
-  a.nvals = (K*)s->nvals;
-  a.bnodes = s->bnodes;
-  a.free_ids = s->free_ids;
+  a.layout = s->d_layout;
   a.cap = s->cap;
-  a.pool = s->pool;
   a.ctl = s->ctl;
   a.bk[0] = (K*)s->bk[0];
   a.bk[1] = (K*)s->bk[1];
@@ -841,6 +865,8 @@ int drain_launch(flix_store* s, const DrainBatch* b, u32 nb, unsigned long long*
 }
 
 int drain_validate(flix_store* s, const flix_batch* h, u32 nbatch) {
+  // look-back epochs of one drain must fit the 30-bit epoch field
+  if (nbatch > (1u << 24)) return FLIX_EINVAL;
   for (u32 i = 0; i < nbatch; ++i) {
     const flix_batch& b = h[i];
     if (b.op > FLIX_OP_DELETE) return FLIX_EINVAL;
@@ -922,7 +948,8 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   if ((rc = dev_alloc(&s->d_status, s->d_status_words * 8)) ||
       (rc = dev_alloc(&s->d_status_cl, s->d_cluster_words * 8)) ||
       (rc = dev_alloc(&s->d_hist, 2 * 2048 * sizeof(u32))) ||
-      (rc = dev_alloc(&s->dctl, sizeof(DrainCtl)))) {
+      (rc = dev_alloc(&s->dctl, sizeof(DrainCtl))) ||
+      (rc = dev_alloc(&s->d_layout, sizeof(StoreLayout)))) {
     destroy_all(s);
     delete s;
     return rc;

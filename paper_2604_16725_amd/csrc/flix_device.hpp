@@ -36,6 +36,11 @@ struct alignas(64) Ctl {
   u64 pad1[3];
 };
 
+// Sticky status codes written by kernels (the negated C ABI error codes).
+constexpr u32 kErrInval = 0xFFFFFFFFu;     // -1
+constexpr u32 kErrNomem = 0xFFFFFFFEu;     // -2
+constexpr u32 kErrInternal = 0xFFFFFFFBu;  // -5: internal consistency check failed
+
 template <typename K>
 __device__ __forceinline__ K key_max() { return ~K(0); }
 

@@ -45,20 +45,29 @@ struct DrainCtl {
   u32 pad[12];
 };
 
+// The store's layout as the kernels see it.  Bulk loads reallocate the
+// directory and the pool, so a drain captured in a graph must not hold these
+// pointers: it reads this record, which every bulk load rewrites, when each
+// replay starts.
+struct alignas(16) StoreLayout {
+  const void* mkba;
+  NodeHdr* hdr;
+  void* nkeys;
+  void* nvals;
+  u32* bnodes;
+  u32* free_ids;
+  u32 nb;
+  u32 pool;
+  u32 pad[2];
+};
+
 template <typename K>
 struct DrainArgs {
   const DrainBatch* batches;
   u32 nbatch;
-  // store
-  const K* mkba;
-  u32 nb;
-  NodeHdr* hdr;
-  K* nkeys;
-  K* nvals;
-  u32* bnodes;
-  u32* free_ids;
+  // store: layout read from device memory at kernel start
+  const StoreLayout* layout;
   u32 cap;
-  u32 pool;
   Ctl* ctl;
   // scratch
   K* bk[2];
@@ -77,8 +86,12 @@ struct DrainArgs {
 };
 
 // Grid-wide barrier for a co-resident grid.  Bounded: a workgroup that waits
-// too long records an error and continues, so the kernel always ends.
-__device__ __forceinline__ void grid_sync(DrainCtl* c, u32 nblocks) {
+// too long records an error.  Returns true (in every thread of the
+// workgroup) once the grid has failed, a barrier wait or a sort look-back
+// having given up: the caller must then leave the kernel, since later phases
+// would read buffers that earlier phases did not finish.
+__device__ __forceinline__ bool grid_sync(DrainCtl* c, u32 nblocks) {
+  __shared__ u32 s_abort;
   __syncthreads();
   if (threadIdx.x == 0) {
     const u32 gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -101,8 +114,10 @@ __device__ __forceinline__ void grid_sync(DrainCtl* c, u32 nblocks) {
       }
     }
     __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    s_abort = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
   }
   __syncthreads();
+  return s_abort != 0;
 }
 
 template <typename K, int RB, int GL, int KPL>
@@ -138,10 +153,15 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
   const u32 G = gridDim.x;
   const u32 blk = blockIdx.x;
   DrainCtl* dc = a.dctl;
+  const StoreLayout L = *a.layout;
+  const K* const mkba = (const K*)L.mkba;
+  K* const nkeys = (K*)L.nkeys;
+  K* const nvals = (K*)L.nvals;
 
   // Epochs: every workgroup reads the base before anyone advances it (the
-  // advance happens after the final barrier).  Near wrap-around the status
-  // words are cleared first.
+  // advance happens after the first barrier, by the most this drain can use,
+  // so a drain that stops early never leaves epochs to be reused).  Near
+  // wrap-around the status words are cleared first.
   if (threadIdx.x == 0) s_epoch = __hip_atomic_load(&dc->epoch, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
@@ -157,7 +177,11 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
   if (blk == 0)
     for (int i = threadIdx.x; i < 2 * P * R; i += 256) a.hist[i] = 0;
   if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[0] = wall_clock64();
-  grid_sync(dc, G);
+  const u32 epoch_end = epoch + need_epochs;
+  const bool failed0 = grid_sync(dc, G);
+  if (blk == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&dc->epoch, epoch_end, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (failed0) return;
 
   u32 nz = 0;   // batches processed so far: selects the histogram slot
   for (u32 bi = 0; bi < a.nbatch; ++bi) {
@@ -183,7 +207,7 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
     // ---- histogram
     radix_hist_part<K, RB>((const K*)d.keys, n, hist, blk, G,
                            *reinterpret_cast<HistSmem<K, RB>*>(smem));
-    grid_sync(dc, G);
+    if (grid_sync(dc, G)) return;
     // ---- onesweep passes
     const u32 ntiles = (n + kSortTile - 1) / kSortTile;
     for (int p = 0; p < P; ++p) {
@@ -227,7 +251,7 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
           onesweep_tile<K, u32, RB, kSortNT, kSortIPT, kPayIndex>(
               pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayIndex>*>(smem));
       }
-      grid_sync(dc, G);
+      if (grid_sync(dc, G)) return;
     }
     const int r = ((P - 1) & 1) ? 1 : 0;
     // the other histogram slot was last used by the previous batch and is
@@ -240,11 +264,11 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
       ra.skeys = a.bk[r];
       ra.sidx = (const u32*)a.bp[r];
       ra.m = n;
-      ra.mkba = a.mkba;
-      ra.nb = a.nb;
-      ra.hdr = a.hdr;
-      ra.nkeys = a.nkeys;
-      ra.nvals = a.nvals;
+      ra.mkba = mkba;
+      ra.nb = L.nb;
+      ra.hdr = L.hdr;
+      ra.nkeys = nkeys;
+      ra.nvals = nvals;
       ra.cap = a.cap;
       ra.share = SR;
       ra.out_v = (K*)d.out_v;
@@ -252,7 +276,9 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
       ra.hi = (const K*)d.aux;
       ra.counts = d.counts;
       ra.maxpq = d.maxpq;
-      const u32 nshares = (u32)(((u64)n + a.nb + SR - 1) / SR);
+      ra.pool = L.pool;
+      ra.err = &a.ctl->status;
+      const u32 nshares = (u32)(((u64)n + L.nb + SR - 1) / SR);
       for (u32 vb = blk; vb < nshares; vb += G) {
         read_share<K, 256, SR, GL, KPL, U>(ra, (int)d.op, vb,
                                           *reinterpret_cast<ReadSmem<K, SR, 256>*>(smem));
@@ -263,35 +289,35 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
       sa.skeys = a.bk[r];
       sa.svals = d.op == kOpInsert ? (const K*)a.bp[r] : nullptr;
       sa.m = n;
-      sa.mkba = a.mkba;
-      sa.nb = a.nb;
-      sa.hdr = a.hdr;
-      sa.bnodes = a.bnodes;
+      sa.mkba = mkba;
+      sa.nb = L.nb;
+      sa.hdr = L.hdr;
+      sa.bnodes = L.bnodes;
       sa.cap = a.cap;
       sa.share = SS;
       sa.work = a.work;
       sa.ctl = a.ctl;
-      const u32 nshares = (u32)(((u64)n + a.nb + SS - 1) / SS);
+      const u32 nshares = (u32)(((u64)n + L.nb + SS - 1) / SS);
       for (u32 vb = blk; vb < nshares; vb += G) {
         if (d.op == kOpInsert)
           slices_share<K, 256, SS, true>(sa, vb, *reinterpret_cast<SliceSmem<K, SS, 256>*>(smem));
         else
           slices_share<K, 256, SS, false>(sa, vb, *reinterpret_cast<SliceSmem<K, SS, 256>*>(smem));
       }
-      grid_sync(dc, G);
+      if (grid_sync(dc, G)) return;
       UpdArgs<K> ua;
-      ua.mkba = a.mkba;
+      ua.mkba = mkba;
       ua.skeys = a.bk[r];
       ua.svals = d.op == kOpInsert ? (const K*)a.bp[r] : nullptr;
       ua.m = n;
-      ua.hdr = a.hdr;
-      ua.nkeys = a.nkeys;
-      ua.nvals = a.nvals;
-      ua.bnodes = a.bnodes;
-      ua.free_ids = a.free_ids;
+      ua.hdr = L.hdr;
+      ua.nkeys = nkeys;
+      ua.nvals = nvals;
+      ua.bnodes = L.bnodes;
+      ua.free_ids = L.free_ids;
       ua.cap = a.cap;
       ua.chunk = a.chunk;
-      ua.pool = a.pool;
+      ua.pool = L.pool;
       ua.work = a.work;
       ua.ctl = a.ctl;
       ua.status = &a.ctl->status;
@@ -302,12 +328,9 @@ __global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
       else
         delete_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_counter);
     }
-    grid_sync(dc, G);
+    if (grid_sync(dc, G)) return;
     if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[bi + 1] = wall_clock64();
   }
-  // every workgroup has read the epoch base long ago (first barrier)
-  if (blk == 0 && threadIdx.x == 0)
-    __hip_atomic_store(&dc->epoch, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace flix

@@ -127,6 +127,13 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
   d[1] = d[0] + a.share < total ? d[0] + a.share : total;
   coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
   const u32 q0 = s_cut[0], q1 = s_cut[1];
+  // Cuts of a sorted batch are ordered; anything else (an unsorted batch)
+  // is reported instead of indexing past the share.
+  if (q1 < q0 || q1 > a.m || d[0] < q0 || d[1] < q1 || d[0] - q0 > d[1] - q1 ||
+      d[1] - q1 > a.nb) {
+    if (tid == 0) atomicCAS(a.err, 0u, kErrInternal);
+    return;
+  }
   const u32 b0 = (u32)(d[0] - q0), b1 = (u32)(d[1] - q1);
   const u32 nq = q1 - q0;
   if (nq == 0) return;
@@ -294,7 +301,14 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
     }
     // Global-memory path: walk the chain to the node holding x.
     NodeHdr h;
-    u32 node = locate_node(a.hdr, b, (u64)x, &h);
+    u32 node = locate_node(a.hdr, a.pool, b, (u64)x, &h);
+    if (node == kBadLink) {
+      atomicCAS(a.err, 0u, kErrInternal);
+      if (op == kOpRange) a.counts[orig] = 0;
+      else a.out_v[orig] = NF;
+      if (op == kOpSuccessor) a.out_k[orig] = NF;
+      continue;
+    }
     const K* keys = a.nkeys + (u64)node * a.cap;
     u32 p = lower_bound_idx<K>(keys, 0u, h.size, x);
     if (op == kOpLookup) {
@@ -306,8 +320,10 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
         rv = a.nvals[(u64)node * a.cap + p];
       } else {
         NodeHdr g;
-        u32 nn = next_nonempty(a.hdr, a.nb, &b, h, &g);
-        if (nn != kNil) {
+        u32 nn = next_nonempty(a.hdr, a.nb, a.pool, &b, h, &g);
+        if (nn == kBadLink) {
+          atomicCAS(a.err, 0u, kErrInternal);
+        } else if (nn != kNil) {
           rk = a.nkeys[(u64)nn * a.cap];
           rv = a.nvals[(u64)nn * a.cap];
         }
@@ -329,7 +345,11 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
           }
           if (ub < h.size) break;
           NodeHdr g;
-          u32 nn = next_nonempty(a.hdr, a.nb, &b, h, &g);
+          u32 nn = next_nonempty(a.hdr, a.nb, a.pool, &b, h, &g);
+          if (nn == kBadLink) {
+            atomicCAS(a.err, 0u, kErrInternal);
+            break;
+          }
           if (nn == kNil) break;
           node = nn;
           h = g;

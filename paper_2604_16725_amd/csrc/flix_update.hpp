@@ -21,10 +21,6 @@
 
 namespace flix {
 
-constexpr u32 kErrInval = 0xFFFFFFFFu;   // -1
-constexpr u32 kErrNomem = 0xFFFFFFFEu;   // -2
-constexpr u32 kErrInternal = 0xFFFFFFFBu;  // -5: internal consistency check failed
-
 // Work item: bucket and its slice [s, e) of the sorted batch, plus the head
 // node's size with kSingleNode set when the bucket is that one node.
 struct alignas(16) WorkItem {
@@ -91,6 +87,13 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
     s_part[3] = (u32)(d1 - q1);
   }
   __syncthreads();
+  // cuts of a sorted batch are ordered; report anything else instead of
+  // indexing past the share
+  if (s_part[1] < s_part[0] || s_part[3] < s_part[2] || s_part[3] > a.nb) {
+    if (tid == 0) atomicCAS(&a.ctl->status, 0u, kErrInternal);
+    __syncthreads();
+    return;
+  }
   const u32 q0 = s_part[0], q1 = s_part[1];
   const u32 b0 = s_part[2], b1 = s_part[3];
   const u32 nq = q1 - q0;
@@ -399,7 +402,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       if (hX.next != kNil) {   // chain: walk to the node holding skeys[j]
         const K first = a.skeys[j];
         while ((u64)first > hX.fence) {
-          if (hX.next == kNil) { broken = true; break; }
+          if (hX.next >= a.pool) { broken = true; break; }   // end of chain, or a bad link
           X = hX.next;
           hX = ld_hdr(a.hdr + X, fresh);
         }
@@ -508,6 +511,10 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         if (i < sa && !drop && !(k == 1 && pos == i)) {   // an item that keeps its slot stays
           u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
           u32 node = pc == 0 ? X : a.free_ids[base_id - pc];
+          if (node >= a.pool) {   // a free-stack entry outside the pool: never expected
+            atomicCAS(a.status, 0u, kErrInternal);
+            continue;
+          }
           u32 slot = pos - piece_start(pc, c, k);
           a.nkeys[(u64)node * a.cap + slot] = kk;
           a.nvals[(u64)node * a.cap + slot] = vv;
@@ -533,6 +540,10 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         if (jj < tb) {
           u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
           u32 node = pc == 0 ? X : a.free_ids[base_id - pc];
+          if (node >= a.pool) {
+            atomicCAS(a.status, 0u, kErrInternal);
+            continue;
+          }
           u32 slot = pos - piece_start(pc, c, k);
           a.nkeys[(u64)node * a.cap + slot] = kk;
           a.nvals[(u64)node * a.cap + slot] = vv;
@@ -548,6 +559,10 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       } else {
         for (u32 p = g.lane; p < k; p += GL) {
           u32 node = p == 0 ? X : a.free_ids[base_id - p];
+          if (node >= a.pool) {
+            atomicCAS(a.status, 0u, kErrInternal);
+            continue;
+          }
           u32 sz = piece_start(p + 1, c, k) - piece_start(p, c, k);
           a.hdr[node].size = sz;
           a.hdr[node].next = (p + 1 < k) ? a.free_ids[base_id - (p + 1)] : hX.next;
@@ -750,7 +765,8 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         p_fence_known = true;
         if (g.lane == 0) {
           u32 pos = atomicAdd(&a.ctl->free_top, 1u);
-          a.free_ids[pos] = X;
+          if (pos < a.pool) a.free_ids[pos] = X;
+          else atomicCAS(a.status, 0u, kErrInternal);   // more frees than nodes: never expected
         }
         ++freed;
       } else {
@@ -774,6 +790,10 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       if (nxt == kNil) break;
       const bool more = j < w.e || (p_is_head && hP.size == 0) || (p_dirty && hP.size <= f);
       if (!more) break;
+      if (nxt >= a.pool) {   // a link outside the pool: never expected
+        if (g.lane == 0) atomicCAS(a.status, 0u, kErrInternal);
+        break;
+      }
       X = nxt;
       hX = a.hdr[X];
       x_fence_known = true;

@@ -162,3 +162,36 @@ def test_drain_graph_replays_with_eager_work_between():
         torch.cuda.synchronize()
         assert_same_contents(s, o, kb, f"after replay {rep}")
     graph.close()
+
+
+def test_drain_graph_captured_before_bulk_loads_that_grow_the_store():
+    """A graph captured on a freshly created (empty) store keeps working after
+    bulk loads that reallocate the directory and the pool: replays read the
+    store's current layout, not the one seen at capture."""
+    import torch
+    from oracle.oracle import Oracle
+    from paper_2604_16725_amd.flix import Store
+    kb = 32
+    rng = np.random.default_rng(17)
+    universe = np.unique(rng.integers(0, 1 << 32, 60000, dtype=np.uint64).astype(np.uint32))
+    s = Store(key_bits=kb, capacity=32, lanes=16, radix_bits=4, max_batch=4096)
+    stream = torch.cuda.Stream()
+    q = _queue(rng, kb, universe, 8, 4096)
+    with torch.cuda.stream(stream):
+        graph = s.drain_graph(q, stream=stream)   # captured on the empty store
+    for rep, nbuild in enumerate((20000, 4000, 30000)):
+        build = rng.choice(universe, nbuild, replace=False)
+        s.bulk_load(to_dev(build), to_dev(build))
+        o = Oracle(kb)
+        o.bulk_load(build, build)
+        if rep:
+            q = _queue(rng, kb, universe, 8, 4096)
+            graph.update(q)
+        torch.cuda.synchronize()
+        graph.launch(stream)
+        stream.synchronize()
+        assert s.status() == 0
+        _oracle_apply_and_check(o, q, kb, f"replay {rep} after a bulk load of {nbuild}")
+        assert_same_contents(s, o, kb, f"replay {rep}")
+    graph.close()
+    s.close()
