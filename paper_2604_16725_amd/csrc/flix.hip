@@ -1060,6 +1060,11 @@ int flix_status(flix_store* s, void* stream) {
   HIP_TRY(hipMemcpyAsync(&de, &s->dctl->err, sizeof(u32), hipMemcpyDeviceToHost, S(stream)));
   HIP_TRY(hipMemsetAsync(&s->dctl->err, 0, sizeof(u32), S(stream)));
   HIP_TRY(hipStreamSynchronize(S(stream)));
+  if (de & 1u) {
+    // a drain stopped part way: its barrier counters are left mid-count
+    HIP_TRY(hipMemset(&s->dctl->top_count, 0, sizeof(u32)));
+    HIP_TRY(hipMemset(&s->dctl->grp[0][0], 0, sizeof(s->dctl->grp)));
+  }
   for (int i = 0; i < 2; ++i) {
     if (!s->ep[i]) continue;
     u32 x = 0;

@@ -37,12 +37,18 @@ struct alignas(16) DrainBatch {
   void* reserved2;
 };
 
+// Arrival groups of the grid barrier: workgroup b arrives on counter b % 8,
+// which matches the round-robin placement of workgroups on the 8 XCDs, so no
+// counter takes more than an eighth of the arrivals.
+constexpr u32 kBarGroups = 8;
+
 struct DrainCtl {
-  u32 bar_count;     // arrivals at the current grid barrier
   u32 bar_gen;       // barrier generation
   u32 epoch;         // last look-back epoch used by a drain
-  u32 err;           // sticky: 1 barrier wait gave up, 2 look-back gave up
-  u32 pad[12];
+  u32 err;           // sticky: 1 barrier wait or look-back gave up, 4 bad descriptor
+  u32 top_count;     // groups complete at the current barrier
+  u32 pad0[28];
+  u32 grp[kBarGroups][32];   // arrivals per group, one 128-byte line each
 };
 
 // The store's layout as the kernels see it.  Bulk loads reallocate the
@@ -85,35 +91,54 @@ struct DrainArgs {
   u32 max_batch;
 };
 
-// Grid-wide barrier for a co-resident grid.  Bounded: a workgroup that waits
-// too long records an error.  Returns true (in every thread of the
-// workgroup) once the grid has failed, a barrier wait or a sort look-back
-// having given up: the caller must then leave the kernel, since later phases
-// would read buffers that earlier phases did not finish.
+// Grid-wide barrier for a co-resident grid.  Each workgroup publishes its
+// writes (agent-scope release fence: the L2 of its XCD is written back),
+// arrives on its group counter; the last arrival of a group arrives on the
+// top counter, and the last group flips the generation.  Waiters poll the
+// generation with relaxed loads and invalidate their caches once, after the
+// flip (an acquire load per poll would invalidate the L2 on every poll).
+// Bounded: a workgroup that waits too long records an error.  Returns true
+// (in every thread of the workgroup) once the grid has failed, a barrier wait
+// or a sort look-back having given up: the caller must then leave the kernel,
+// since later phases would read buffers that earlier phases did not finish.
 __device__ __forceinline__ bool grid_sync(DrainCtl* c, u32 nblocks) {
   __shared__ u32 s_abort;
   __syncthreads();
   if (threadIdx.x == 0) {
+    const u32 g = blockIdx.x % kBarGroups;
+    const u32 members = (nblocks - g + kBarGroups - 1) / kBarGroups;
+    const u32 ngroups = nblocks < kBarGroups ? nblocks : kBarGroups;
     const u32 gen = __hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);   // this workgroup's writes before arriving
-    const u32 arrived = atomicAdd(&c->bar_count, 1u) + 1u;
-    if (arrived == nblocks) {
-      __hip_atomic_store(&c->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // this workgroup's writes
+    bool flipped = false;
+    const u32 a = __hip_atomic_fetch_add(&c->grp[g][0], 1u, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (a == members) {
+      __hip_atomic_store(&c->grp[g][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");   // the group's writes, onward
+      const u32 t = __hip_atomic_fetch_add(&c->top_count, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      if (t == ngroups) {
+        __hip_atomic_store(&c->top_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        __hip_atomic_store(&c->bar_gen, gen + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        flipped = true;
+      }
+    }
+    if (!flipped) {
       // Bounded wait; once any barrier has failed (the grid was not fully
       // resident) no later barrier waits, so the kernel ends promptly.
       u32 polls = 0;
-      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+      while (__hip_atomic_load(&c->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
         if (__hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u) break;
-        if (++polls > (1u << 20)) {
+        if (++polls > (1u << 22)) {
           atomicOr(&c->err, 1u);
           break;
         }
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(1);
       }
     }
-    __atomic_thread_fence(__ATOMIC_ACQUIRE);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // everyone's writes
     s_abort = __hip_atomic_load(&c->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1u;
   }
   __syncthreads();
