@@ -178,6 +178,7 @@ def batching_compare(args):
             wall, svc = run_plain(st, ds, outs_p, events=(rep == 0))
             if rep == 0:
                 plain = summarize(wall, svc, ds.total_ops)
+                svc_plain = svc
             else:
                 plain["Mops_s"] = round(ds.total_ops / wall / 1e6, 1)
                 plain["wall_ms"] = round(wall * 1e3, 3)
@@ -193,18 +194,30 @@ def batching_compare(args):
             cur = summarize(wall, svc, ds.total_ops)
             if pers is None or cur["Mops_s"] > pers["Mops_s"]:
                 pers = cur
+                svc_pers = svc
         if st.status() != 0:
             raise RuntimeError("device error in the persistent stream")
         dump_g = st.dump()
         log(f"[bench] persistent: {pers}")
         same = (torch.equal(outs_p[0], outs_g[0]) and torch.equal(outs_p[1], outs_g[1])
                 and torch.equal(dump_p[0], dump_g[0]) and torch.equal(dump_p[1], dump_g[1]))
+        # mean service time per batch-size band (both forms, same batches)
+        bands = {}
+        lg = np.log2(ds.sizes)
+        for lo_, hi_ in ((8, 11), (11, 14), (14, 17), (17, 20.01)):
+            m_ = (lg >= lo_) & (lg < hi_)
+            if m_.any():
+                bands[f"2^{lo_}..2^{int(hi_)}"] = {
+                    "batches": int(m_.sum()),
+                    "plain_mean_us": round(float(svc_plain[m_].mean()) * 1e6, 1),
+                    "persistent_mean_us": round(float(svc_pers[m_].mean()) * 1e6, 1)}
         res = {"workload": f"{ds.n} mixed batches, sizes floor(2^U) U~U[8,20], 70/10/10/10 "
                            f"lookup/successor/insert/delete, 2^{args.keys_log2} u32 keys",
                "ops": ds.total_ops, "store": cfg, "drain_workgroups": st.drain_info()[0],
                "plain": plain, "persistent_graph": pers,
                "speedup_Mops": round(pers["Mops_s"] / plain["Mops_s"], 3),
                "p99_ratio_plain_over_persistent": round(plain["p99_us"] / pers["p99_us"], 3),
+               "service_by_size": bands,
                "results_identical": bool(same)}
         run.close()
         st.close()

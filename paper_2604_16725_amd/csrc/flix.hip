@@ -153,7 +153,14 @@ template <typename T>
 int dev_alloc(T** p, u64 bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
-  if (hipMalloc(reinterpret_cast<void**>(p), bytes) != hipSuccess) return FLIX_ENOMEM;
+  const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    std::snprintf(g_last_error, sizeof(g_last_error), "hipMalloc of %llu bytes: %s",
+                  (unsigned long long)bytes, hipGetErrorString(e));
+    (void)hipGetLastError();
+    return FLIX_ENOMEM;
+  }
   return FLIX_OK;
 }
 template <typename T>

@@ -166,7 +166,7 @@ struct DrainSmemSize {
 };
 
 template <typename K, int RB, int GL, int KPL>
-__global__ __launch_bounds__(256) void k_drain(DrainArgs<K> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_drain(DrainArgs<K> a) {
   extern __shared__ unsigned char smem[];
   __shared__ unsigned long long s_counter;
   __shared__ u32 s_epoch;

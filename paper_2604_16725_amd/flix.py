@@ -20,7 +20,7 @@ _ERR_NAMES = {-1: "FLIX_EINVAL", -2: "FLIX_ENOMEM", -3: "FLIX_EHIP", -4: "FLIX_E
 class FlixError(RuntimeError):
     def __init__(self, code: int, what: str):
         detail = ""
-        if code == FLIX_EHIP and _lib is not None:
+        if code in (FLIX_EHIP, FLIX_ENOMEM) and _lib is not None:
             detail = " (" + _lib.flix_last_error().decode(errors="replace") + ")"
         super().__init__(f"{what} failed: {_ERR_NAMES.get(code, code)}{detail}")
         self.code = code
@@ -102,6 +102,12 @@ def load_library(path: str = LIB_PATH):
         raise RuntimeError(
             f"FliX HIP library not found at {path}; build it with "
             "`python -m paper_2604_16725_amd.build_lib` (no CPU fallback exists)")
+    # One HIP runtime per process: torch carries its own build of it, so it is
+    # loaded first and the library binds to that copy instead of a second one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
     sig = {
