@@ -159,7 +159,8 @@ def batching_compare(args):
                                                run_plain, summarize)
     from paper_2604_16725_amd.workloads import BatchStream
 
-    cfg = autotune.tuned_config()
+    cfg = autotune.tuned_config(form="persistent")
+    cfg_plain = autotune.tuned_config(form="plain")
     t0 = time.time()
     stream = BatchStream(n_keys=1 << args.keys_log2, nbatch=args.nbatch)
     ds = DeviceStream(stream)
@@ -168,9 +169,10 @@ def batching_compare(args):
     cs = torch.cuda.Stream()
     res = {}
     with torch.cuda.stream(cs):
-        st = flix.Store(key_bits=32, capacity=cfg["capacity"], lanes=cfg["lanes"],
-                        radix_bits=cfg["radix_bits"], max_batch=1 << 20,
-                        pool_bytes=pool_bytes_for(stream, cfg["capacity"]))
+        # each form runs on the layout its own sweep picked
+        st = flix.Store(key_bits=32, capacity=cfg_plain["capacity"], lanes=cfg_plain["lanes"],
+                        radix_bits=cfg_plain["radix_bits"], max_batch=1 << 20,
+                        pool_bytes=pool_bytes_for(stream, cfg_plain["capacity"]))
         outs_p, outs_g = ds.outputs(), ds.outputs()
         plain = None
         for rep in range(2):
@@ -186,6 +188,10 @@ def batching_compare(args):
             raise RuntimeError("device error in the plain stream")
         dump_p = st.dump()
         log(f"[bench] plain: {plain}")
+        st.close()
+        st = flix.Store(key_bits=32, capacity=cfg["capacity"], lanes=cfg["lanes"],
+                        radix_bits=cfg["radix_bits"], max_batch=1 << 20,
+                        pool_bytes=pool_bytes_for(stream, cfg["capacity"]))
         run = PersistentRun(st, ds, outs_g, cs)
         pers = None
         for rep in range(2):
@@ -213,7 +219,8 @@ def batching_compare(args):
                     "persistent_mean_us": round(float(svc_pers[m_].mean()) * 1e6, 1)}
         res = {"workload": f"{ds.n} mixed batches, sizes floor(2^U) U~U[8,20], 70/10/10/10 "
                            f"lookup/successor/insert/delete, 2^{args.keys_log2} u32 keys",
-               "ops": ds.total_ops, "store": cfg, "drain_workgroups": st.drain_info()[0],
+               "ops": ds.total_ops, "store_plain": cfg_plain, "store_persistent": cfg,
+               "drain_workgroups": st.drain_info()[0],
                "plain": plain, "persistent_graph": pers,
                "speedup_Mops": round(pers["Mops_s"] / plain["Mops_s"], 3),
                "p99_ratio_plain_over_persistent": round(plain["p99_us"] / pers["p99_us"], 3),

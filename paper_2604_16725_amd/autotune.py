@@ -30,11 +30,13 @@ GRID = {"capacity": (32, 64, 128, 256), "lanes": (16, 32, 64), "radix_bits": (4,
 FALLBACK = {"capacity": 128, "lanes": 16, "radix_bits": 8}
 
 
-def tuned_config(path: str = DEFAULT_PATH) -> dict:
-    """The best point of a saved sweep, else the untuned default."""
+def tuned_config(path: str = DEFAULT_PATH, form: str = "persistent") -> dict:
+    """The best point of a saved sweep for one form ("persistent": the drain
+    from a hipGraph; "plain": one call per batch), else the untuned default."""
+    key = "best" if form == "persistent" else "best_plain"
     try:
         with open(path) as f:
-            best = json.load(f)["best"]
+            best = json.load(f)[key]
         return {k: int(best[k]) for k in FALLBACK}
     except (OSError, KeyError, ValueError):
         return dict(FALLBACK)
@@ -86,7 +88,13 @@ def sweep(n_keys: int = 1 << 26, nbatch: int = 4096, prefix: int = 512, reps: in
             st.close()
             del outs
     best = max(points, key=lambda p: p["persistent"]["Mops_s"])
-    return {"workload": f"mixed batch stream prefix: {ds.n} of {nbatch} batches "
+    with_p = [p for p in points if "plain" in p]
+    best_plain = max(with_p, key=lambda p: p["plain"]["Mops_s"]) if with_p else None
+    extra = {}
+    if best_plain is not None:
+        extra["best_plain"] = ({k: best_plain[k] for k in ("capacity", "lanes", "radix_bits")}
+                               | {"Mops_s": best_plain["plain"]["Mops_s"]})
+    return extra | {"workload": f"mixed batch stream prefix: {ds.n} of {nbatch} batches "
                         f"({ds.total_ops} ops), sizes 2^8..2^20 log-uniform, 70/10/10/10 "
                         f"lookup/successor/insert/delete, {n_keys} u32 keys",
             "device": torch.cuda.get_device_name(0),
