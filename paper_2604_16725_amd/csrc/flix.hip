@@ -92,6 +92,7 @@ struct flix_store {
   int drain_grid = 0;                 // co-resident workgroups of the drain kernel
   size_t drain_shm = 0;
   StoreLayout* d_layout = nullptr;    // layout record read by drains (graph replays)
+  u32 upd_resident[4] = {0, 0, 0, 0}; // resident workgroups of each update kernel
   // epoch slots (allocated by the first epoch call)
   EpochSlot* ep[2] = {nullptr, nullptr};
 };
@@ -370,24 +371,44 @@ u32 upd_lds_items(const flix_store* s) { return s->cap + upd_chunk(s); }
 
 // m_dev: null for a list of host-known length n; otherwise the length is read
 // from device memory and n is its upper bound (grid sizing only).
+// The grid gives every lane group one work item when there are few and is
+// capped at the resident workgroup count when there are many, so each group
+// then walks a run of items with the next one's loads in flight.
 template <typename K, int GL>
-void launch_update(flix_store* s, bool insert, const UpdArgs<K>& a, u32 grid, hipStream_t st,
+void launch_update(flix_store* s, bool insert, const UpdArgs<K>& a, u64 items, hipStream_t st,
                    u32 lds_items, const u32* m_dev) {
   size_t shm = (size_t)(kUpdNT / GL) * 2 * lds_items * sizeof(K);
   static size_t attr_set[4] = {0, 0, 0, 0};
   const int which = (insert ? 1 : 0) + (m_dev ? 2 : 0);
+  const void* fn;
+  switch (which) {
+    case 0: fn = reinterpret_cast<const void*>(&k_delete_apply<K, GL, kUpdNT>); break;
+    case 1: fn = reinterpret_cast<const void*>(&k_insert_apply<K, GL, kUpdNT>); break;
+    case 2: fn = reinterpret_cast<const void*>(&k_delete_counted<K, GL, kUpdNT>); break;
+    default: fn = reinterpret_cast<const void*>(&k_insert_counted<K, GL, kUpdNT>); break;
+  }
   if (shm > 65536 && shm > attr_set[which]) {
-    const void* fn;
-    switch (which) {
-      case 0: fn = reinterpret_cast<const void*>(&k_delete_apply<K, GL, kUpdNT>); break;
-      case 1: fn = reinterpret_cast<const void*>(&k_insert_apply<K, GL, kUpdNT>); break;
-      case 2: fn = reinterpret_cast<const void*>(&k_delete_counted<K, GL, kUpdNT>); break;
-      default: fn = reinterpret_cast<const void*>(&k_insert_counted<K, GL, kUpdNT>); break;
-    }
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e == hipSuccess) attr_set[which] = shm;
     (void)hipGetLastError();
   }
+  if (s->upd_resident[which] == 0) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kUpdNT, shm) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        per_cu < 1 || cus < 1) {
+      per_cu = 4;
+      cus = 256;
+    }
+    (void)hipGetLastError();
+    s->upd_resident[which] = (u32)(per_cu * cus);
+  }
+  const u32 gpb = kUpdNT / GL;
+  u64 g2 = (items + gpb - 1) / gpb;
+  if (g2 < 1) g2 = 1;
+  if (g2 > s->upd_resident[which]) g2 = s->upd_resident[which];
+  const u32 grid = (u32)g2;
   switch (which) {
     case 0:
       hipLaunchKernelGGL((k_delete_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
@@ -461,15 +482,11 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   ua.status = &s->ctl->status;
   u32 lds_items = upd_lds_items(s);
   u64 items = std::min<u64>(n, s->nb);
-  u32 gpb = kUpdNT / s->gl;
-  u64 g2 = (items + 2 * gpb - 1) / (2 * gpb);
-  if (g2 < 1) g2 = 1;
-  if (g2 > 16384) g2 = 16384;
   tm_begin(s, st, &b);
   switch (s->gl) {
-    case 16: launch_update<K, 16>(s, insert, ua, (u32)g2, st, lds_items, m_dev); break;
-    case 32: launch_update<K, 32>(s, insert, ua, (u32)g2, st, lds_items, m_dev); break;
-    default: launch_update<K, 64>(s, insert, ua, (u32)g2, st, lds_items, m_dev); break;
+    case 16: launch_update<K, 16>(s, insert, ua, items, st, lds_items, m_dev); break;
+    case 32: launch_update<K, 32>(s, insert, ua, items, st, lds_items, m_dev); break;
+    default: launch_update<K, 64>(s, insert, ua, items, st, lds_items, m_dev); break;
   }
   tm_end(s, st, insert ? F_INSERT : F_DELETE, b);
   HIP_TRY(hipGetLastError());
