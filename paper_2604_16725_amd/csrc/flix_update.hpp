@@ -464,9 +464,14 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         j = j2;
         continue;
       }
+      // Node items below the chunk's smallest key neither move nor meet a
+      // chunk key: the duplicate scan starts at the group-aligned run that
+      // holds the first node key >= bk[0].
+      const u32 f0 = lower_bound_idx<K>(ak, 0u, sa, bk[0]);
+      const u32 i_lo = f0 - f0 % GL;
       // duplicates between node and chunk
       u32 dd = 0;
-      for (u32 i0 = 0; i0 < sa; i0 += GL) {
+      for (u32 i0 = i_lo; i0 < sa; i0 += GL) {
         u32 i = i0 + g.lane;
         bool drop = false;
         if (i < sa) {
@@ -493,9 +498,9 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         nodes_added += k - 1;
       }
       // node id of piece p: X for p == 0, free_ids[base_id - p] otherwise
-      // write node items
+      // write node items (without a split, only from the first moving one)
       u32 drop_before = 0;
-      for (u32 i0 = 0; i0 < sa; i0 += GL) {
+      for (u32 i0 = (k == 1) ? i_lo : 0u; i0 < sa; i0 += GL) {
         u32 i = i0 + g.lane;
         bool drop = false;
         u32 pos = 0;
@@ -515,7 +520,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
             atomicCAS(a.status, 0u, kErrInternal);
             continue;
           }
-          u32 slot = pos - piece_start(pc, c, k);
+          u32 slot = (k == 1) ? pos : pos - piece_start(pc, c, k);
           a.nkeys[(u64)node * a.cap + slot] = kk;
           a.nvals[(u64)node * a.cap + slot] = vv;
           if (k > 1 && pc + 1 < k && slot + 1 == piece_start(pc + 1, c, k) - piece_start(pc, c, k))
@@ -544,7 +549,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
             atomicCAS(a.status, 0u, kErrInternal);
             continue;
           }
-          u32 slot = pos - piece_start(pc, c, k);
+          u32 slot = (k == 1) ? pos : pos - piece_start(pc, c, k);
           a.nkeys[(u64)node * a.cap + slot] = kk;
           a.nvals[(u64)node * a.cap + slot] = vv;
           if (k > 1 && pc + 1 < k && slot + 1 == piece_start(pc + 1, c, k) - piece_start(pc, c, k))
@@ -720,9 +725,14 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       }
       u32 first_gone = sx;   // slot of the first removed item: earlier slots stay
       if (touched) {
-        // mark + compact in LDS (survivors only move left)
-        u32 kept = 0;
-        for (u32 i0 = 0; i0 < sx; i0 += GL) {
+        // mark + compact in LDS (survivors only move left); node items below
+        // the slice's smallest key survive in place, so the scan starts at
+        // the group-aligned run holding the first key >= it
+        const K smin = slice_lds ? bk[0] : a.skeys[j];
+        const u32 f0 = lower_bound_idx<K>(ak, 0u, sx, smin);
+        const u32 i_lo = f0 - f0 % GL;
+        u32 kept = i_lo;
+        for (u32 i0 = i_lo; i0 < sx; i0 += GL) {
           u32 i = i0 + g.lane;
           bool keep = false;
           K kk = K(0), vv = K(0);
