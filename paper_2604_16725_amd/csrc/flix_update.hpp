@@ -497,10 +497,65 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         }
         nodes_added += k - 1;
       }
+      if (k == 1) {
+        // No split: the merge stays in X.  Node items from the first moving
+        // one are shifted right by the chunk keys below them (less the
+        // duplicates before them); chunk items land at their merged rank.
+        K* const xk = a.nkeys + (u64)X * a.cap;
+        K* const xv = a.nvals + (u64)X * a.cap;
+        u32 drop_before = 0;
+        for (u32 i0 = i_lo; i0 < sa; i0 += GL) {
+          const u32 i = i0 + g.lane;
+          bool drop = false;
+          u32 pos = 0;
+          K kk = K(0), vv = K(0);
+          if (i < sa) {
+            kk = ak[i];
+            vv = av[i];
+            const u32 p = lower_bound_idx<K>(bk, 0u, tb, kk);
+            drop = p < tb && bk[p] == kk;
+            pos = i - (drop_before + g.rank(drop)) + p;
+          }
+          drop_before += g.count(drop);
+          if (i < sa && !drop && pos != i) {
+            xk[pos] = kk;
+            xv[pos] = vv;
+          }
+        }
+        u32 match_before = 0;
+        for (u32 j0 = 0; j0 < tb; j0 += GL) {
+          const u32 jj = j0 + g.lane;
+          bool match = false;
+          u32 pos = 0;
+          K kk = K(0), vv = K(0);
+          if (jj < tb) {
+            kk = bk[jj];
+            vv = bv[jj];
+            const u32 p = lower_bound_idx<K>(ak, 0u, sa, kk);
+            match = p < sa && ak[p] == kk;
+            pos = jj + p - (match_before + g.rank(match));
+          }
+          match_before += g.count(match);
+          if (jj < tb) {
+            xk[pos] = kk;
+            xv[pos] = vv;
+          }
+        }
+        added += c - sa;
+        if (g.lane == 0) a.hdr[X].size = c;
+        hX.size = c;
+        j = j2;
+        if (j < w.e) {
+          fresh = true;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        }
+        wave_lds_sync();
+        continue;
+      }
       // node id of piece p: X for p == 0, free_ids[base_id - p] otherwise
-      // write node items (without a split, only from the first moving one)
+      // write node items
       u32 drop_before = 0;
-      for (u32 i0 = (k == 1) ? i_lo : 0u; i0 < sa; i0 += GL) {
+      for (u32 i0 = 0; i0 < sa; i0 += GL) {
         u32 i = i0 + g.lane;
         bool drop = false;
         u32 pos = 0;
