@@ -238,14 +238,28 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
               s_pos[j] = (lb << 16) | (gl * KPL + (u32)hit);
             }
           } else {
-            // lower bound of x (and upper bound of hi for ranges)
-            u32 lt = 0, le = 0;
+            // Lower bound of x (and upper bound of hi for ranges).  The
+            // node is sorted and lane l holds positions [l*KPL, l*KPL+KPL),
+            // so the lanes whose first key is below x form a prefix of L
+            // lanes and the bound lies in lane L-1: one ballot over first
+            // keys plus that lane's own count.
             const K hi = (op == kOpRange) ? s_hi[j] : K(0);
+            const bool v0 = gl * KPL < size;
+            u32 c_lt = 0, c_le = 0;
 #pragma unroll
             for (int k = 0; k < KPL; ++k) {
-              bool v = gl * KPL + k < size;
-              lt += (u32)__popcll(wave_ballot(v && kv[u].k[k] < x) & gmask);
-              if (op == kOpRange) le += (u32)__popcll(wave_ballot(v && kv[u].k[k] <= hi) & gmask);
+              const bool v = gl * KPL + k < size;
+              c_lt += (v && kv[u].k[k] < x) ? 1u : 0u;
+              if (op == kOpRange) c_le += (v && kv[u].k[k] <= hi) ? 1u : 0u;
+            }
+            const u32 L1 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] < x) & gmask);
+            const u32 s_lt = (u32)__shfl((int)c_lt, (int)(gbase + (L1 ? L1 - 1 : 0)), 64);
+            const u32 lt = L1 ? (L1 - 1) * KPL + s_lt : 0u;
+            u32 le = 0;
+            if (op == kOpRange) {
+              const u32 L2 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] <= hi) & gmask);
+              const u32 s_le = (u32)__shfl((int)c_le, (int)(gbase + (L2 ? L2 - 1 : 0)), 64);
+              le = L2 ? (L2 - 1) * KPL + s_le : 0u;
             }
             if (gl == 0) {
               u32 code;
