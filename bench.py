@@ -237,8 +237,10 @@ def serving_compare(args):
     """Open-loop Poisson arrivals on a 2^serve_keys_log2 u64 store: the
     coalescing request loop (two pipelined epoch slots) against the plain
     form (every request its own epoch, one at a time), at 0.2..0.95 of the
-    plain form's saturation rate, measured first with all requests queued
-    at time 0.  Each run starts from the same bulk load."""
+    plain form's saturation rate (measured first with all requests queued
+    at time 0), and at 1.5 and 3 times it, beyond what the plain form can
+    serve.  The serving form's own saturation is measured the same way.
+    Each run starts from the same bulk load."""
     import torch
     from paper_2604_16725_amd import flix, serve
     from paper_2604_16725_amd.workloads import ServingWorkload
@@ -268,8 +270,11 @@ def serving_compare(args):
     sat = one(None, False)
     sat_rate = sat["completed"] / sat["span_s"]
     log(f"[bench] plain form saturation: {sat_rate:.0f} requests/s")
+    sat_s = one(None, True)
+    sat_rate_s = sat_s["completed"] / sat_s["span_s"]
+    log(f"[bench] serving form saturation: {sat_rate_s:.0f} requests/s")
     rows = []
-    for frac in (0.2, 0.4, 0.6, 0.8, 0.95):
+    for frac in (0.2, 0.4, 0.6, 0.8, 0.95, 1.5, 3.0):
         rate = frac * sat_rate
         row = {"load": frac, "rate_req_s": round(rate, 1)}
         for name, coalesce in (("plain", False), ("serving", True)):
@@ -281,7 +286,11 @@ def serving_compare(args):
                         f"80/5/7.5/7.5 lookup/range/insert/delete, ranges of 8..64 keys, "
                         f"2^{args.serve_keys_log2} u64 keys, Poisson arrivals",
             "epoch_capacity_ops": E, "budget_bytes": budget,
-            "plain_saturation_req_s": round(sat_rate, 1), "rates": rows}
+            "plain_saturation_req_s": round(sat_rate, 1),
+            "plain_saturation_Mops_s": round(sat["ops"] / sat["span_s"] / 1e6, 3),
+            "serving_saturation_req_s": round(sat_rate_s, 1),
+            "serving_saturation_Mops_s": round(sat_s["ops"] / sat_s["span_s"] / 1e6, 3),
+            "rates": rows}
 
 
 def main():
