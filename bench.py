@@ -127,26 +127,29 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
 
 
 def counter_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for a plain copy),
-    or None when the kernel's sources no longer hash to what was measured."""
+    """HBM bytes per launch of kernel family `kernel` from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by what it reads for
+    a plain copy), or None when the kernel sources no longer hash to what was
+    measured or the family was not measured."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "read_path_step_hbm_counters.md")
     try:
         m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
         rec = json.loads(m.group(1))
-    except (OSError, AttributeError, ValueError):
-        return None
-    if rec.get("kernel") != kernel:
+        fam = rec["families"][kernel]
+    except (OSError, AttributeError, ValueError, KeyError):
         return None
     h = hashlib.sha256()
     for fn in rec["sources"]:
-        with open(os.path.join(ROOT, "paper_2604_16725_amd", "csrc", fn), "rb") as fh:
-            h.update(fh.read())
+        try:
+            with open(os.path.join(ROOT, "paper_2604_16725_amd", "csrc", fn), "rb") as fh:
+                h.update(fh.read())
+        except OSError:
+            return None
     if h.hexdigest() != rec["sources_sha256"]:
         return None
-    return rec["traffic_bytes_per_launch"]
+    return fam["traffic_bytes_per_launch"]
 
 
 def batching_compare(args):
