@@ -164,13 +164,6 @@ int flix_copy_layout(flix_store* s, void* h_mkba, void* h_hdr, void* h_keys, voi
 int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
                     uint32_t* d_idx_out, void* stream);
 
-/* Per-kernel timing on `stream` with HIP events (for the benchmark).  When
- * enabled, every launch of the named kernel family is bracketed by events;
- * flix_kernel_time returns the summed milliseconds and launch count since the
- * last reset.  Each family is one kernel: "sort_hist" (digit histograms),
- * "sort_pass" (one onesweep pass), "read_apply" (lookup/successor/range
- * bucket kernel), "slices" (update slice discovery and node budget),
- * "insert_apply", "delete_apply".  Enabling or disabling resets the sums. */
 /* ---- Persistent fused drain (a queue of mixed batches in one launch) ----
  * One co-resident grid executes the batches in order with the same phases as
  * the per-batch calls (sort, bound search, apply) separated by grid barriers,
@@ -265,7 +258,20 @@ int flix_epoch_apply(flix_store* s, uint32_t slot, const flix_epoch* e, void* st
  * (which call and the runtime's message); "" if none.  Never NULL. */
 const char* flix_last_error(void);
 
+/* Per-kernel timing with HIP events (for the benchmark).  While enabled,
+ * every launch of a timed kernel family carries a start and a stop event that
+ * the dispatch itself stamps (no marker packets between kernels);
+ * flix_kernel_time returns the summed milliseconds and launch count since the
+ * last reset.  Each family is one kernel: "sort_hist" (digit histograms),
+ * "sort_pass" (one onesweep pass), "read_apply" (lookup/successor/range
+ * bucket kernel), "slices" (update slice discovery and node budget),
+ * "insert_apply", "delete_apply".  flix_set_timing(s, enable) times every
+ * family (enable != 0) or none; flix_set_timing_only(s, family) times only
+ * the named family, leaving the other launches uninstrumented (FLIX_EINVAL
+ * for an unknown name).  Both reset the sums.  Host-side and synchronous with
+ * respect to earlier timed launches (their events are collected first). */
 int flix_set_timing(flix_store* s, int enable);
+int flix_set_timing_only(flix_store* s, const char* family);
 int flix_kernel_time(flix_store* s, const char* family, double* ms, uint64_t* launches);
 
 #ifdef __cplusplus

@@ -29,6 +29,7 @@ enum Family { F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DEL
 
 struct Timing {
   bool on = false;
+  u32 mask = 0;   // bit f: family f is timed
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -118,24 +119,27 @@ inline hipStream_t S(void* st) { return reinterpret_cast<hipStream_t>(st); }
 u64 node_bytes(const flix_store* s) { return (u64)s->cap * 2 * s->ksz + sizeof(NodeHdr); }
 
 // ---- timing -----------------------------------------------------------------
-void tm_begin(flix_store* s, hipStream_t st, hipEvent_t* b) {
-  *b = nullptr;
-  if (!s->tm.on) return;
+// Timing token: the start/stop events of one kernel dispatch (both null while
+// timing is off); the launch stamps them (launch_timed).
+struct TmTok {
+  hipEvent_t b = nullptr, e = nullptr;
+};
+TmTok tm_arm(flix_store* s, int fam) {
+  TmTok t;
+  if (!s->tm.on || !(s->tm.mask & (1u << fam))) return t;
   if (s->tm.used + 2 > s->tm.pool.size()) {
     for (int i = 0; i < 64; ++i) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return;
+      if (hipEventCreate(&e) != hipSuccess) return t;
       s->tm.pool.push_back(e);
     }
   }
-  *b = s->tm.pool[s->tm.used++];
-  (void)hipEventRecord(*b, st);
+  t.b = s->tm.pool[s->tm.used++];
+  t.e = s->tm.pool[s->tm.used++];
+  return t;
 }
-void tm_end(flix_store* s, hipStream_t st, int fam, hipEvent_t b) {
-  if (!s->tm.on || b == nullptr) return;
-  hipEvent_t e = s->tm.pool[s->tm.used++];
-  (void)hipEventRecord(e, st);
-  s->tm.pending.push_back({fam, {b, e}});
+void tm_done(flix_store* s, int fam, const TmTok& t) {
+  if (t.b && t.e) s->tm.pending.push_back({fam, {t.b, t.e}});
 }
 void tm_collect(flix_store* s) {
   for (auto& p : s->tm.pending) {
@@ -256,14 +260,16 @@ __global__ void k_reset_call(Ctl* ctl) {
   ctl->heavy_cursor = 0;
 }
 
-void sort_hook_begin(void* ctx, hipStream_t st, void** tok) {
-  hipEvent_t b;
-  tm_begin(static_cast<flix_store*>(ctx), st, &b);
-  *tok = b;
+void sort_hook_begin(void* ctx, int fam, hipEvent_t* e0, hipEvent_t* e1) {
+  const TmTok t = tm_arm(static_cast<flix_store*>(ctx), fam == 0 ? F_HIST : F_PASS);
+  *e0 = t.b;
+  *e1 = t.e;
 }
-void sort_hook_end(void* ctx, hipStream_t st, int fam, void* tok) {
-  tm_end(static_cast<flix_store*>(ctx), st, fam == 0 ? F_HIST : F_PASS,
-         static_cast<hipEvent_t>(tok));
+void sort_hook_end(void* ctx, int fam, hipEvent_t e0, hipEvent_t e1) {
+  TmTok t;
+  t.b = e0;
+  t.e = e1;
+  tm_done(static_cast<flix_store*>(ctx), fam == 0 ? F_HIST : F_PASS, t);
 }
 
 template <typename K>
@@ -285,29 +291,30 @@ struct ReadCfg<u64> {
 };
 
 template <typename K, int GL, int KPL>
-void launch_read2_k(const ReadArgs<K>& a, int op, u32 grid, hipStream_t st) {
+void launch_read2_k(const ReadArgs<K>& a, int op, u32 grid, hipStream_t st, const TmTok& t) {
   constexpr int U = KPL >= 16 ? 2 : 4;
-  hipLaunchKernelGGL((k_read_apply2<K, 256, ReadCfg<K>::S, GL, KPL, U>), dim3(grid), dim3(256), 0,
-                     st, a, op);
+  launch_timed(t.b, t.e, k_read_apply2<K, 256, ReadCfg<K>::S, GL, KPL, U>, dim3(grid), dim3(256),
+               0, st, a, op);
 }
 
 // Lanes per bucket GL and keys per lane KPL = max(1, cap / GL).
 template <typename K>
-void launch_read2(const flix_store* s, const ReadArgs<K>& a, int op, u32 grid, hipStream_t st) {
+void launch_read2(const flix_store* s, const ReadArgs<K>& a, int op, u32 grid, hipStream_t st,
+                  const TmTok& t) {
   const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
   switch (s->gl * 100 + kpl) {
-    case 1601: launch_read2_k<K, 16, 1>(a, op, grid, st); break;
-    case 1602: launch_read2_k<K, 16, 2>(a, op, grid, st); break;
-    case 1604: launch_read2_k<K, 16, 4>(a, op, grid, st); break;
-    case 1608: launch_read2_k<K, 16, 8>(a, op, grid, st); break;
-    case 1616: launch_read2_k<K, 16, 16>(a, op, grid, st); break;
-    case 3201: launch_read2_k<K, 32, 1>(a, op, grid, st); break;
-    case 3202: launch_read2_k<K, 32, 2>(a, op, grid, st); break;
-    case 3204: launch_read2_k<K, 32, 4>(a, op, grid, st); break;
-    case 3208: launch_read2_k<K, 32, 8>(a, op, grid, st); break;
-    case 6401: launch_read2_k<K, 64, 1>(a, op, grid, st); break;
-    case 6402: launch_read2_k<K, 64, 2>(a, op, grid, st); break;
-    default: launch_read2_k<K, 64, 4>(a, op, grid, st); break;
+    case 1601: launch_read2_k<K, 16, 1>(a, op, grid, st, t); break;
+    case 1602: launch_read2_k<K, 16, 2>(a, op, grid, st, t); break;
+    case 1604: launch_read2_k<K, 16, 4>(a, op, grid, st, t); break;
+    case 1608: launch_read2_k<K, 16, 8>(a, op, grid, st, t); break;
+    case 1616: launch_read2_k<K, 16, 16>(a, op, grid, st, t); break;
+    case 3201: launch_read2_k<K, 32, 1>(a, op, grid, st, t); break;
+    case 3202: launch_read2_k<K, 32, 2>(a, op, grid, st, t); break;
+    case 3204: launch_read2_k<K, 32, 4>(a, op, grid, st, t); break;
+    case 3208: launch_read2_k<K, 32, 8>(a, op, grid, st, t); break;
+    case 6401: launch_read2_k<K, 64, 1>(a, op, grid, st, t); break;
+    case 6402: launch_read2_k<K, 64, 2>(a, op, grid, st, t); break;
+    default: launch_read2_k<K, 64, 4>(a, op, grid, st, t); break;
   }
 }
 
@@ -334,10 +341,9 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   a.pool = s->pool;
   a.err = &s->ctl->status;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
-  hipEvent_t b;
-  tm_begin(s, st, &b);
-  launch_read2<K>(s, a, op, (u32)grid, st);
-  tm_end(s, st, F_READ, b);
+  const TmTok t = tm_arm(s, F_READ);
+  launch_read2<K>(s, a, op, (u32)grid, st, t);
+  tm_done(s, F_READ, t);
   HIP_TRY(hipGetLastError());
   return FLIX_OK;
 }
@@ -376,7 +382,7 @@ u32 upd_lds_items(const flix_store* s) { return s->cap + upd_chunk(s); }
 // then walks a run of items with the next one's loads in flight.
 template <typename K, int GL>
 void launch_update(flix_store* s, bool insert, const UpdArgs<K>& a, u64 items, hipStream_t st,
-                   u32 lds_items, const u32* m_dev) {
+                   u32 lds_items, const u32* m_dev, const TmTok& t) {
   size_t shm = (size_t)(kUpdNT / GL) * 2 * lds_items * sizeof(K);
   static size_t attr_set[4] = {0, 0, 0, 0};
   const int which = (insert ? 1 : 0) + (m_dev ? 2 : 0);
@@ -409,22 +415,20 @@ void launch_update(flix_store* s, bool insert, const UpdArgs<K>& a, u64 items, h
   if (g2 < 1) g2 = 1;
   if (g2 > s->upd_resident[which]) g2 = s->upd_resident[which];
   const u32 grid = (u32)g2;
+  const dim3 g(grid), blk(kUpdNT);
+  const uint32_t sh = (uint32_t)shm;
   switch (which) {
     case 0:
-      hipLaunchKernelGGL((k_delete_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
-                         lds_items);
+      launch_timed(t.b, t.e, k_delete_apply<K, GL, kUpdNT>, g, blk, sh, st, a, lds_items);
       break;
     case 1:
-      hipLaunchKernelGGL((k_insert_apply<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
-                         lds_items);
+      launch_timed(t.b, t.e, k_insert_apply<K, GL, kUpdNT>, g, blk, sh, st, a, lds_items);
       break;
     case 2:
-      hipLaunchKernelGGL((k_delete_counted<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
-                         lds_items, m_dev);
+      launch_timed(t.b, t.e, k_delete_counted<K, GL, kUpdNT>, g, blk, sh, st, a, lds_items, m_dev);
       break;
     default:
-      hipLaunchKernelGGL((k_insert_counted<K, GL, kUpdNT>), dim3(grid), dim3(kUpdNT), shm, st, a,
-                         lds_items, m_dev);
+      launch_timed(t.b, t.e, k_insert_counted<K, GL, kUpdNT>, g, blk, sh, st, a, lds_items, m_dev);
       break;
   }
 }
@@ -448,20 +452,21 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   sa.ctl = s->ctl;
   constexpr int SS = SliceCfg<K>::S;
   u64 grid = ((u64)n + s->nb + sa.share - 1) / sa.share;
-  hipEvent_t b;
-  tm_begin(s, st, &b);
+  TmTok t = tm_arm(s, F_PRE);
   if (m_dev) {
     if (insert)
-      hipLaunchKernelGGL((k_slices_counted<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa, m_dev);
+      launch_timed(t.b, t.e, k_slices_counted<K, 256, SS, true>, dim3(grid), dim3(256), 0, st, sa,
+                   m_dev);
     else
-      hipLaunchKernelGGL((k_slices_counted<K, 256, SS, false>), dim3(grid), dim3(256), 0, st, sa, m_dev);
+      launch_timed(t.b, t.e, k_slices_counted<K, 256, SS, false>, dim3(grid), dim3(256), 0, st, sa,
+                   m_dev);
   } else {
     if (insert)
-      hipLaunchKernelGGL((k_slices<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa);
+      launch_timed(t.b, t.e, k_slices<K, 256, SS, true>, dim3(grid), dim3(256), 0, st, sa);
     else
-      hipLaunchKernelGGL((k_slices<K, 256, SS, false>), dim3(grid), dim3(256), 0, st, sa);
+      launch_timed(t.b, t.e, k_slices<K, 256, SS, false>, dim3(grid), dim3(256), 0, st, sa);
   }
-  tm_end(s, st, F_PRE, b);
+  tm_done(s, F_PRE, t);
   HIP_TRY(hipGetLastError());
 
   UpdArgs<K> ua;
@@ -482,13 +487,13 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   ua.status = &s->ctl->status;
   u32 lds_items = upd_lds_items(s);
   u64 items = std::min<u64>(n, s->nb);
-  tm_begin(s, st, &b);
+  t = tm_arm(s, insert ? F_INSERT : F_DELETE);
   switch (s->gl) {
-    case 16: launch_update<K, 16>(s, insert, ua, items, st, lds_items, m_dev); break;
-    case 32: launch_update<K, 32>(s, insert, ua, items, st, lds_items, m_dev); break;
-    default: launch_update<K, 64>(s, insert, ua, items, st, lds_items, m_dev); break;
+    case 16: launch_update<K, 16>(s, insert, ua, items, st, lds_items, m_dev, t); break;
+    case 32: launch_update<K, 32>(s, insert, ua, items, st, lds_items, m_dev, t); break;
+    default: launch_update<K, 64>(s, insert, ua, items, st, lds_items, m_dev, t); break;
   }
-  tm_end(s, st, insert ? F_INSERT : F_DELETE, b);
+  tm_done(s, insert ? F_INSERT : F_DELETE, t);
   HIP_TRY(hipGetLastError());
   return FLIX_OK;
 }
@@ -1333,10 +1338,11 @@ int flix_drain_info(flix_store* s, uint32_t* grid_blocks, uint64_t* timestamp_hz
   return FLIX_OK;
 }
 
-int flix_set_timing(flix_store* s, int enable) {
+static int set_timing_mask(flix_store* s, u32 mask) {
   if (!s) return FLIX_ESTATE;
   tm_collect(s);
-  s->tm.on = enable != 0;
+  s->tm.on = mask != 0;
+  s->tm.mask = mask;
   s->ss.on_begin = s->tm.on ? sort_hook_begin : nullptr;
   s->ss.on_end = s->tm.on ? sort_hook_end : nullptr;
   s->ss.hook_ctx = s;
@@ -1345,6 +1351,18 @@ int flix_set_timing(flix_store* s, int enable) {
     s->tm.count[i] = 0;
   }
   return FLIX_OK;
+}
+
+int flix_set_timing(flix_store* s, int enable) {
+  return set_timing_mask(s, enable ? (1u << kFamilies) - 1u : 0u);
+}
+
+int flix_set_timing_only(flix_store* s, const char* family) {
+  if (!s) return FLIX_ESTATE;
+  if (!family) return set_timing_mask(s, (1u << kFamilies) - 1u);
+  for (int i = 0; i < kFamilies; ++i)
+    if (std::strcmp(family, kFamilyNames[i]) == 0) return set_timing_mask(s, 1u << i);
+  return FLIX_EINVAL;
 }
 
 int flix_kernel_time(flix_store* s, const char* family, double* ms, uint64_t* launches) {

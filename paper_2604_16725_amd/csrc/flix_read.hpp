@@ -39,17 +39,55 @@ struct ReadArgs {
   u32* err;            // sticky status word for internal errors
 };
 
-// Number of batch keys among the first d items of merge(keys, mkba), ties to
-// the keys: a key equal to MKBA[i] belongs to bucket i.
+// Cooperative merge-path cut for the two diagonals d[0], d[1] of one
+// workgroup (NT == 256: threads 0..127 search d[0], 128..255 search d[1]).
+// Returns, for both diagonals, the number of batch keys among the first d
+// items of merge(keys, mkba) with ties to the keys (a key equal to MKBA[i]
+// belongs to bucket i).
 template <typename K>
-__device__ u32 merge_path_keys(const K* a, u32 na, const K* mk, u32 nm, u64 d) {
-  u32 lo = d > nm ? (u32)(d - nm) : 0u;
-  u32 hi = d < na ? (u32)d : na;
-  while (lo < hi) {
-    u32 mid = (lo + hi) >> 1;
-    if (a[mid] <= mk[(u32)(d - mid - 1)]) lo = mid + 1; else hi = mid;
+__device__ void coop_merge_path(const K* a, u32 na, const K* mk, u32 nm, const u64 d[2],
+                                u32* s_lo, u32* s_hi, u32* s_wc, u32* out) {
+  const u32 tid = threadIdx.x;
+  const u32 half = tid >> 7;
+  const u32 t = tid & 127;
+  if (t == 0) {
+    u64 dd = d[half];
+    s_lo[half] = dd > nm ? (u32)(dd - nm) : 0u;
+    s_hi[half] = dd < na ? (u32)dd : na;
   }
-  return lo;
+  __syncthreads();
+  for (int round = 0; round < 8; ++round) {
+    const u32 lo = s_lo[half], hi = s_hi[half];
+    const bool any = (s_lo[0] < s_hi[0]) || (s_lo[1] < s_hi[1]);
+    if (!any) break;
+    const u64 dd = d[half];
+    const u32 span = hi - lo;
+    u32 p = 0;
+    bool pred = false;
+    if (span > 0) {
+      p = span <= 128 ? lo + t : lo + (u32)(((u64)span * t) / 128u);
+      if (span > 128 || t < span) pred = a[p] <= mk[(u32)(dd - p - 1)];
+    }
+    u64 bal = wave_ballot(pred);
+    if ((tid & 63) == 0) s_wc[tid >> 6] = (u32)__popcll(bal);
+    __syncthreads();
+    if (t == 0 && span > 0) {
+      u32 c = s_wc[2 * half] + s_wc[2 * half + 1];
+      if (span <= 128) {
+        s_lo[half] = lo + c;
+        s_hi[half] = lo + c;
+      } else if (c == 0) {
+        s_hi[half] = lo;
+      } else {
+        u32 pl = lo + (u32)(((u64)span * (c - 1)) / 128u);
+        s_lo[half] = pl + 1;
+        if (c < 128) s_hi[half] = lo + (u32)(((u64)span * c) / 128u);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < 2) out[tid] = s_lo[tid];
+  __syncthreads();
 }
 
 constexpr u32 kBadLink = 0xFFFFFFFEu;   // a link outside the pool

@@ -17,6 +17,8 @@
 // needs clearing between passes or calls.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "flix_device.hpp"
 
 namespace flix {
@@ -347,21 +349,34 @@ struct SortScratch {
   u32 epoch = 0;            // last epoch used
   u32 parity = 0;           // histogram slot of the next call
   u64 max_items = 0;        // capacity of the status array, in items
-  // optional per-kernel timing hooks (family 0: histogram, 1: one pass)
-  void (*on_begin)(void* ctx, hipStream_t st, void** tok) = nullptr;
-  void (*on_end)(void* ctx, hipStream_t st, int family, void* tok) = nullptr;
+  // optional per-kernel timing hooks (family 0: histogram, 1: one pass):
+  // on_begin hands out the start/stop events of the next dispatch
+  void (*on_begin)(void* ctx, int family, hipEvent_t* e0, hipEvent_t* e1) = nullptr;
+  void (*on_end)(void* ctx, int family, hipEvent_t e0, hipEvent_t e1) = nullptr;
   void* hook_ctx = nullptr;
 };
 
+// Kernel launch that, given events, has the dispatch itself stamp them at its
+// start and end (hipExtLaunchKernelGGL): timing then adds no marker packets
+// between kernels.  Without events it is a plain launch.
+template <typename F, typename... Args>
+inline void launch_timed(hipEvent_t e0, hipEvent_t e1, F kernel, dim3 grid, dim3 block,
+                         uint32_t shm, hipStream_t st, Args... args) {
+  if (e0 && e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, st, e0, e1, 0u, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
+}
+
 struct SortTimer {
   SortScratch& s;
-  hipStream_t st;
-  void* tok = nullptr;
-  SortTimer(SortScratch& s_, hipStream_t st_) : s(s_), st(st_) {
-    if (s.on_begin) s.on_begin(s.hook_ctx, st, &tok);
+  int fam;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SortTimer(SortScratch& s_, int fam_) : s(s_), fam(fam_) {
+    if (s.on_begin) s.on_begin(s.hook_ctx, fam, &e0, &e1);
   }
-  void end(int fam) {
-    if (s.on_end) s.on_end(s.hook_ctx, st, fam, tok);
+  void end() {
+    if (s.on_end && e0) s.on_end(s.hook_ctx, fam, e0, e1);
   }
 };
 
@@ -396,10 +411,10 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
   u32 hb = (n + 256u * 16u - 1u) / (256u * 16u);
   if (hb > 1024u) hb = 1024u;
   {
-    SortTimer t(s, st);
-    hipLaunchKernelGGL((k_radix_hist<K, RB>), dim3(hb), dim3(256), 0, st, kin, n, hist,
-                       hist_next, s.tile_ctr);
-    t.end(0);
+    SortTimer t(s, 0);
+    launch_timed(t.e0, t.e1, k_radix_hist<K, RB>, dim3(hb), dim3(256), 0, st, kin, n, hist,
+                 hist_next, s.tile_ctr);
+    t.end();
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -428,10 +443,10 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     pa.status_cl = s.status_cl;
     pa.epoch = epoch;
     pa.err = s.err;
-    SortTimer t(s, st);
-    hipLaunchKernelGGL((k_onesweep<K, V, RB, kSortNT, kSortIPT, PAY>), dim3(ntiles),
-                       dim3(kSortNT), 0, st, pa);
-    t.end(1);
+    SortTimer t(s, 1);
+    launch_timed(t.e0, t.e1, k_onesweep<K, V, RB, kSortNT, kSortIPT, PAY>, dim3(ntiles),
+                 dim3(kSortNT), 0, st, pa);
+    t.end();
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

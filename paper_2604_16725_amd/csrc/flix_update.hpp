@@ -51,6 +51,7 @@ struct SliceSmem {
   u32 live[S + 1];   // exclusive prefix of live flags
   u32 tmp[NT / 64 + 1];
   u32 part[4];
+  u32 lo[2], hiw[2], wc[4];
   u32 wbase;
   unsigned long long need;
   u32 bad;
@@ -70,21 +71,24 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
   u32& s_bad = sm.bad;
   u32& s_gstart = sm.gstart;
 
+  static_assert(NT == 256, "the cooperative cut uses 256 threads");
   const u32 tid = threadIdx.x;
   const u64 total = (u64)a.m + a.nb;
   const u64 d0 = (u64)vb * a.share;
   const u64 d1 = d0 + a.share < total ? d0 + a.share : total;
   if (vb == 0 && tid == 0) a.ctl->free_snapshot = a.ctl->free_top;
   if (tid == 0) {
-    u32 q0 = merge_path_keys(a.skeys, a.m, a.mkba, a.nb, d0);
-    s_part[0] = q0;
-    s_part[2] = (u32)(d0 - q0);
     s_need = 0;
     s_bad = 0;
-  } else if (tid == 64 % NT) {
-    u32 q1 = merge_path_keys(a.skeys, a.m, a.mkba, a.nb, d1);
-    s_part[1] = q1;
-    s_part[3] = (u32)(d1 - q1);
+  }
+  {
+    const u64 dd[2] = {d0, d1};
+    u32* cut = s_part;   // cut[0] = q0, cut[1] = q1
+    coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, dd, sm.lo, sm.hiw, sm.wc, cut);
+  }
+  if (tid == 0) {
+    s_part[2] = (u32)(d0 - s_part[0]);
+    s_part[3] = (u32)(d1 - s_part[1]);
   }
   __syncthreads();
   // cuts of a sorted batch are ordered; report anything else instead of
@@ -104,8 +108,21 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
     __syncthreads();
     return;
   }
-  if (tid == 0) {
-    s_gstart = (b0 == 0) ? 0u : upper_bound_idx<K>(a.skeys, 0u, q0, a.mkba[b0 - 1]);
+  // Slice start of local bucket 0: the keys of skeys[0, q0) above
+  // MKBA[b0 - 1] form a suffix.  The first wave probes the 64 keys below q0
+  // (lane l takes q0 - 1 - l) in the same round as the loads below; a longer
+  // suffix falls back to a binary search under the probed window.
+  if (tid < 64) {
+    u32 g = 0;
+    if (b0 != 0) {
+      const K x = a.mkba[b0 - 1];
+      const bool in = tid < q0;
+      const K kk = in ? a.skeys[q0 - 1 - tid] : K(0);
+      const u32 n_gt = (u32)__popcll(wave_ballot(in && kk > x));
+      g = q0 - n_gt;
+      if (n_gt == 64 && q0 > 64 && tid == 0) g = upper_bound_idx<K>(a.skeys, 0u, q0 - 64, x);
+    }
+    if (tid == 0) s_gstart = g;
   }
   for (u32 j = tid; j <= nq; j += NT) {
     if (j < nq || q0 + j < a.m) s_q[j] = a.skeys[q0 + j];

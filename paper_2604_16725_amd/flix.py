@@ -133,6 +133,7 @@ def load_library(path: str = LIB_PATH):
         "flix_graph_destroy": (i32, [vp]),
         "flix_drain_info": (i32, [vp, ctypes.POINTER(u32), ctypes.POINTER(u64)]),
         "flix_set_timing": (i32, [vp, i32]),
+        "flix_set_timing_only": (i32, [vp, ctypes.c_char_p]),
         "flix_epoch_prepare": (i32, [vp, u32, ctypes.POINTER(FlixEpoch), vp]),
         "flix_epoch_apply": (i32, [vp, u32, ctypes.POINTER(FlixEpoch), vp]),
         "flix_kernel_time": (i32, [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -372,8 +373,12 @@ class Store:
         self._chk(self.lib.flix_epoch_apply(self.h, slot, ctypes.byref(ep), _stream(stream)),
                   "flix_epoch_apply")
 
-    def set_timing(self, on: bool):
-        self._chk(self.lib.flix_set_timing(self.h, 1 if on else 0), "flix_set_timing")
+    def set_timing(self, on: bool, only: str | None = None):
+        """Per-kernel HIP-event timing: every family, or only ``only``."""
+        if on and only is not None:
+            self._chk(self.lib.flix_set_timing_only(self.h, only.encode()), "flix_set_timing_only")
+        else:
+            self._chk(self.lib.flix_set_timing(self.h, 1 if on else 0), "flix_set_timing")
 
     def kernel_time(self, family: str):
         ms = ctypes.c_double()
