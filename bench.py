@@ -102,6 +102,11 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
            - np.searchsorted(build_sorted, lo, side="left")).sum()
     rng = read_bytes(lo, m * (4 + vbytes) + cnt * (kbytes + vbytes), cnt)
     fam["read_apply"] = look + succ + rng
+    # cut list of each read call: one u32 per share boundary, found by a
+    # 64-ary search whose probes read one batch key and one MKBA entry each
+    ncuts = -(-(m + nb) // 512) + 1
+    rounds = int(np.ceil(np.log(max(m, 2)) / np.log(65)))
+    fam["read_cuts"] = 3 * ncuts * (4 + rounds * 64 * (kbytes + kbytes))
 
     ins = wl["insert_keys"]
     bi = np.searchsorted(mkba, ins, side="left")
@@ -360,7 +365,8 @@ def main():
         raise RuntimeError("device error during warmup")
     log("[bench] warmup done")
 
-    fams = ["sort_hist", "sort_pass", "read_apply", "slices", "insert_apply", "delete_apply"]
+    fams = ["sort_hist", "sort_pass", "read_cuts", "read_apply", "slices", "insert_apply",
+            "delete_apply"]
 
     def run_steps(k):
         torch.cuda.synchronize()

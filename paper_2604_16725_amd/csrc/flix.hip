@@ -22,10 +22,12 @@ using namespace flix;
 
 namespace {
 
-constexpr int kFamilies = 6;
+constexpr int kFamilies = 7;
 const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
-                                       "insert_apply", "delete_apply"};
-enum Family { F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5 };
+                                       "insert_apply", "delete_apply", "read_cuts"};
+enum Family {
+  F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6
+};
 
 struct Timing {
   bool on = false;
@@ -33,8 +35,8 @@ struct Timing {
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  double ms[kFamilies] = {0, 0, 0, 0, 0, 0};
-  uint64_t count[kFamilies] = {0, 0, 0, 0, 0, 0};
+  double ms[kFamilies] = {};
+  uint64_t count[kFamilies] = {};
 };
 
 }  // namespace
@@ -76,6 +78,7 @@ struct flix_store {
   void* nkeys = nullptr;
   void* nvals = nullptr;
   u32* bnodes = nullptr;
+  u32* cuts = nullptr;   // read-share cuts [(max_batch + nb_alloc) / 512 + 2]
   u32* free_ids = nullptr;
   Ctl* ctl = nullptr;
   // scratch
@@ -207,13 +210,18 @@ int alloc_pool(flix_store* s, u32 pool) {
   return FLIX_OK;
 }
 
+// Entries of the read-share cut list for batches of up to n keys over nb buckets.
+u64 cuts_for(u64 n, u64 nb) { return (n + nb) / 512u + 2u; }
+
 int alloc_dir(flix_store* s, u32 nb) {
   if (nb <= s->nb_alloc) return FLIX_OK;
   dev_free(&s->mkba);
   dev_free(&s->bnodes);
+  dev_free(&s->cuts);
   int rc;
   if ((rc = dev_alloc(&s->mkba, (u64)nb * s->ksz))) return rc;
   if ((rc = dev_alloc(&s->bnodes, (u64)nb * sizeof(u32)))) return rc;
+  if ((rc = dev_alloc(&s->cuts, (cuts_for(s->max_batch, nb) * sizeof(u32))))) return rc;
   s->nb_alloc = nb;
   return FLIX_OK;
 }
@@ -341,6 +349,17 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   a.pool = s->pool;
   a.err = &s->ctl->status;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
+  // cut list: one wave per share boundary (the list holds cuts_for(max_batch,
+  // nb_alloc) >= grid + 1 entries)
+  a.cuts = nullptr;
+  if (s->cuts && grid + 1 <= cuts_for(s->max_batch, s->nb_alloc)) {
+    const u32 ncuts = (u32)grid + 1u;
+    const TmTok tc = tm_arm(s, F_CUTS);
+    launch_timed(tc.b, tc.e, k_merge_cuts<K>, dim3((ncuts + 3) / 4), dim3(256), 0, st, skeys,
+                 (u32)n, (const K*)s->mkba, s->nb, a.share, ncuts, s->cuts);
+    tm_done(s, F_CUTS, tc);
+    a.cuts = s->cuts;
+  }
   const TmTok t = tm_arm(s, F_READ);
   launch_read2<K>(s, a, op, (u32)grid, st, t);
   tm_done(s, F_READ, t);
@@ -784,6 +803,7 @@ int check_args(flix_store* s, u64 n, std::initializer_list<const void*> ptrs) {
 
 void destroy_all(flix_store* s) {
   dev_free(&s->mkba);
+  dev_free(&s->cuts);
   dev_free(&s->hdr);
   dev_free(&s->nkeys);
   dev_free(&s->nvals);

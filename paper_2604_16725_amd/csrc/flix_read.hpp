@@ -37,6 +37,8 @@ struct ReadArgs {
   u32 maxpq;           // range output stride
   u32 pool;            // nodes in the pool (bound of every link)
   u32* err;            // sticky status word for internal errors
+  const u32* cuts;     // merge-path cut of every share boundary [nshares + 1], or
+                       // nullptr: each workgroup searches its own two cuts
 };
 
 // Cooperative merge-path cut for the two diagonals d[0], d[1] of one
@@ -88,6 +90,48 @@ __device__ void coop_merge_path(const K* a, u32 na, const K* mk, u32 nm, const u
   }
   if (tid < 2) out[tid] = s_lo[tid];
   __syncthreads();
+}
+
+// Merge-path cuts of "MKBA (+) sorted batch" at every share boundary, for
+// the read kernel: cut c is the number of batch keys among the first
+// min(c * share, m + nb) items of the merge, ties to the keys (a key equal to
+// MKBA[i] belongs to bucket i).  One wave per cut, 64-ary search: 64 probes
+// split the candidate range into 65 parts and one ballot keeps the part that
+// holds the cut (four dependent rounds for 2^21 items), so the read kernel's
+// workgroups start from one load instead of a search of their own.
+template <typename K>
+__global__ __launch_bounds__(256) void k_merge_cuts(const K* __restrict__ a, u32 na,
+                                                    const K* __restrict__ mk, u32 nm, u32 share,
+                                                    u32 ncuts, u32* __restrict__ cuts) {
+  const u32 c = blockIdx.x * 4u + (threadIdx.x >> 6);
+  const u32 lane = threadIdx.x & 63u;
+  if (c >= ncuts) return;   // whole waves
+  const u64 total = (u64)na + nm;
+  const u64 d = (u64)c * share < total ? (u64)c * share : total;
+  // the predicate a[p] <= mk[d - p - 1] holds exactly for p < cut, cut in [lo, hi]
+  u32 lo = d > nm ? (u32)(d - nm) : 0u;
+  u32 hi = d < na ? (u32)d : na;
+  while (lo < hi) {
+    const u32 span = hi - lo;
+    if (span <= 64u) {
+      bool pr = false;
+      if (lane < span) {
+        const u32 p = lo + lane;
+        pr = a[p] <= mk[(u32)(d - p - 1)];
+      }
+      lo += (u32)__popcll(wave_ballot(pr));
+      break;
+    }
+    // probes x_l = lo + floor(span * (l + 1) / 65): strictly increasing, all < hi
+    const u32 p = lo + (u32)(((u64)span * (lane + 1u)) / 65u);
+    const bool pr = a[p] <= mk[(u32)(d - p - 1)];
+    const u32 t = (u32)__popcll(wave_ballot(pr));   // probes below the cut
+    const u32 nlo = t ? lo + (u32)(((u64)span * t) / 65u) + 1u : lo;
+    const u32 nhi = t < 64u ? lo + (u32)(((u64)span * (t + 1u)) / 65u) : hi;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) cuts[c] = lo;
 }
 
 constexpr u32 kBadLink = 0xFFFFFFFEu;   // a link outside the pool

@@ -3,7 +3,8 @@
 // Same flipped structure as flix_read.hpp (Section 3.3: every bucket pulls the
 // slice of the sorted batch that falls into (MKBA[i-1], MKBA[i]]), organised
 // for wave64 latency hiding:
-//   1. merge-path cut of "MKBA (+) sorted batch" into equal shares, found by a
+//   1. merge-path cut of "MKBA (+) sorted batch" into equal shares: loaded
+//      from the cut list k_merge_cuts wrote, or (persistent drain) found by a
 //      cooperative 128-ary search (three dependent rounds instead of ~21);
 //   2. one coalesced round of loads: the share's keys, their input positions,
 //      MKBA entries and node headers (and range upper bounds);
@@ -75,7 +76,12 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
   u64 d[2];
   d[0] = (u64)vb * a.share;
   d[1] = d[0] + a.share < total ? d[0] + a.share : total;
-  coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
+  if (a.cuts) {
+    if (tid < 2) s_cut[tid] = a.cuts[vb + tid];
+    __syncthreads();
+  } else {
+    coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
+  }
   const u32 q0 = s_cut[0], q1 = s_cut[1];
   // Cuts of a sorted batch are ordered; anything else (an unsorted batch)
   // is reported instead of indexing past the share.
