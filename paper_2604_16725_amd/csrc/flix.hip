@@ -84,7 +84,7 @@ struct flix_store {
   // scratch
   void* bk[2] = {nullptr, nullptr};   // sort keys ping-pong [max_batch]
   void* bp[2] = {nullptr, nullptr};   // sort payload ping-pong [max_batch] (8-byte slots)
-  WorkItem* work = nullptr;           // [max_batch]
+  WorkItem* work = nullptr;           // [work_slots(max_batch)]
   SortScratch ss;
   Timing tm;
   // persistent drain: its own look-back words, histogram slots and control
@@ -262,10 +262,11 @@ int sort_batch_t(flix_store* s, const K* keys, const K* vals, u32 n, int pay, hi
 // Per-call counters are cleared by a one-block kernel at the start of every
 // update call (they are read by the kernels that follow on the stream).
 __global__ void k_reset_call(Ctl* ctl) {
-  ctl->need = 0;
-  ctl->call_err = 0;
-  ctl->heavy_count = 0;
-  ctl->heavy_cursor = 0;
+  if (threadIdx.x == 0) {
+    ctl->need = 0;
+    ctl->call_err = 0;
+  }
+  reset_work_regions(ctl, threadIdx.x);
 }
 
 void sort_hook_begin(void* ctx, int fam, hipEvent_t* e0, hipEvent_t* e1) {
@@ -468,6 +469,7 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   sa.cap = s->cap;
   sa.share = SliceCfg<K>::S;
   sa.work = s->work;
+  sa.rcap = work_region_cap(s->max_batch);
   sa.ctl = s->ctl;
   constexpr int SS = SliceCfg<K>::S;
   u64 grid = ((u64)n + s->nb + sa.share - 1) / sa.share;
@@ -502,6 +504,7 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   ua.chunk = upd_chunk(s);
   ua.pool = s->pool;
   ua.work = s->work;
+  ua.rcap = work_region_cap(s->max_batch);
   ua.ctl = s->ctl;
   ua.status = &s->ctl->status;
   u32 lds_items = upd_lds_items(s);
@@ -520,7 +523,7 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
 template <typename K>
 int update_batch(flix_store* s, bool insert, const void* keys, const void* vals, u64 n,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl);
   int r;
   int rc = sort_batch<K>(s, keys, vals, n, insert ? kPayValue : kPayNone, st, &r);
   if (rc) return rc;
@@ -645,11 +648,11 @@ int epoch_apply_t(flix_store* s, EpochSlot* es, const flix_epoch* e, hipStream_t
   if (e->n_update) {
     // the folded lists hold distinct keys, so deletes and upserts commute;
     // deletes go first and return nodes to the free list
-    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl);
     if ((rc = update_apply_sorted<K>(s, false, (const K*)es->del_k, nullptr, e->n_update,
                                      es->counts + 1, st)))
       return rc;
-    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(1), 0, st, s->ctl);
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl);
     if ((rc = update_apply_sorted<K>(s, true, (const K*)es->ins_k, (const K*)es->ins_v,
                                      e->n_update, es->counts, st)))
       return rc;
@@ -968,7 +971,7 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   u64 mb = cfg->max_batch;
   if ((rc = dev_alloc(&s->ctl, sizeof(Ctl))) || (rc = dev_alloc(&s->bk[0], mb * s->ksz)) ||
       (rc = dev_alloc(&s->bk[1], mb * s->ksz)) || (rc = dev_alloc(&s->bp[0], mb * 8)) ||
-      (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, mb * sizeof(WorkItem))) ||
+      (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, work_slots(mb) * sizeof(WorkItem))) ||
       (rc = dev_alloc(&s->ss.hist, 2 * 2048 * sizeof(u32))) ||
       (rc = dev_alloc(&s->ss.tile_ctr, 64)) || (rc = dev_alloc(&s->ss.err, 16))) {
     destroy_all(s);

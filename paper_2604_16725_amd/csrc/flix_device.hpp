@@ -21,8 +21,15 @@ struct alignas(16) NodeHdr {
   u32 next;   // next node of the same bucket, or kNil
 };
 
+// Regions of the update work list.  The slice workgroups of one call append
+// to kWorkRegions regions (consecutive shares to the same one), each with a
+// counter on a line of its own, so the thousands of workgroups of a call do
+// not serialise on a single address (same-address device atomics are
+// executed one at a time past the L2s).
+constexpr u32 kWorkRegions = 64;
+
 // Device control block: counters and status words owned by one store.
-struct alignas(64) Ctl {
+struct alignas(128) Ctl {
   u32 free_top;        // number of node ids on the free stack
   u32 status;          // sticky first device-detected error (negative code)
   u32 call_err;        // error raised by the pre-check of the current call
@@ -30,10 +37,82 @@ struct alignas(64) Ctl {
   u64 need;            // pre-check: upper bound of nodes the call may take
   u64 nkeys;           // number of live keys in the store
   u32 free_snapshot;   // free_top as seen before the current apply kernel
-  u32 heavy_count;     // number of buckets queued for the heavy path
-  u32 heavy_cursor;    // work-stealing cursor over the heavy list
+  u32 work_ovf;        // work items in the overflow region of the work list
+  u32 pad1;
   u32 scan_total;      // output of device-wide compaction scans
-  u64 pad1[3];
+  // per region: [0] items claimed, [1] first claim that did not fit (all
+  // ones: none), so the region holds min([0], [1]) items
+  alignas(128) u32 wreg[kWorkRegions][32];
+};
+
+// Work-list slots of a store whose batches hold at most max_batch keys:
+// kWorkRegions regions of region_cap slots, then an overflow region of
+// max_batch slots (a call never has more work items than keys).
+__host__ __device__ inline u32 work_region_cap(u64 max_batch) {
+  return (u32)((max_batch + kWorkRegions - 1) / kWorkRegions);
+}
+__host__ __device__ inline u64 work_slots(u64 max_batch) {
+  return (u64)kWorkRegions * work_region_cap(max_batch) + max_batch;
+}
+
+// Per-call reset of the work-list counters (region r by thread r).
+__device__ __forceinline__ void reset_work_regions(Ctl* ctl, u32 t) {
+  if (t < kWorkRegions) {
+    ctl->wreg[t][0] = 0;
+    ctl->wreg[t][1] = 0xFFFFFFFFu;
+  }
+  if (t == 0) ctl->work_ovf = 0;
+}
+
+// Work-list map of an apply workgroup: s_pre[r] = items in regions < r
+// (kWorkRegions + 1 entries).  All threads call; returns the item count.
+__device__ inline u32 load_work_map(const Ctl* ctl, u32* s_pre) {
+  if (threadIdx.x < kWorkRegions) {
+    const u32 lane = threadIdx.x;
+    const u32 c = ctl->wreg[lane][0], f = ctl->wreg[lane][1];
+    u32 x = c < f ? c : f;
+    for (u32 o = 1; o < kWorkRegions; o <<= 1) {
+      const u32 y = (u32)__shfl_up((int)x, o, 64);
+      if (lane >= o) x += y;
+    }
+    s_pre[lane + 1] = x;
+    if (lane == 0) s_pre[0] = 0;
+  }
+  __syncthreads();
+  return s_pre[kWorkRegions] + ctl->work_ovf;
+}
+
+// Position of an apply group in the work list: region r (kWorkRegions is the
+// overflow region, which starts at slot kWorkRegions * rcap) and the number
+// of items before it.  A group visits increasing item indices, so after one
+// binary search it only steps forward over the map.
+struct WorkCursor {
+  u32 r;
+  u32 base;   // s_pre[r]
+  __device__ void seek(const u32* s_pre, u32 i) {
+    if (i >= s_pre[kWorkRegions]) {
+      r = kWorkRegions;
+      base = s_pre[kWorkRegions];
+      return;
+    }
+    u32 lo = 0, hi = kWorkRegions;   // s_pre[lo] <= i < s_pre[hi]
+    while (hi - lo > 1) {
+      const u32 mid = (lo + hi) >> 1;
+      if (s_pre[mid] <= i) lo = mid; else hi = mid;
+    }
+    r = lo;
+    base = s_pre[lo];
+  }
+  // advance to item i (not below the current one)
+  __device__ void move(const u32* s_pre, u32 i) {
+    while (r < kWorkRegions) {
+      const u32 next = s_pre[r + 1];
+      if (next > i) break;
+      ++r;
+      base = next;
+    }
+  }
+  __device__ u32 slot(u32 i, u32 rcap) const { return r * rcap + (i - base); }
 };
 
 // Sticky status codes written by kernels (the negated C ABI error codes).

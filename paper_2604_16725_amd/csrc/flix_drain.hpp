@@ -168,7 +168,7 @@ struct DrainSmemSize {
 template <typename K, int RB, int GL, int KPL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_drain(DrainArgs<K> a) {
   extern __shared__ unsigned char smem[];
-  __shared__ unsigned long long s_counter;
+  __shared__ UpdShared s_upd;
   __shared__ u32 s_epoch;
   constexpr int R = RadixShape<K, RB>::R;
   constexpr int P = RadixShape<K, RB>::P;
@@ -224,10 +224,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const u32 slot = nz & 1u;
     ++nz;
     u32* hist = a.hist + slot * (P * R);
-    if (is_update && blk == 0 && threadIdx.x == 0) {
-      a.ctl->need = 0;
-      a.ctl->call_err = 0;
-      a.ctl->heavy_count = 0;
+    if (is_update && blk == 0) {
+      if (threadIdx.x == 0) {
+        a.ctl->need = 0;
+        a.ctl->call_err = 0;
+      }
+      reset_work_regions(a.ctl, threadIdx.x);
     }
     // ---- histogram
     radix_hist_part<K, RB>((const K*)d.keys, n, hist, blk, G,
@@ -322,6 +324,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       sa.cap = a.cap;
       sa.share = SS;
       sa.work = a.work;
+      sa.rcap = work_region_cap(a.max_batch);
       sa.ctl = a.ctl;
       const u32 nshares = (u32)(((u64)n + L.nb + SS - 1) / SS);
       for (u32 vb = blk; vb < nshares; vb += G) {
@@ -345,14 +348,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ua.chunk = a.chunk;
       ua.pool = L.pool;
       ua.work = a.work;
+      ua.rcap = work_region_cap(a.max_batch);
       ua.ctl = a.ctl;
       ua.status = &a.ctl->status;
-      if (threadIdx.x == 0) s_counter = 0;
-      __syncthreads();
       if (d.op == kOpInsert)
-        insert_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_counter);
+        insert_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_upd);
       else
-        delete_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_counter);
+        delete_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_upd);
     }
     if (grid_sync(dc, G)) return;
     if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[bi + 1] = wall_clock64();

@@ -96,20 +96,20 @@ template <typename K, int GL, int NT>
 __global__ __launch_bounds__(NT) void k_insert_counted(UpdArgs<K> a, u32 lds_items,
                                                        const u32* __restrict__ m_dev) {
   extern __shared__ unsigned char s_dyn[];
-  __shared__ unsigned long long s_added;
+  __shared__ UpdShared sh;
   a.m = *m_dev;
   if (a.m == 0) return;
-  insert_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, s_added);
+  insert_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, sh);
 }
 
 template <typename K, int GL, int NT>
 __global__ __launch_bounds__(NT) void k_delete_counted(UpdArgs<K> a, u32 lds_items,
                                                        const u32* __restrict__ m_dev) {
   extern __shared__ unsigned char s_dyn[];
-  __shared__ unsigned long long s_removed;
+  __shared__ UpdShared sh;
   a.m = *m_dev;
   if (a.m == 0) return;
-  delete_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, s_removed);
+  delete_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, sh);
 }
 
 }  // namespace flix

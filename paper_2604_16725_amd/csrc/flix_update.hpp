@@ -39,7 +39,8 @@ struct SliceArgs {
   const u32* bnodes;
   u32 cap;
   u32 share;
-  WorkItem* work;
+  WorkItem* work;   // [work_slots(max_batch)]
+  u32 rcap;         // work_region_cap(max_batch)
   Ctl* ctl;
 };
 
@@ -163,7 +164,8 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
   }
   __syncthreads();
 
-  // Append touched buckets to the work list (one atomic per workgroup).
+  // Append touched buckets to the work list (one atomic per workgroup, on
+  // the counter of this share's region).
   // Local bucket lb < nbl has the global slice [q0 + s, q0 + e), except that
   // bucket 0 starts at gstart (<= q0).  Local bucket nbl is left to the next
   // share.
@@ -205,7 +207,21 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
   u32 tot_items;
   u32 ex = block_exclusive_scan<NT>(cnt, s_tmp, &tot_items);
   if (INSERT && need) atomicAdd(&s_need, need);
-  if (tid == 0 && tot_items) s_wbase = atomicAdd(&a.ctl->heavy_count, tot_items);
+  if (tid == 0 && tot_items) {
+    // claim slots in this share's region (consecutive shares share a region,
+    // so the list stays in bucket order); a claim that does not fit records
+    // where the region's valid items end and goes to the overflow region
+    const u32 nsh = (u32)((total + a.share - 1) / a.share);
+    const u32 spr = (nsh + kWorkRegions - 1) / kWorkRegions;
+    const u32 r = vb / spr;
+    const u32 old = atomicAdd(&a.ctl->wreg[r][0], tot_items);
+    if ((u64)old + tot_items <= a.rcap) {
+      s_wbase = r * a.rcap + old;
+    } else {
+      atomicMin(&a.ctl->wreg[r][1], old);
+      s_wbase = kWorkRegions * a.rcap + atomicAdd(&a.ctl->work_ovf, tot_items);
+    }
+  }
   __syncthreads();
   u32 w = s_wbase + ex;
 #pragma unroll
@@ -328,8 +344,16 @@ struct UpdArgs {
   u32 chunk;          // batch items staged per merge step (<= per-group LDS room)
   u32 pool;           // node pool size
   const WorkItem* work;
+  u32 rcap;           // work_region_cap(max_batch)
   Ctl* ctl;
   u32* status;        // sticky status word (== &ctl->status)
+};
+
+// Workgroup-shared state of the apply kernels: a key counter and the map of
+// the work list's regions.
+struct UpdShared {
+  unsigned long long counter;
+  u32 pre[kWorkRegions + 1];
 };
 
 // Header write that leaves the fence alone when the caller never loaded it.
@@ -365,10 +389,11 @@ __device__ __forceinline__ u32 piece_of(u32 pos, u32 c, u32 k) {
 // its last key and the last one keeps X's fence and link.
 // ---------------------------------------------------------------------------
 // Insert work of workgroup `blk` of `nblk` (groups stride over the work list).
-// `s_dyn`: per-group LDS regions; `s_added`: one workgroup-shared counter.
+// `s_dyn`: per-group LDS regions; `sh`: workgroup-shared counter and work map.
 template <typename K, int GL, int NT>
 __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nblk,
-                             unsigned char* s_dyn, unsigned long long& s_added) {
+                             unsigned char* s_dyn, UpdShared& sh) {
+  unsigned long long& s_added = sh.counter;
   constexpr int GPB = NT / GL;
   Group<GL> g;
   const u32 gid = threadIdx.x / GL;
@@ -390,16 +415,21 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
     __syncthreads();
     return;
   }
-  const u32 nitems = ctl->heavy_count;
+  const u32 nitems = load_work_map(ctl, sh.pre);
   const u32 f = a.cap / 2;
   u64 added = 0;
   const u32 stride = nblk * GPB;
   u32 it = blk * GPB + gid;
   WorkItem wnext;
-  if (it < nitems) wnext = a.work[it];
+  WorkCursor cur;
+  cur.seek(sh.pre, it);
+  if (it < nitems) wnext = a.work[cur.slot(it, a.rcap)];
   for (; it < nitems; it += stride) {
     const WorkItem w = wnext;
-    if (it + stride < nitems) wnext = a.work[it + stride];   // prefetch
+    if (it + stride < nitems) {   // prefetch
+      cur.move(sh.pre, it + stride);
+      wnext = a.work[cur.slot(it + stride, a.rcap)];
+    }
     u32 X = w.b;
     NodeHdr hX;
     bool fence_known = true;
@@ -671,8 +701,8 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
 template <typename K, int GL, int NT>
 __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items) {
   extern __shared__ unsigned char s_dyn[];
-  __shared__ unsigned long long s_added;
-  insert_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, s_added);
+  __shared__ UpdShared sh;
+  insert_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -687,7 +717,8 @@ __global__ __launch_bounds__(NT) void k_insert_apply(UpdArgs<K> a, u32 lds_items
 // ---------------------------------------------------------------------------
 template <typename K, int GL, int NT>
 __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nblk,
-                             unsigned char* s_dyn, unsigned long long& s_removed) {
+                             unsigned char* s_dyn, UpdShared& sh) {
+  unsigned long long& s_removed = sh.counter;
   constexpr int GPB = NT / GL;
   Group<GL> g;
   const u32 gid = threadIdx.x / GL;
@@ -696,16 +727,21 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
   K* bk = ak + a.cap;                                                   // slice keys [chunk]
   if (threadIdx.x == 0) s_removed = 0;
   __syncthreads();
-  const u32 nitems = a.ctl->heavy_count;
+  const u32 nitems = load_work_map(a.ctl, sh.pre);
   const u32 f = a.cap / 2;
   u64 removed = 0;
   const u32 stride = nblk * GPB;
   u32 it = blk * GPB + gid;
   WorkItem wnext;
-  if (it < nitems) wnext = a.work[it];
+  WorkCursor cur;
+  cur.seek(sh.pre, it);
+  if (it < nitems) wnext = a.work[cur.slot(it, a.rcap)];
   for (; it < nitems; it += stride) {
     const WorkItem w = wnext;
-    if (it + stride < nitems) wnext = a.work[it + stride];   // prefetch
+    if (it + stride < nitems) {   // prefetch
+      cur.move(sh.pre, it + stride);
+      wnext = a.work[cur.slot(it + stride, a.rcap)];
+    }
     // predecessor state (P), kept in registers; P == kNil before the head
     u32 P = kNil;
     NodeHdr hP;
@@ -893,8 +929,8 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
 template <typename K, int GL, int NT>
 __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items) {
   extern __shared__ unsigned char s_dyn[];
-  __shared__ unsigned long long s_removed;
-  delete_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, s_removed);
+  __shared__ UpdShared sh;
+  delete_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, sh);
 }
 
 }  // namespace flix

@@ -312,3 +312,32 @@ def test_error_paths_leave_store_unchanged():
     o2.insert(small, small)
     assert t.status() == 0
     assert_same_contents(t, o2, kb, "after ENOMEM then insert")
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_work_list_region_overflow(kb):
+    """Small max_batch (region capacity 64 work items) on a store of 65536
+    buckets: uniform batches fill some regions past capacity after their first
+    share, and a batch over consecutive buckets overflows every region, so the
+    work items of the overflow region and the valid prefix of each region are
+    both exercised; contents and reads match the oracle after every batch."""
+    log(f"work-list overflow kb={kb}")
+    rng = np.random.default_rng(77 + kb)
+    s, o = new_pair(kb, cap=16, lanes=16, max_batch=4096)
+    k0 = np.unique(_keys(rng, kb, 1 << 19))
+    v0 = rng.integers(0, 1 << 30, k0.size, dtype=np.uint64).astype(ktype(kb))
+    s.bulk_load(to_dev(k0), to_dev(v0))
+    o.bulk_load(k0, v0)
+    srt = np.sort(k0)
+    dense = srt[1000:1000 + 8 * 4096:8] + ktype(kb)(1)   # one key per bucket, consecutive buckets
+    for name, ks in [("uniform", _keys(rng, kb, 4096)), ("dense", dense)]:
+        vs = rng.integers(0, 1 << 30, ks.size, dtype=np.uint64).astype(ktype(kb))
+        s.insert(to_dev(ks), to_dev(vs))
+        o.insert(ks, vs)
+        assert s.status() == 0
+        assert_same_contents(s, o, kb, f"{name} insert")
+        check_reads(s, o, kb, ks[:2000], maxpq=4, where=f"{name} reads")
+        s.delete(to_dev(ks))
+        o.delete(ks)
+        assert s.status() == 0
+        assert_same_contents(s, o, kb, f"{name} delete")
