@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace flix {
@@ -20,6 +21,8 @@ struct alignas(16) NodeHdr {
   u32 size;   // live keys, stored sorted in slots [0, size)
   u32 next;   // next node of the same bucket, or kNil
 };
+static_assert(sizeof(NodeHdr) == 16 && offsetof(NodeHdr, size) == 8 && offsetof(NodeHdr, next) == 12,
+              "size and next are read together as one 8-byte word");
 
 // Regions of the update work list.  The slice workgroups of one call append
 // to kWorkRegions regions (consecutive shares to the same one), each with a

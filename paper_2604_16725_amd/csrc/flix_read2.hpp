@@ -95,23 +95,50 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
   if (nq == 0) return;
   const u32 nbl = b1 - b0;
 
-  // One round of coalesced loads.
-  for (u32 j = tid; j < nq; j += NT) {
-    s_q[j] = a.skeys[q0 + j];
-    u32 ix = a.sidx[q0 + j];
-    s_idx[j] = ix;
-    if (op == kOpRange) s_hi[j] = a.hi[ix];
-  }
-  for (u32 i = tid; i <= nbl; i += NT) {
-    if (i < nbl) s_mk[i] = a.mkba[b0 + i];
-    u32 sz = 0, nx = kNil;
-    if (b0 + i < a.nb) {
-      NodeHdr h = a.hdr[b0 + i];
-      sz = h.size;
-      nx = h.next;
+  // One round of coalesced loads: a share holds at most S keys and S + 1
+  // bucket entries, and every load of a thread is issued before its first
+  // LDS store (range upper bounds follow, indexed by the input positions).
+  constexpr u32 RQ = (S + NT - 1) / NT;
+  constexpr u32 RBK = (S + 1 + NT - 1) / NT;
+  {
+    K qk[RQ];
+    u32 qi[RQ];
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if (j < nq) {
+        qk[r] = a.skeys[q0 + j];
+        qi[r] = a.sidx[q0 + j];
+      }
     }
-    s_hsz[i] = sz;
-    s_hnx[i] = nx;
+    K mk[RBK];
+    u64 hw[RBK];   // size | next << 32 of the bucket's head node
+#pragma unroll
+    for (u32 r = 0; r < RBK; ++r) {
+      const u32 i = tid + r * NT;
+      hw[r] = (u64)kNil << 32;
+      if (i < nbl) mk[r] = a.mkba[b0 + i];
+      if (i <= nbl && b0 + i < a.nb)
+        hw[r] = *reinterpret_cast<const u64*>(&a.hdr[b0 + i].size);
+    }
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if (j < nq) {
+        s_q[j] = qk[r];
+        s_idx[j] = qi[r];
+        if (op == kOpRange) s_hi[j] = a.hi[qi[r]];
+      }
+    }
+#pragma unroll
+    for (u32 r = 0; r < RBK; ++r) {
+      const u32 i = tid + r * NT;
+      if (i <= nbl) {
+        if (i < nbl) s_mk[i] = mk[r];
+        s_hsz[i] = (u32)hw[r];
+        s_hnx[i] = (u32)(hw[r] >> 32);
+      }
+    }
   }
   __syncthreads();
 
@@ -241,8 +268,35 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
   }
   __syncthreads();
 
-  // Phase B: one lane per key.
+  // Phase B: one lane per key.  Lookups and successors resolved in phase A
+  // issue all of a thread's value (and key) loads before its output writes.
   const K NF = key_max<K>();
+  if (op != kOpRange) {
+    K rv[RQ], rk[RQ];
+    u32 pc[RQ];
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      pc[r] = j < nq ? s_pos[j] : kPosSlow;
+      const u32 pos = pc[r] & 0xFFFFu;
+      rv[r] = NF;
+      rk[r] = NF;
+      if (pos != kPosSlow && pos != kPosMiss) {
+        const u64 at = (u64)(b0 + (pc[r] >> 16)) * a.cap + pos;
+        rv[r] = a.nvals[at];
+        if (op == kOpSuccessor) rk[r] = a.nkeys[at];
+      }
+    }
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if ((pc[r] & 0xFFFFu) != kPosSlow) {
+        const u32 orig = s_idx[j];
+        a.out_v[orig] = rv[r];
+        if (op == kOpSuccessor) a.out_k[orig] = rk[r];
+      }
+    }
+  }
   for (u32 j = tid; j < nq; j += NT) {
     const u32 code = s_pos[j];
     const u32 lb = code >> 16;
@@ -252,11 +306,8 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
     const K x = s_q[j];
     if (pos != kPosSlow) {
       const u64 nb_ = (u64)b * a.cap;
-      if (op == kOpLookup) {
-        a.out_v[orig] = (pos == kPosMiss) ? NF : a.nvals[nb_ + pos];
-      } else if (op == kOpSuccessor) {
-        a.out_k[orig] = a.nkeys[nb_ + pos];
-        a.out_v[orig] = a.nvals[nb_ + pos];
+      if (op != kOpRange) {
+        continue;   // written above
       } else {
         const u32 cnt = s_cnt[j];
         const u32 wn = cnt < a.maxpq ? cnt : a.maxpq;
@@ -332,8 +383,11 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
   }
 }
 
+// Eight waves per SIMD (64 VGPRs): the kernel is latency-bound, and the
+// register budget, not LDS, otherwise caps it at six workgroups per CU.
 template <typename K, int NT, int S, int GL, int KPL, int U>
-__global__ __launch_bounds__(NT) void k_read_apply2(ReadArgs<K> a, int op) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_read_apply2(
+    ReadArgs<K> a, int op) {
   __shared__ ReadSmem<K, S, NT> sm;
   read_share<K, NT, S, GL, KPL, U>(a, op, blockIdx.x, sm);
 }

@@ -48,19 +48,36 @@ struct HistSmem {
   u32 sh[RadixShape<K, RB>::P * RadixShape<K, RB>::R];
 };
 
-// Histogram part `part` of `nparts` (grid-stride over the keys).
+// Keys per thread and chunk of the histogram: one chunk's loads are all
+// issued before its first count, so a chunk costs one memory round trip.
+constexpr int kHistIPT = 16;
+
+// Histogram part `part` of `nparts` (grid-stride over chunks of 256 x
+// kHistIPT keys; each of a chunk's kHistIPT loads is coalesced across the
+// workgroup).
 template <typename K, int RB>
 __device__ void radix_hist_part(const K* __restrict__ keys, u32 n, u32* __restrict__ hist,
                                 u32 part, u32 nparts, HistSmem<K, RB>& sm) {
   constexpr int R = RadixShape<K, RB>::R;
   constexpr int P = RadixShape<K, RB>::P;
+  constexpr u32 CH = 256u * kHistIPT;
   u32* sh = sm.sh;
   for (int i = threadIdx.x; i < P * R; i += 256) sh[i] = 0;
   __syncthreads();
-  for (u32 i = part * 256u + threadIdx.x; i < n; i += nparts * 256u) {
-    K k = keys[i];
+  for (u64 base = (u64)part * CH; base < n; base += (u64)nparts * CH) {
+    K kk[kHistIPT];
 #pragma unroll
-    for (int p = 0; p < P; ++p) atomicAdd(&sh[p * R + digit_of<K, RB>(k, p * RB)], 1u);
+    for (int c = 0; c < kHistIPT; ++c) {
+      const u64 i = base + (u64)c * 256u + threadIdx.x;
+      kk[c] = i < n ? keys[i] : K(0);
+    }
+#pragma unroll
+    for (int c = 0; c < kHistIPT; ++c) {
+      if (base + (u64)c * 256u + threadIdx.x < n) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) atomicAdd(&sh[p * R + digit_of<K, RB>(kk[c], p * RB)], 1u);
+      }
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < P * R; i += 256)
@@ -408,7 +425,7 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
   u32* hist = s.hist + (size_t)s.parity * (P * R);
   u32* hist_next = s.hist + (size_t)(s.parity ^ 1u) * (P * R);
   s.parity ^= 1u;
-  u32 hb = (n + 256u * 16u - 1u) / (256u * 16u);
+  u32 hb = (n + 256u * kHistIPT - 1u) / (256u * kHistIPT);
   if (hb > 1024u) hb = 1024u;
   {
     SortTimer t(s, 0);

@@ -125,10 +125,33 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
     }
     if (tid == 0) s_gstart = g;
   }
-  for (u32 j = tid; j <= nq; j += NT) {
-    if (j < nq || q0 + j < a.m) s_q[j] = a.skeys[q0 + j];
+  {
+    // every load of a thread is issued before its first LDS store (the
+    // share holds at most S keys plus the one after it, and S buckets)
+    constexpr u32 RQ = (S + 1 + NT - 1) / NT;
+    constexpr u32 RM = (S + NT - 1) / NT;
+    K qk[RQ], mk[RM];
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if (j <= nq && (j < nq || q0 + j < a.m)) qk[r] = a.skeys[q0 + j];
+    }
+#pragma unroll
+    for (u32 r = 0; r < RM; ++r) {
+      const u32 i = tid + r * NT;
+      if (i < nbl) mk[r] = a.mkba[b0 + i];
+    }
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if (j <= nq && (j < nq || q0 + j < a.m)) s_q[j] = qk[r];
+    }
+#pragma unroll
+    for (u32 r = 0; r < RM; ++r) {
+      const u32 i = tid + r * NT;
+      if (i < nbl) s_mk[i] = mk[r];
+    }
   }
-  for (u32 i = tid; i < nbl; i += NT) s_mk[i] = a.mkba[b0 + i];
   __syncthreads();
   for (u32 lb = tid; lb <= nbl; lb += NT)
     s_e[lb] = (lb < nbl) ? upper_bound_idx<K>(s_q, 0u, nq, s_mk[lb]) : nq;
