@@ -392,7 +392,9 @@ struct SliceCfg<u64> {
 
 constexpr int kUpdNT = 256;
 
-u32 upd_chunk(const flix_store* s) { return std::max<u32>(s->cap, 64u); }
+// Batch items staged per merge step: half a node (at least 64).  With
+// capacity 128 a group's LDS is then 1.5 KB, so six workgroups fit a CU.
+u32 upd_chunk(const flix_store* s) { return std::max<u32>(s->cap / 2, 64u); }
 u32 upd_lds_items(const flix_store* s) { return s->cap + upd_chunk(s); }
 
 // m_dev: null for a list of host-known length n; otherwise the length is read

@@ -93,8 +93,9 @@ __global__ __launch_bounds__(NT) void k_slices_counted(SliceArgs<K> a, const u32
 }
 
 template <typename K, int GL, int NT>
-__global__ __launch_bounds__(NT) void k_insert_counted(UpdArgs<K> a, u32 lds_items,
-                                                       const u32* __restrict__ m_dev) {
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 6 : 1))) void k_insert_counted(
+    UpdArgs<K> a, u32 lds_items, const u32* __restrict__ m_dev) {
   extern __shared__ unsigned char s_dyn[];
   __shared__ UpdShared sh;
   a.m = *m_dev;

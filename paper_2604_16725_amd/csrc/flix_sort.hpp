@@ -338,13 +338,17 @@ __device__ void onesweep_tile(const PassArgs<K, V>& pa, u32 tile,
   // Write out in digit order: consecutive threads write consecutive slots of
   // one digit's run.
   u32 valid_n = (n - tile0) < (u32)TILE ? (n - tile0) : (u32)TILE;
-  for (u32 i = tid; i < valid_n; i += NT) {
-    K kk = s_k[i];
-    u32 d = digit_of<K, RB>(kk, shift);
-    u32 g = s_gbase[d] + (i - s_lstart[d]);
-    if (g < n) {   // always true for a consistent histogram
-      kout[g] = kk;
-      if (PAY != kPayNone) vout[g] = s_v[i];
+#pragma unroll
+  for (u32 r = 0; r < (u32)IPT; ++r) {
+    const u32 i = tid + r * (u32)NT;
+    if (i < valid_n) {
+      K kk = s_k[i];
+      u32 d = digit_of<K, RB>(kk, shift);
+      u32 g = s_gbase[d] + (i - s_lstart[d]);
+      if (g < n) {   // always true for a consistent histogram
+        kout[g] = kk;
+        if (PAY != kPayNone) vout[g] = s_v[i];
+      }
     }
   }
   __syncthreads();
