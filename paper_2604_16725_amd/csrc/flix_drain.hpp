@@ -149,9 +149,9 @@ template <typename K, int RB, int GL, int KPL>
 struct DrainSmemSize {
   static constexpr int U = KPL >= 16 ? 2 : 4;
   static constexpr size_t hist = sizeof(HistSmem<K, RB>);
-  static constexpr size_t pass_idx = sizeof(OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayIndex>);
-  static constexpr size_t pass_val = sizeof(OnesweepSmem<K, K, RB, kSortNT, kSortIPT, kPayValue>);
-  static constexpr size_t pass_none = sizeof(OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayNone>);
+  static constexpr size_t pass_idx = sizeof(OnesweepSmem<K, u32, RB, kDrainSortNT, kDrainSortIPT, kPayIndex>);
+  static constexpr size_t pass_val = sizeof(OnesweepSmem<K, K, RB, kDrainSortNT, kDrainSortIPT, kPayValue>);
+  static constexpr size_t pass_none = sizeof(OnesweepSmem<K, u32, RB, kDrainSortNT, kDrainSortIPT, kPayNone>);
   static constexpr size_t read = sizeof(ReadSmem<K, 512, 256>);
   static constexpr size_t slices = sizeof(SliceSmem<K, (sizeof(K) == 4 ? 1024 : 512), 256>);
   static constexpr size_t fixed() {
@@ -256,16 +256,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
         pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
         for (u32 t = blk; t < ntiles; t += G)
-          onesweep_tile<K, K, RB, kSortNT, kSortIPT, kPayValue>(
-              pa, t, *reinterpret_cast<OnesweepSmem<K, K, RB, kSortNT, kSortIPT, kPayValue>*>(smem));
+          onesweep_tile<K, K, RB, kDrainSortNT, kDrainSortIPT, kPayValue>(
+              pa, t, *reinterpret_cast<OnesweepSmem<K, K, RB, kDrainSortNT, kDrainSortIPT, kPayValue>*>(smem));
       } else if (d.op == kOpDelete) {
         PassArgs<K, u32> pa;
         pa.kin = ki; pa.vin = nullptr; pa.kout = ko; pa.vout = nullptr;
         pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
         pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
         for (u32 t = blk; t < ntiles; t += G)
-          onesweep_tile<K, u32, RB, kSortNT, kSortIPT, kPayNone>(
-              pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayNone>*>(smem));
+          onesweep_tile<K, u32, RB, kDrainSortNT, kDrainSortIPT, kPayNone>(
+              pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kDrainSortNT, kDrainSortIPT, kPayNone>*>(smem));
       } else {
         PassArgs<K, u32> pa;
         pa.kin = ki;
@@ -275,8 +275,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         pa.n = n; pa.shift = (u32)(p * RB); pa.hist_p = hist + p * R;
         pa.status = a.status; pa.status_cl = a.status_cl; pa.epoch = epoch; pa.err = &dc->err;
         for (u32 t = blk; t < ntiles; t += G)
-          onesweep_tile<K, u32, RB, kSortNT, kSortIPT, kPayIndex>(
-              pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kSortNT, kSortIPT, kPayIndex>*>(smem));
+          onesweep_tile<K, u32, RB, kDrainSortNT, kDrainSortIPT, kPayIndex>(
+              pa, t, *reinterpret_cast<OnesweepSmem<K, u32, RB, kDrainSortNT, kDrainSortIPT, kPayIndex>*>(smem));
       }
       if (grid_sync(dc, G)) return;
     }

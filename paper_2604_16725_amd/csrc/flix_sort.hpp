@@ -401,9 +401,15 @@ struct SortTimer {
   }
 };
 
-constexpr int kSortNT = 256;
-constexpr int kSortIPT = 8;
+// Pass kernel shape: 2048-item tiles of 512 threads x 4 items (eight waves
+// share a tile's ranking and scatter; measured faster than 256 x 8 and
+// 1024 x 2).  The persistent drain's 256-thread workgroups take the same
+// tiles as 256 x 8, so both read the same look-back words.
+constexpr int kSortNT = 512;
+constexpr int kSortIPT = 4;
 constexpr int kSortTile = kSortNT * kSortIPT;
+constexpr int kDrainSortNT = 256;
+constexpr int kDrainSortIPT = kSortTile / kDrainSortNT;
 
 inline u64 sort_status_words(u64 max_items, int rb) {
   return ((max_items + kSortTile - 1) / kSortTile + 1) * (u64)(1 << rb);
