@@ -87,7 +87,13 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     # sort: 5 sorts per step (lookup, successor, range, insert, delete)
     fam["sort_hist"] = 5 * m * kbytes
     pay = [4, 4, 4, vbytes, 0]
-    fam["sort_pass"] = sum(P * m * 2 * (kbytes + p) for p in pay)
+    # batches of up to 2^22 keys with 8-bit digits: one device-wide pass on
+    # the top digit, then one read and one write of every pair by the
+    # per-run sort; otherwise P device-wide passes
+    local = rb == 8 and m <= (1 << 22)
+    fam["sort_pass"] = sum((1 if local else P) * m * 2 * (kbytes + p) for p in pay)
+    if local:
+        fam["sort_local"] = sum(m * 2 * (kbytes + p) for p in pay)
 
     def read_bytes(keys, extra_out, val_reads):
         t = touched(keys)
@@ -365,8 +371,8 @@ def main():
         raise RuntimeError("device error during warmup")
     log("[bench] warmup done")
 
-    fams = ["sort_hist", "sort_pass", "read_cuts", "read_apply", "slices", "insert_apply",
-            "delete_apply"]
+    fams = ["sort_hist", "sort_pass", "sort_local", "read_cuts", "read_apply", "slices",
+            "insert_apply", "delete_apply"]
 
     def run_steps(k):
         torch.cuda.synchronize()

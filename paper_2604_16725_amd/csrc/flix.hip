@@ -22,12 +22,14 @@ using namespace flix;
 
 namespace {
 
-constexpr int kFamilies = 7;
+constexpr int kFamilies = 8;
 const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
-                                       "insert_apply", "delete_apply", "read_cuts"};
+                                       "insert_apply", "delete_apply", "read_cuts", "sort_local"};
 enum Family {
-  F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6
+  F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6,
+  F_LOCAL = 7
 };
+int sort_family(int fam) { return fam == 0 ? F_HIST : fam == 1 ? F_PASS : F_LOCAL; }
 
 struct Timing {
   bool on = false;
@@ -270,7 +272,7 @@ __global__ void k_reset_call(Ctl* ctl) {
 }
 
 void sort_hook_begin(void* ctx, int fam, hipEvent_t* e0, hipEvent_t* e1) {
-  const TmTok t = tm_arm(static_cast<flix_store*>(ctx), fam == 0 ? F_HIST : F_PASS);
+  const TmTok t = tm_arm(static_cast<flix_store*>(ctx), sort_family(fam));
   *e0 = t.b;
   *e1 = t.e;
 }
@@ -278,7 +280,7 @@ void sort_hook_end(void* ctx, int fam, hipEvent_t e0, hipEvent_t e1) {
   TmTok t;
   t.b = e0;
   t.e = e1;
-  tm_done(static_cast<flix_store*>(ctx), fam == 0 ? F_HIST : F_PASS, t);
+  tm_done(static_cast<flix_store*>(ctx), sort_family(fam), t);
 }
 
 template <typename K>

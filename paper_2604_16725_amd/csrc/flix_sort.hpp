@@ -360,17 +360,388 @@ __global__ __launch_bounds__(NT) void k_onesweep(PassArgs<K, V> pa) {
   onesweep_tile<K, V, RB, NT, IPT, PAY>(pa, blockIdx.x, sm);
 }
 
+// ---------------------------------------------------------------------------
+// Batches of at most kLocalMaxItems items with 8-bit digits: one onesweep pass
+// on the most significant digit splits the batch into 256 runs (stably), then
+// k_local_sort gives every run one workgroup that sorts it on the remaining
+// digits.  A run of at most kLocalCap items stays in LDS for all of its
+// passes; a longer one (skewed keys) is sorted in global memory, chunk by
+// chunk, in the two buffers of its run.  Every pass is a stable counting sort
+// whose ranks come from wave ballots over wave-striped items (as in a
+// onesweep tile), so the sort stays stable.  This replaces P - 1 device-wide
+// passes, each with its look-back, by work that stays inside one CU.
+constexpr int kLocalNT = 1024;
+constexpr int kLocalIPT = 8;
+constexpr u32 kLocalCap = kLocalNT * kLocalIPT;
+constexpr u32 kLocalMaxItems = 1u << 22;
+
+constexpr int kLocalMaxPass = 7;   // digits below the top one (64-bit keys)
+
+struct LocalSortHead {
+  u32 wc[kLocalNT / 64][256];   // per-wave digit counts, then their prefixes
+  u32 dstart[256];              // first slot of every digit in the run or chunk
+  u32 off[256];                 // running digit offsets (chunked runs)
+  u32 hist[kLocalMaxPass][256]; // digit counts of every pass (chunked runs)
+  u32 tmp[kLocalNT / 64 + 1];
+  u32 range[2];
+};
+constexpr size_t kLocalHeadBytes = (sizeof(LocalSortHead) + 15) & ~size_t(15);
+
+template <typename K, typename V, int PAY>
+constexpr size_t local_sort_lds() {
+  return kLocalHeadBytes + (size_t)kLocalCap * sizeof(K) +
+         (PAY == kPayNone ? 0 : (size_t)kLocalCap * sizeof(V));
+}
+
+// Stable ranks of the kLocalIPT wave-striped items of each thread among the
+// items of its wave with the same digit; per-wave digit counts go to
+// h.wc[wave] (cleared by the caller).
+template <typename K>
+__device__ __forceinline__ void local_rank(const K (&key)[kLocalIPT], u32 nvalid_base, u32 n,
+                                           u32 shift, LocalSortHead& h, u32 (&rank)[kLocalIPT]) {
+  const u32 w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+#pragma unroll
+  for (int k = 0; k < kLocalIPT; ++k) {
+    const u32 li = nvalid_base + w * 64u * kLocalIPT + (u32)k * 64u + lane;
+    const bool valid = li < n;
+    const u32 d = digit_of<K, 8>(key[k], shift);
+    u64 m = wave_ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const u64 bb = wave_ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const u32 below = rank_below(m);
+    const u32 cnt = (u32)__popcll(m);
+    const u32 base = valid ? h.wc[w][d] : 0u;
+    rank[k] = base + below;
+    if (valid && below == cnt - 1) h.wc[w][d] = base + cnt;
+  }
+}
+
+// Turns h.wc into exclusive prefixes across waves (per digit) and returns,
+// in thread d < 256, the digit's total.  All threads call.
+__device__ __forceinline__ u32 local_wave_prefix(LocalSortHead& h) {
+  constexpr int WAVES = kLocalNT / 64;
+  const u32 tid = threadIdx.x;
+  u32 tot = 0;
+  if (tid < 256u) {
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) {
+      const u32 c = h.wc[ww][tid];
+      h.wc[ww][tid] = tot;
+      tot += c;
+    }
+  }
+  return tot;
+}
+
+// Sorts the cnt (<= kLocalCap) wave-striped items held in registers on digits
+// 0..npass-1, leaving them sorted and wave-striped in registers; s_k / s_v
+// are the LDS staging arrays.  All threads call.
+template <typename K, typename V, int PAY>
+__device__ void local_lds_passes(K (&key)[kLocalIPT], V (&pay)[kLocalIPT], u32 cnt, u32 npass,
+                                 LocalSortHead& h, K* s_k, V* s_v) {
+  constexpr int IPT = kLocalIPT;
+  const u32 tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
+  u32 rank[IPT];
+  for (u32 p = 0; p < npass; ++p) {
+    const u32 shift = p * 8u;
+    for (u32 i = tid; i < (kLocalNT / 64) * 256u; i += kLocalNT) (&h.wc[0][0])[i] = 0;
+    __syncthreads();
+    local_rank<K>(key, 0u, cnt, shift, h, rank);
+    __syncthreads();
+    const u32 tot = local_wave_prefix(h);
+    u32 dummy;
+    const u32 ds = block_exclusive_scan<kLocalNT>(tid < 256u ? tot : 0u, h.tmp, &dummy);
+    if (tid < 256u) h.dstart[tid] = ds;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+      if (li < cnt) {
+        const u32 d = digit_of<K, 8>(key[k], shift);
+        const u32 pos = h.dstart[d] + h.wc[w][d] + rank[k];
+        s_k[pos] = key[k];
+        if (PAY != kPayNone) s_v[pos] = pay[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+      if (li < cnt) {
+        key[k] = s_k[li];
+        if (PAY != kPayNone) pay[k] = s_v[li];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Stable rank of the flagged wave-striped items of a chunk among the flagged
+// items (input order); returns the chunk's flagged count.  All threads call.
+__device__ __forceinline__ u32 local_class_rank(const bool (&is)[kLocalIPT],
+                                                u32 (&rank)[kLocalIPT], LocalSortHead& h) {
+  const u32 tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
+  u32 run = 0;
+#pragma unroll
+  for (int k = 0; k < kLocalIPT; ++k) {
+    const u64 m = wave_ballot(is[k]);
+    rank[k] = run + rank_below(m);
+    run += (u32)__popcll(m);
+  }
+  if (lane == 0) h.wc[0][w] = run;
+  __syncthreads();
+  u32 pre = 0, total = 0;
+  for (u32 ww = 0; ww < kLocalNT / 64; ++ww) {
+    const u32 c = h.wc[0][ww];
+    if (ww < w) pre += c;
+    total += c;
+  }
+#pragma unroll
+  for (int k = 0; k < kLocalIPT; ++k) rank[k] += pre;
+  __syncthreads();
+  return total;
+}
+
+template <typename K, typename V, int PAY>
+__global__ __launch_bounds__(kLocalNT) void k_local_sort(K* __restrict__ ka, V* __restrict__ va,
+                                                         K* __restrict__ kb, V* __restrict__ vb,
+                                                         const u32* __restrict__ top_count,
+                                                         u32 npass, u32 n, u32* __restrict__ err) {
+  extern __shared__ unsigned char lsm[];
+  LocalSortHead& h = *reinterpret_cast<LocalSortHead*>(lsm);
+  K* s_k = reinterpret_cast<K*>(lsm + kLocalHeadBytes);
+  V* s_v = reinterpret_cast<V*>(lsm + kLocalHeadBytes + (size_t)kLocalCap * sizeof(K));
+  constexpr int IPT = kLocalIPT;
+  const u32 tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
+  // this run: the blockIdx.x-th run of the most significant digit
+  {
+    const u32 c = tid < 256u ? top_count[tid] : 0u;
+    u32 total;
+    const u32 ex = block_exclusive_scan<kLocalNT>(c, h.tmp, &total);
+    if (tid == blockIdx.x) {
+      h.range[0] = ex;
+      h.range[1] = c;
+    }
+    __syncthreads();
+  }
+  const u32 start = h.range[0], cnt = h.range[1];
+  if (cnt == 0 || npass > (u32)kLocalMaxPass) return;
+  if ((u64)start + cnt > n) {   // histogram inconsistent with the keys: never expected
+    if (tid == 0) atomicOr(err, 2u);
+    return;
+  }
+  K key[IPT];
+  V pay[IPT];
+  u32 rank[IPT];
+  if (cnt <= kLocalCap) {
+    // the run lives in registers and LDS for all passes
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+      if (li < cnt) {
+        key[k] = ka[start + li];
+        if (PAY != kPayNone) pay[k] = va[start + li];
+      } else {
+        key[k] = K(0);
+      }
+    }
+    local_lds_passes<K, V, PAY>(key, pay, cnt, npass, h, s_k, s_v);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+      if (li < cnt) {
+        kb[start + li] = key[k];
+        if (PAY != kPayNone) vb[start + li] = pay[k];
+      }
+    }
+    return;
+  }
+  // A long run is usually one repeated key (skewed batches).  With X the key
+  // in the middle of the run: the items other than X are gathered in order
+  // into LDS; if they fit, they are sorted there and written around the
+  // block of X items, which keep their input order (stable).
+  {
+    const K X = ka[start + cnt / 2];
+    u32 nrest = 0;
+    bool fits = true;
+    for (u32 base = 0; base < cnt; base += kLocalCap) {
+      bool rest[IPT];
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base + w * 64u * IPT + (u32)k * 64u + lane;
+        const bool valid = li < cnt;
+        key[k] = valid ? ka[start + li] : X;
+        if (PAY != kPayNone && valid) pay[k] = va[start + li];
+        rest[k] = valid && key[k] != X;
+      }
+      const u32 tot = local_class_rank(rest, rank, h);
+      if (nrest + tot > kLocalCap) {   // uniform: tot and nrest are workgroup-wide
+        fits = false;
+        break;
+      }
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        if (rest[k]) {
+          s_k[nrest + rank[k]] = key[k];
+          if (PAY != kPayNone) s_v[nrest + rank[k]] = pay[k];
+        }
+      }
+      nrest += tot;
+    }
+    if (fits) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+        if (li < nrest) {
+          key[k] = s_k[li];
+          if (PAY != kPayNone) pay[k] = s_v[li];
+        }
+      }
+      __syncthreads();
+      local_lds_passes<K, V, PAY>(key, pay, nrest, npass, h, s_k, s_v);
+      // items below X come first, then the X block, then the rest
+      u32 mine = 0;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+        if (li < nrest && key[k] < X) ++mine;
+      }
+      u32 nlt;
+      (void)block_exclusive_scan<kLocalNT>(mine, h.tmp, &nlt);
+      const u32 neq = cnt - nrest;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
+        if (li < nrest) {
+          const u32 o = li < nlt ? li : li + neq;
+          kb[start + o] = key[k];
+          if (PAY != kPayNone) vb[start + o] = pay[k];
+        }
+      }
+      // the X items in input order
+      u32 xbase = 0;
+      for (u32 base = 0; base < cnt; base += kLocalCap) {
+        bool isx[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          const u32 li = base + w * 64u * IPT + (u32)k * 64u + lane;
+          const bool valid = li < cnt;
+          isx[k] = false;
+          if (valid) {
+            isx[k] = ka[start + li] == X;
+            if (PAY != kPayNone) pay[k] = va[start + li];
+          }
+        }
+        const u32 tot = local_class_rank(isx, rank, h);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          if (isx[k]) {
+            kb[start + nlt + xbase + rank[k]] = X;
+            if (PAY != kPayNone) vb[start + nlt + xbase + rank[k]] = pay[k];
+          }
+        }
+        xbase += tot;
+      }
+      return;
+    }
+    __syncthreads();
+  }
+  // A long run: each pass reads one buffer of the run and writes the other
+  // (npass is odd, so the last pass writes the second buffer), chunk by
+  // chunk in order.  The digit counts of every pass come from one sweep over
+  // the run first (a pass only permutes the run).
+  for (u32 i = tid; i < npass * 256u; i += kLocalNT) (&h.hist[0][0])[i] = 0;
+  __syncthreads();
+  for (u32 base = 0; base < cnt; base += kLocalCap) {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = base + (u32)k * kLocalNT + tid;
+      key[k] = li < cnt ? ka[start + li] : K(0);
+    }
+    // Skewed runs repeat a few keys: the wave's most common case, the first
+    // valid lane's digit, is added once with its lane count, the other lanes
+    // add one each (LDS atomics on one address would serialise the wave).
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const bool valid = base + (u32)k * kLocalNT + tid < cnt;
+      const u64 vm = wave_ballot(valid);
+      if (vm == 0) continue;   // uniform across the wave
+      const int src = __ffsll((unsigned long long)vm) - 1;
+      for (u32 p = 0; p < npass; ++p) {
+        const u32 d = digit_of<K, 8>(key[k], p * 8u);
+        const u32 d0 = (u32)__shfl((int)d, src, 64);
+        const u64 same = wave_ballot(valid && d == d0);
+        if ((int)lane == src) atomicAdd(&h.hist[p][d0], (u32)__popcll(same));
+        if (valid && d != d0) atomicAdd(&h.hist[p][d], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  for (u32 p = 0; p < npass; ++p) {
+    const u32 shift = p * 8u;
+    K* ik = (p & 1u) ? kb + start : ka + start;
+    V* iv = (p & 1u) ? vb + start : va + start;
+    K* ok = (p & 1u) ? ka + start : kb + start;
+    V* ov = (p & 1u) ? va + start : vb + start;
+    {
+      const u32 c = tid < 256u ? h.hist[p][tid] : 0u;
+      u32 dummy;
+      const u32 ex = block_exclusive_scan<kLocalNT>(c, h.tmp, &dummy);
+      if (tid < 256u) h.off[tid] = ex;
+      __syncthreads();
+    }
+    for (u32 base = 0; base < cnt; base += kLocalCap) {
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base + w * 64u * IPT + (u32)k * 64u + lane;
+        if (li < cnt) {
+          key[k] = ik[li];
+          if (PAY != kPayNone) pay[k] = iv[li];
+        } else {
+          key[k] = K(0);
+        }
+      }
+      for (u32 i = tid; i < (kLocalNT / 64) * 256u; i += kLocalNT) (&h.wc[0][0])[i] = 0;
+      __syncthreads();
+      local_rank<K>(key, base, cnt, shift, h, rank);
+      __syncthreads();
+      const u32 tot = local_wave_prefix(h);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base + w * 64u * IPT + (u32)k * 64u + lane;
+        if (li < cnt) {
+          const u32 d = digit_of<K, 8>(key[k], shift);
+          const u32 pos = h.off[d] + h.wc[w][d] + rank[k];
+          ok[pos] = key[k];
+          if (PAY != kPayNone) ov[pos] = pay[k];
+        }
+      }
+      __syncthreads();
+      if (tid < 256u) h.off[tid] += tot;
+      __syncthreads();
+    }
+  }
+}
+
 // Scratch shared by every sort call of one store.
 struct SortScratch {
   u32* hist = nullptr;      // [2][P*R] ping-pong histogram slots
   u64* status = nullptr;    // [max_tiles * R]
   u64* status_cl = nullptr; // [max_tiles / cluster * R]
   u32* tile_ctr = nullptr;  // [16] per-pass tile ticket counters (cleared by k_radix_hist)
-  u32* err = nullptr;       // sticky sort error bits (1: look-back wait gave up, 2: bad ticket)
+  u32* err = nullptr;       // sticky sort error bits (1: look-back wait gave up, 2: runs
+                            // that do not fit the batch)
   u32 epoch = 0;            // last epoch used
   u32 parity = 0;           // histogram slot of the next call
   u64 max_items = 0;        // capacity of the status array, in items
-  // optional per-kernel timing hooks (family 0: histogram, 1: one pass):
+  // optional per-kernel timing hooks (family 0: histogram, 1: one pass,
+  // 2: local run sort):
   // on_begin hands out the start/stop events of the next dispatch
   void (*on_begin)(void* ctx, int family, hipEvent_t* e0, hipEvent_t* e1) = nullptr;
   void (*on_end)(void* ctx, int family, hipEvent_t e0, hipEvent_t e1) = nullptr;
@@ -445,7 +816,10 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int p = 0; p < P; ++p) {
+  // Small batches with 8-bit digits: one onesweep pass on the top digit, then
+  // the runs are sorted on the other digits by k_local_sort (result in k1).
+  const bool local = RB == 8 && n <= kLocalMaxItems && ((P - 1) & 1) == 1;
+  for (int p = local ? P - 1 : 0; p < P; ++p) {
     if (s.epoch >= (1u << 30) - 1u) {
       e = hipMemsetAsync(s.status, 0, sort_status_words(s.max_items, RB) * sizeof(u64), st);
       if (e != hipSuccess) return e;
@@ -454,10 +828,11 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
       s.epoch = 0;
     }
     const u32 epoch = ++s.epoch;
-    const K* ki = (p == 0) ? kin : ((p & 1) ? k0 : k1);
-    const V* vi = (p == 0) ? vin : ((p & 1) ? v0 : v1);
-    K* ko = (p & 1) ? k1 : k0;
-    V* vo = (p & 1) ? v1 : v0;
+    const bool first = local || p == 0;
+    const K* ki = first ? kin : ((p & 1) ? k0 : k1);
+    const V* vi = first ? vin : ((p & 1) ? v0 : v1);
+    K* ko = (local || !(p & 1)) ? k0 : k1;
+    V* vo = (local || !(p & 1)) ? v0 : v1;
     PassArgs<K, V> pa;
     pa.kin = ki;
     pa.vin = vi;
@@ -476,6 +851,24 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     t.end();
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if (local) {
+    constexpr size_t lds = local_sort_lds<K, V, PAY>();
+    static bool lds_set = false;
+    if (!lds_set) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_local_sort<K, V, PAY>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      lds_set = true;
+    }
+    SortTimer t(s, 2);
+    launch_timed(t.e0, t.e1, k_local_sort<K, V, PAY>, dim3(R), dim3(kLocalNT), (uint32_t)lds, st,
+                 k0, v0, k1, v1, (const u32*)(hist + (P - 1) * R), (u32)(P - 1), n, s.err);
+    t.end();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    *result_buf = 1;
+    return hipSuccess;
   }
   *result_buf = ((P - 1) & 1) ? 1 : 0;
   return hipSuccess;

@@ -60,6 +60,69 @@ def test_sort_single_digit_keys_take_copy_pass():
     assert np.array_equal(to_host(ko, 64), k[ref])
 
 
+@pytest.mark.parametrize("kb", [32, 64])
+def test_sort_skewed_top_digit_runs(kb):
+    """Batches below 2^22 keys are split on the top 8-bit digit and every run
+    is sorted by one workgroup: runs longer than the workgroup's LDS take the
+    chunked global-memory path.  Here one top digit holds ~60% of the keys
+    (many duplicates among them), others are uniform or empty."""
+    from paper_2604_16725_amd.flix import Store
+    log(f"skewed top digit kb={kb}")
+    s = Store(key_bits=kb, capacity=64, radix_bits=8, max_batch=1 << 18)
+    rng = np.random.default_rng(11 + kb)
+    n = (1 << 17) + 3
+    top = np.uint64(0x5A) << np.uint64(kb - 8)
+    low = rng.integers(0, 1 << 12, int(n * 0.6), dtype=np.uint64)
+    k = np.concatenate([top + low, _keys(rng, kb, n - low.size).astype(np.uint64)])
+    k = rng.permutation(k).astype(ktype(kb))
+    ko, io = s.sort_pairs(to_dev(k))
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
+    assert np.array_equal(to_host(ko, kb), k[ref])
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_sort_dominant_key_run(kb):
+    """A top-digit run made mostly of one repeated key (a Zipf-skewed batch):
+    the repeated key's items keep their input order between the sorted
+    smaller and larger keys of the run."""
+    from paper_2604_16725_amd.flix import Store
+    log(f"dominant key kb={kb}")
+    s = Store(key_bits=kb, capacity=64, radix_bits=8, max_batch=1 << 18)
+    rng = np.random.default_rng(23 + kb)
+    top = np.uint64(0x3C) << np.uint64(kb - 8)
+    x = top + np.uint64(777)
+    near = top + rng.integers(0, 1 << (kb - 9), 3000, dtype=np.uint64)
+    k = np.concatenate([np.full(60000, x, dtype=np.uint64), near, near[:500],
+                        _keys(rng, kb, 60000).astype(np.uint64)])
+    k = rng.permutation(k).astype(ktype(kb))
+    ko, io = s.sort_pairs(to_dev(k))
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
+    assert np.array_equal(to_host(ko, kb), k[ref])
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_insert_repeated_key_last_wins(kb):
+    """An insert batch with one key repeated 2^15 times among others: the last
+    occurrence's value wins (the batch sort is stable on the long run)."""
+    log(f"repeated insert key kb={kb}")
+    rng = np.random.default_rng(31 + kb)
+    s, o = new_pair(kb, cap=64, lanes=16, max_batch=1 << 16)
+    k0 = np.unique(_keys(rng, kb, 1 << 14))
+    v0 = rng.integers(0, 1 << 30, k0.size, dtype=np.uint64).astype(ktype(kb))
+    s.bulk_load(to_dev(k0), to_dev(v0))
+    o.bulk_load(k0, v0)
+    x = k0[k0.size // 2]
+    ks = np.concatenate([np.full(1 << 15, x, dtype=ktype(kb)), _keys(rng, kb, 2000)])
+    ks = rng.permutation(ks)
+    vs = rng.integers(0, 1 << 30, ks.size, dtype=np.uint64).astype(ktype(kb))
+    s.insert(to_dev(ks), to_dev(vs))
+    o.insert(ks, vs)
+    assert s.status() == 0
+    assert_same_contents(s, o, kb, "repeated insert")
+
+
 # ---------------------------------------------------------------------------
 def test_bulk_load_layout_follows_build_rule():
     g = json.load(open(os.path.join(GOLDEN, "initial_build_example.json")))
