@@ -446,6 +446,8 @@ def main():
         reps = max(5, args.steps)
 
         def timeit(name, fn, nops):
+            fn()   # one untimed call: first-use costs stay out of the samples
+            torch.cuda.synchronize()
             evs = []
             for _ in range(reps):
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
