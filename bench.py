@@ -17,6 +17,7 @@ HBM roofline of the dominant kernel (algorithmic bytes / its average duration
 from HIP events), and the CPU oracle timed on a bounded sample as a baseline.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -448,13 +449,17 @@ def main():
         def timeit(name, fn, nops):
             fn()   # one untimed call: first-use costs stay out of the samples
             torch.cuda.synchronize()
-            evs = []
-            for _ in range(reps):
-                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                fn()
-                b.record()
-                evs.append((a, b))
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(reps)]
+            # no collector pause between an event and the launches it brackets
+            gc.disable()
+            try:
+                for a, b in evs:
+                    a.record()
+                    fn()
+                    b.record()
+            finally:
+                gc.enable()
             torch.cuda.synchronize()
             ms = np.array([a.elapsed_time(b) for a, b in evs])
             breakdown[name] = {"Mops_s": round(nops / (np.median(ms) / 1000) / 1e6, 1),

@@ -264,9 +264,10 @@ const char* flix_last_error(void);
  * flix_kernel_time returns the summed milliseconds and launch count since the
  * last reset.  Each family is one kernel: "sort_hist" (digit histograms),
  * "sort_pass" (one onesweep pass), "sort_local" (the per-run sort of batches
- * of up to 2^22 keys after their top-digit pass), "read_apply" (lookup/successor/range
- * bucket kernel), "read_cuts" (merge-path cuts of the read shares), "slices"
- * (update slice discovery and node budget), "insert_apply", "delete_apply".  flix_set_timing(s, enable) times every
+ * of up to 2^22 keys after their top-digit pass), "read_apply"
+ * (lookup/successor/range bucket kernel), "read_cuts" (merge-path cuts of the
+ * read shares), "slices" (update slice discovery and node budget),
+ * "insert_apply", "delete_apply".  flix_set_timing(s, enable) times every
  * family (enable != 0) or none; flix_set_timing_only(s, family) times only
  * the named family, leaving the other launches uninstrumented (FLIX_EINVAL
  * for an unknown name).  Both reset the sums.  Host-side and synchronous with
