@@ -352,13 +352,13 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   a.pool = s->pool;
   a.err = &s->ctl->status;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
-  // cut list: one wave per share boundary (the list holds cuts_for(max_batch,
+  // cut list: half a wave per share boundary (the list holds cuts_for(max_batch,
   // nb_alloc) >= grid + 1 entries)
   a.cuts = nullptr;
   if (s->cuts && grid + 1 <= cuts_for(s->max_batch, s->nb_alloc)) {
     const u32 ncuts = (u32)grid + 1u;
     const TmTok tc = tm_arm(s, F_CUTS);
-    launch_timed(tc.b, tc.e, k_merge_cuts<K>, dim3((ncuts + 3) / 4), dim3(256), 0, st, skeys,
+    launch_timed(tc.b, tc.e, k_merge_cuts<K>, dim3((ncuts + 7) / 8), dim3(256), 0, st, skeys,
                  (u32)n, (const K*)s->mkba, s->nb, a.share, ncuts, s->cuts);
     tm_done(s, F_CUTS, tc);
     a.cuts = s->cuts;

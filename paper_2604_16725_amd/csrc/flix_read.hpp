@@ -95,17 +95,19 @@ __device__ void coop_merge_path(const K* a, u32 na, const K* mk, u32 nm, const u
 // Merge-path cuts of "MKBA (+) sorted batch" at every share boundary, for
 // the read kernel: cut c is the number of batch keys among the first
 // min(c * share, m + nb) items of the merge, ties to the keys (a key equal to
-// MKBA[i] belongs to bucket i).  One wave per cut, 64-ary search: 64 probes
-// split the candidate range into 65 parts and one ballot keeps the part that
-// holds the cut (four dependent rounds for 2^21 items), so the read kernel's
-// workgroups start from one load instead of a search of their own.
+// MKBA[i] belongs to bucket i).  Half a wave per cut, 32-ary search: 32
+// probes split the candidate range into 33 parts and one ballot keeps the
+// part that holds the cut (four dependent rounds for 2^21 items, each probe a
+// cache line), so the read kernel's workgroups start from one load instead
+// of a search of their own.
 template <typename K>
 __global__ __launch_bounds__(256) void k_merge_cuts(const K* __restrict__ a, u32 na,
                                                     const K* __restrict__ mk, u32 nm, u32 share,
                                                     u32 ncuts, u32* __restrict__ cuts) {
-  const u32 c = blockIdx.x * 4u + (threadIdx.x >> 6);
-  const u32 lane = threadIdx.x & 63u;
-  if (c >= ncuts) return;   // whole waves
+  const u32 c = blockIdx.x * 8u + (threadIdx.x >> 5);
+  const u32 lane = threadIdx.x & 31u;
+  const u64 half = 0xFFFFFFFFull << (32u * ((threadIdx.x >> 5) & 1u));
+  if (c >= ncuts) return;   // whole half-waves
   const u64 total = (u64)na + nm;
   const u64 d = (u64)c * share < total ? (u64)c * share : total;
   // the predicate a[p] <= mk[d - p - 1] holds exactly for p < cut, cut in [lo, hi]
@@ -113,21 +115,21 @@ __global__ __launch_bounds__(256) void k_merge_cuts(const K* __restrict__ a, u32
   u32 hi = d < na ? (u32)d : na;
   while (lo < hi) {
     const u32 span = hi - lo;
-    if (span <= 64u) {
+    if (span <= 32u) {
       bool pr = false;
       if (lane < span) {
         const u32 p = lo + lane;
         pr = a[p] <= mk[(u32)(d - p - 1)];
       }
-      lo += (u32)__popcll(wave_ballot(pr));
+      lo += (u32)__popcll(wave_ballot(pr) & half);
       break;
     }
-    // probes x_l = lo + floor(span * (l + 1) / 65): strictly increasing, all < hi
-    const u32 p = lo + (u32)(((u64)span * (lane + 1u)) / 65u);
+    // probes x_l = lo + floor(span * (l + 1) / 33): strictly increasing, all < hi
+    const u32 p = lo + (u32)(((u64)span * (lane + 1u)) / 33u);
     const bool pr = a[p] <= mk[(u32)(d - p - 1)];
-    const u32 t = (u32)__popcll(wave_ballot(pr));   // probes below the cut
-    const u32 nlo = t ? lo + (u32)(((u64)span * t) / 65u) + 1u : lo;
-    const u32 nhi = t < 64u ? lo + (u32)(((u64)span * (t + 1u)) / 65u) : hi;
+    const u32 t = (u32)__popcll(wave_ballot(pr) & half);   // probes below the cut
+    const u32 nlo = t ? lo + (u32)(((u64)span * t) / 33u) + 1u : lo;
+    const u32 nhi = t < 32u ? lo + (u32)(((u64)span * (t + 1u)) / 33u) : hi;
     lo = nlo;
     hi = nhi;
   }
