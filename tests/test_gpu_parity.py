@@ -81,6 +81,23 @@ def test_sort_skewed_top_digit_runs(kb):
     assert np.array_equal(to_host(ko, kb), k[ref])
 
 
+@pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 1])
+def test_sort_at_the_per_run_limit(n):
+    """2^22 keys still take the top-digit pass and the per-run sort (runs of
+    ~16K items, above the LDS run size, take the chunked path); one more key
+    takes the onesweep passes."""
+    from paper_2604_16725_amd.flix import Store
+    log(f"sort at the per-run limit n={n}")
+    s = Store(key_bits=32, capacity=64, radix_bits=8, max_batch=(1 << 22) + 1)
+    rng = np.random.default_rng(n % 97)
+    k = _keys(rng, 32, n)
+    k[: n // 8] = k[n // 8: n // 4]   # duplicates: stability is visible
+    ko, io = s.sort_pairs(to_dev(k))
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
+    assert np.array_equal(to_host(ko, 32), k[ref])
+
+
 @pytest.mark.parametrize("kb", [32, 64])
 def test_sort_dominant_key_run(kb):
     """A top-digit run made mostly of one repeated key (a Zipf-skewed batch):
