@@ -137,6 +137,12 @@ __device__ __forceinline__ u32 rank_below(u64 m) {
 
 __device__ __forceinline__ u64 wave_ballot(bool p) { return __ballot(p); }
 
+// Orders a wave's LDS writes before its later LDS reads (by any of its lanes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Agent-scope relaxed atomics for words other workgroups poll.
 __device__ __forceinline__ u64 ld_agent(const u64* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -301,11 +301,6 @@ struct Group {
   }
 };
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 // Re-reads of node data that the same wave wrote earlier in this kernel.  The
 // writer and the reader are lanes of one wave, so a workgroup-scope fence
 // between them is enough; these loads are workgroup-scope atomics so the
