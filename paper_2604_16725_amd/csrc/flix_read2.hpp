@@ -207,15 +207,17 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
           for (u32 j = s + gl; j < e; j += GL) s_pos[j] = (lb << 16) | kPosSlow;
           continue;
         }
+        K prev = K(0);
         for (u32 j = s; j < e; ++j) {
           const K x = s_q[j];
           // a repeated key (skewed batches) takes the previous key's answer;
           // that answer was written to LDS earlier by a lane of this wave
-          if (op != kOpRange && j > s && x == s_q[j - 1]) {
+          if (op != kOpRange && j > s && x == prev) {
             wave_lds_sync();
             if (gl == 0) s_pos[j] = s_pos[j - 1];
             continue;
           }
+          prev = x;
           if (op == kOpLookup) {
             int hit = -1;
 #pragma unroll
