@@ -207,17 +207,23 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
           for (u32 j = s + gl; j < e; j += GL) s_pos[j] = (lb << 16) | kPosSlow;
           continue;
         }
-        K prev = K(0);
+        K prev = K(0), prev_hi = K(0);
         for (u32 j = s; j < e; ++j) {
           const K x = s_q[j];
-          // a repeated key (skewed batches) takes the previous key's answer;
-          // that answer was written to LDS earlier by a lane of this wave
-          if (op != kOpRange && j > s && x == prev) {
+          const K hi = (op == kOpRange) ? s_hi[j] : K(0);
+          // a repeated query (skewed batches) takes the previous query's
+          // answer; that answer was written to LDS earlier by a lane of this
+          // wave (a range also needs the same upper bound)
+          if (j > s && x == prev && hi == prev_hi) {
             wave_lds_sync();
-            if (gl == 0) s_pos[j] = s_pos[j - 1];
+            if (gl == 0) {
+              s_pos[j] = s_pos[j - 1];
+              if (op == kOpRange) s_cnt[j] = s_cnt[j - 1];
+            }
             continue;
           }
           prev = x;
+          prev_hi = hi;
           if (op == kOpLookup) {
             int hit = -1;
 #pragma unroll
@@ -235,7 +241,6 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
             // so the lanes whose first key is below x form a prefix of L
             // lanes and the bound lies in lane L-1: one ballot over first
             // keys plus that lane's own count.
-            const K hi = (op == kOpRange) ? s_hi[j] : K(0);
             const bool v0 = gl * KPL < size;
             u32 c_lt = 0, c_le = 0;
 #pragma unroll
