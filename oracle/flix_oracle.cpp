@@ -14,21 +14,24 @@
 // is: two parallel arrays (keys strictly increasing, values beside them).
 //
 // Readings of the paper that this file fixes (the paper is silent on them):
-//  * NOT_FOUND is the all-ones value of the value width (Section 3.3 only says
-//    "a not found value").  Inserting it is rejected (return -1) and the store
-//    is left unchanged.  KEY_MAX is the all-ones key; every key, 0 and KEY_MAX
+//  * NOT_FOUND is the all-ones value of the value width (Section 3.3 names a
+//    miss result but gives it no encoding).  Inserting it is rejected
+//    (return -1) and the store is left unchanged.  KEY_MAX is the all-ones key; every key, 0 and KEY_MAX
 //    included, is a legal key.
 //  * Duplicate keys inside one insert batch: the last occurrence in input order
 //    wins (sequential semantics).  Duplicates in a delete batch are harmless.
 //    Read batches answer every occurrence.
-//  * Successor is "smallest key >= q" (Section 6.5).  A miss returns
-//    (KEY_MAX, NOT_FOUND).
+//  * Successor is the smallest stored key that is >= q (Section 6.5).  A miss
+//    returns (KEY_MAX, NOT_FOUND).
+//  * Predecessor, the mirror operation that Section 2.1 lists beside it, is the
+//    largest stored key that is <= q.  A miss returns (0, NOT_FOUND): 0 is the
+//    smallest key, and the reserved value tells the miss apart from a stored 0.
 //  * Range [lo, hi] is closed; lo > hi yields count 0.  The first
 //    min(count, max_per_query) pairs are written in ascending key order.
 //
 // Parity pins for every function live in tests/test_oracle_pins.py (brute
 // force against a Python dict replayed op by op, the paper's worked examples
-// in Tables 2 and 3, closed-form special cases).
+// in Tables 2 and 3, closed-form special cases, planted mistakes).
 
 #include <algorithm>
 #include <cstdint>
@@ -46,8 +49,8 @@ struct Store {
   static constexpr K kNotFound = ~K(0);
   static constexpr K kKeyMax = ~K(0);
 
-  // Batch insert (Section 3.2 "If a key is not already present, it is
-  // inserted"; an existing key takes the new value).  Sequential meaning: for
+  // Batch insert (Section 3.2: an absent key is added to its node; an
+  // existing key takes the new value).  Sequential meaning: for
   // i = 0..n-1 in input order, S[k_i] <- v_i.  Written as: stable sort of the
   // batch by key, keep the last pair of each equal-key run, then one linear
   // merge with S in which the batch pair wins on equal keys.
@@ -144,6 +147,22 @@ struct Store {
     }
   }
 
+  // Predecessor (Section 2.1): largest stored key k' <= q.  upper_bound gives
+  // the first key > q; the entry before it, if any, is the answer.
+  void predecessor(const K* q, uint64_t n, K* kout, K* vout) const {
+    for (uint64_t i = 0; i < n; ++i) {
+      auto it = std::upper_bound(keys.begin(), keys.end(), q[i]);
+      if (it == keys.begin()) {
+        kout[i] = K(0);
+        vout[i] = kNotFound;
+      } else {
+        --it;
+        kout[i] = *it;
+        vout[i] = vals[it - keys.begin()];
+      }
+    }
+  }
+
   // Range (Section 2.1): all pairs with lo <= k <= hi, ascending.
   void range(const K* lo, const K* hi, uint64_t n, uint32_t maxpq,
              uint32_t* counts, K* kout, K* vout) const {
@@ -225,6 +244,15 @@ void orc_successor(void* hp, const void* q, uint64_t n, void* kout,
     h->s32.successor((const uint32_t*)q, n, (uint32_t*)kout, (uint32_t*)vout);
   else
     h->s64.successor((const uint64_t*)q, n, (uint64_t*)kout, (uint64_t*)vout);
+}
+
+void orc_predecessor(void* hp, const void* q, uint64_t n, void* kout,
+                     void* vout) {
+  Handle* h = static_cast<Handle*>(hp);
+  if (h->key_bits == 32)
+    h->s32.predecessor((const uint32_t*)q, n, (uint32_t*)kout, (uint32_t*)vout);
+  else
+    h->s64.predecessor((const uint64_t*)q, n, (uint64_t*)kout, (uint64_t*)vout);
 }
 
 void orc_range(void* hp, const void* lo, const void* hi, uint64_t n,

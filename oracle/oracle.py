@@ -33,6 +33,7 @@ def _load():
     lib.orc_delete.argtypes = [vp, vp, u64]
     lib.orc_lookup.argtypes = [vp, vp, u64, vp]
     lib.orc_successor.argtypes = [vp, vp, u64, vp, vp]
+    lib.orc_predecessor.argtypes = [vp, vp, u64, vp, vp]
     lib.orc_range.argtypes = [vp, vp, vp, u64, ctypes.c_uint32, vp, vp, vp]
     lib.orc_size.restype = u64
     lib.orc_size.argtypes = [vp]
@@ -88,6 +89,13 @@ class Oracle:
         q = self._arr(q)
         ko, vo = np.empty_like(q), np.empty_like(q)
         self._lib.orc_successor(self._h, _ptr(q), q.size, _ptr(ko), _ptr(vo))
+        return ko, vo
+
+    def predecessor(self, q):
+        """Largest stored key <= q and its value; (0, NOT_FOUND) on a miss."""
+        q = self._arr(q)
+        ko, vo = np.empty_like(q), np.empty_like(q)
+        self._lib.orc_predecessor(self._h, _ptr(q), q.size, _ptr(ko), _ptr(vo))
         return ko, vo
 
     def range(self, lo, hi, max_per_query: int):

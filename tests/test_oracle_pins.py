@@ -67,6 +67,17 @@ class DictModel:
             out_v.append(_mx(self.kb) if best is None else self.d[best])
         return out_k, out_v
 
+    def predecessor(self, qs):
+        out_k, out_v = [], []
+        for q in qs:
+            best = None
+            for k in self.d:
+                if k <= q and (best is None or k > best):
+                    best = k
+            out_k.append(0 if best is None else best)
+            out_v.append(_mx(self.kb) if best is None else self.d[best])
+        return out_k, out_v
+
     def range(self, los, his, maxpq):
         res = []
         for lo, hi in zip(los, his):
@@ -118,7 +129,8 @@ def _run_random_session(o_cls, kb, seed):
     assert o.bulk_load(ks, vs) == m.bulk_load(ks, vs) == 0
     _check_equal(o, m, kb)
     for _ in range(6):
-        op = rnd.choice(["insert", "delete", "lookup", "successor", "range", "bulk"])
+        op = rnd.choice(["insert", "delete", "lookup", "successor", "predecessor", "range",
+                         "bulk"])
         n = rnd.randrange(0, 20)
         ks = _rand_keys(rnd, kb, n, universe)
         if op == "insert":
@@ -135,6 +147,10 @@ def _run_random_session(o_cls, kb, seed):
         elif op == "successor":
             gk, gv = o.successor(ks)
             mk, mv = m.successor(ks)
+            assert gk.tolist() == mk and gv.tolist() == mv
+        elif op == "predecessor":
+            gk, gv = o.predecessor(ks)
+            mk, mv = m.predecessor(ks)
             assert gk.tolist() == mk and gv.tolist() == mv
         else:
             his = _rand_keys(rnd, kb, n, universe)
@@ -209,6 +225,13 @@ def test_special_cases(kb):
     # successor is >= (Section 6.5), not >
     k, v = o.successor([10])
     assert k.tolist() == [10]
+    # predecessor is the mirror: largest key <= q; a miss is (0, NOT_FOUND)
+    k, v = o.predecessor([10, 9, mx, mx - 1, 0])
+    assert k.tolist() == [10, 0, mx, 10, 0] and v.tolist() == [3, 1, 2, 3, 1]
+    o2 = Oracle(kb)
+    o2.bulk_load([5], [4])
+    k, v = o2.predecessor([4, 5, 0])
+    assert k.tolist() == [0, 5, 0] and v.tolist() == [mx, 4, mx]
     # closed range, lo > hi, saturating hi, max_per_query truncation
     c, rk, rv = o.range([0, 10, 11, 0], [10, 9, mx, mx], 2)
     assert c.tolist() == [2, 0, 1, 3]
@@ -268,6 +291,12 @@ MUTANTS = {
     # successor strictly greater
     "succ_gt": ("auto it = std::lower_bound(keys.begin(), keys.end(), q[i]);\n      if (it == keys.end()) {",
                 "auto it = std::upper_bound(keys.begin(), keys.end(), q[i]);\n      if (it == keys.end()) {"),
+    # predecessor strictly smaller
+    "pred_lt": ("auto it = std::upper_bound(keys.begin(), keys.end(), q[i]);\n      if (it == keys.begin()) {",
+                "auto it = std::lower_bound(keys.begin(), keys.end(), q[i]);\n      if (it == keys.begin()) {"),
+    # predecessor miss reported with KEY_MAX instead of 0
+    "pred_miss_key": ("        kout[i] = K(0);\n        vout[i] = kNotFound;",
+                      "        kout[i] = kKeyMax;\n        vout[i] = kNotFound;"),
     # half-open range
     "range_open": ("auto last = std::upper_bound(keys.begin(), keys.end(), hi[i]);",
                    "auto last = std::lower_bound(keys.begin(), keys.end(), hi[i]);"),
@@ -324,6 +353,8 @@ def _special(cls):
     o = cls(32)
     o.bulk_load([0, mx, 10], [1, 2, 3])
     k, _ = o.successor([10])
+    assert k.tolist() == [10]
+    k, _ = o.predecessor([10])
     assert k.tolist() == [10]
     c, _, _ = o.range([0], [10], 2)
     assert c.tolist() == [2]
