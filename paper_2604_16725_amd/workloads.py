@@ -219,6 +219,29 @@ def read_path(n_keys: int = 1 << 26, batch: int = 1 << 20, range_len: int = 16,
     return out
 
 
+def _sorted_union(present: np.ndarray, add: np.ndarray) -> np.ndarray:
+    """np.union1d(present, add) for a sorted, duplicate-free ``present``, in
+    O(n + m log m): the new distinct keys are inserted at their positions."""
+    s = np.unique(add)
+    pos = np.searchsorted(present, s)
+    inb = pos < present.size
+    dup = np.zeros(s.size, dtype=bool)
+    dup[inb] = present[pos[inb]] == s[inb]
+    return np.insert(present, pos[~dup], s[~dup])
+
+
+def _sorted_difference(present: np.ndarray, drop: np.ndarray) -> np.ndarray:
+    """np.setdiff1d(present, drop) for a sorted, duplicate-free ``present``."""
+    d = np.sort(drop)
+    pos = np.searchsorted(present, d)
+    inb = pos < present.size
+    hit = np.zeros(d.size, dtype=bool)
+    hit[inb] = present[pos[inb]] == d[inb]
+    keep = np.ones(present.size, dtype=bool)
+    keep[pos[hit]] = False
+    return present[keep]
+
+
 class UpdateHeavy:
     """Update-heavy workload: u64 keys/values, node capacity 128.
 
@@ -268,7 +291,7 @@ class UpdateHeavy:
                 ins = np.concatenate([ins, self.ks.fresh(extra)])
             rng.shuffle(ins)
         ins_v = values_for(ins, seed_for(self.cfg, r + 1, STREAM_VALS), 64)
-        self.present = np.union1d(self.present, ins)
+        self.present = _sorted_union(self.present, ins)
         n = self.present.size
         if r % 2 == 0:
             dele = self.present[rng.choice(n, m, replace=False)]
@@ -281,7 +304,7 @@ class UpdateHeavy:
             idx = np.concatenate([o + i * per + np.arange(per) for i, o in enumerate(offs)])
             dele = self.present[idx]
             rng.shuffle(dele)
-        self.present = np.setdiff1d(self.present, dele, assume_unique=True)
+        self.present = _sorted_difference(self.present, dele)
         return ins, ins_v, dele
 
 

@@ -421,3 +421,66 @@ def test_work_list_region_overflow(kb):
         o.delete(ks)
         assert s.status() == 0
         assert_same_contents(s, o, kb, f"{name} delete")
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_range_edge_cases(kb):
+    """Ranges with lo > hi (also repeated), max_per_query = 0, null key or
+    value outputs, hi = KEY_MAX, one lo with several different hi in one
+    slice, and dense ranges spanning many nodes and buckets; slots beyond
+    min(count, max_per_query) keep the caller's contents."""
+    import torch
+    log(f"range edge cases kb={kb}")
+    mx = (1 << kb) - 1
+    dt = ktype(kb)
+    s, o = new_pair(kb, cap=16, max_batch=1 << 14)
+    rng = np.random.default_rng(77 + kb)
+    keys = np.unique(_keys(rng, kb, 6000, hi=200000)).astype(dt)
+    keys = np.concatenate([keys, np.array([0, mx - 1, mx], dtype=dt)])
+    vals = (keys.astype(np.uint64) * np.uint64(3) + np.uint64(1)).astype(dt)
+    vals[vals == dt(mx)] = dt(5)
+    s.bulk_load(to_dev(keys), to_dev(vals))
+    o.bulk_load(keys, vals)
+    # grow chains so that dense ranges cross chained nodes and buckets
+    extra = np.arange(1000, 3000, dtype=np.uint64).astype(dt)
+    s.insert(to_dev(extra), to_dev(extra))
+    o.insert(extra, extra)
+    n = 4096
+    lo = _keys(rng, kb, n, hi=210000)
+    hi = (lo.astype(np.uint64) + rng.integers(0, 3000, n).astype(np.uint64)).astype(dt)
+    sw = rng.random(n) < 0.15                       # lo > hi
+    lo[sw], hi[sw] = hi[sw] + dt(1), lo[sw]
+    lo[:64] = dt(1500)                              # one lo, many different hi
+    hi[:64] = (np.arange(64, dtype=np.uint64) * np.uint64(40) + np.uint64(1400)).astype(dt)
+    lo[64:96] = dt(2500)                            # repeated lo > hi
+    hi[64:96] = dt(2499)
+    hi[96:128] = dt(mx)                             # saturating upper end
+    lo[128:136] = dt(mx)
+    lo[136:144] = dt(0)
+    perm = rng.permutation(n)
+    lo, hi = lo[perm], hi[perm]
+    oc, ok2, ov2 = o.range(lo, hi, 8)
+    for maxpq in (0, 1, 8):
+        for want_k, want_v in ((True, True), (False, True), (True, False)):
+            sent = -7
+            ck = torch.full((max(n * maxpq, 1),), sent, dtype=s.dtype, device="cuda")
+            cv = torch.full((max(n * maxpq, 1),), sent, dtype=s.dtype, device="cuda")
+            c, rk, rv = s.range(to_dev(lo), to_dev(hi), maxpq, out_k=ck if want_k else None,
+                                out_v=cv if want_v else None, want_keys=want_k,
+                                want_vals=want_v)
+            c = c.cpu().numpy().view(np.uint32)
+            assert np.array_equal(c, oc), f"counts maxpq={maxpq}"
+            if maxpq == 0:
+                assert (ck.cpu().numpy() == sent).all() and (cv.cpu().numpy() == sent).all()
+                continue
+            oc_m, ok_m, ov_m = o.range(lo, hi, maxpq)
+            w = np.minimum(oc_m, maxpq)
+            mask = np.arange(maxpq)[None, :] < w[:, None]
+            sent_u = dt(sent & mx)
+            for want, buf, ref in ((want_k, ck, ok_m), (want_v, cv, ov_m)):
+                if not want:
+                    continue   # passed as NULL
+                got = to_host(buf, kb)[: n * maxpq].reshape(n, maxpq)
+                assert np.array_equal(got[mask], ref[mask]), f"maxpq={maxpq} results"
+                assert (got[~mask] == sent_u).all(), f"maxpq={maxpq}: slot beyond count written"
+    assert s.status() == 0
