@@ -85,9 +85,10 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     size_of = sizes_cap  # keys per bucket after bulk load (array over buckets)
 
     fam = {}
-    # sort: 5 sorts per step (lookup, successor, range, insert, delete)
-    fam["sort_hist"] = 5 * m * kbytes
-    pay = [4, 4, 4, vbytes, 0]
+    # update batches sort on the onesweep path (2 sorts per step: insert with
+    # values, delete keys only); read batches take the bucket-group path
+    fam["sort_hist"] = 2 * m * kbytes
+    pay = [vbytes, 0]
     # batches of up to 2^22 keys with 8-bit digits: one device-wide pass on
     # the top digit, then one read and one write of every pair by the
     # per-run sort; otherwise P device-wide passes
@@ -96,9 +97,20 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     if local:
         fam["sort_local"] = sum(m * 2 * (kbytes + p) for p in pay)
 
-    def read_bytes(keys, extra_out, val_reads):
+    # bucket groups: at most 1024 groups of equal bucket counts
+    bpg = -(-nb // 1024)
+    ngroups = -(-nb // bpg)
+    ntiles = -(-m // 4096)
+    # k_part: read the keys, write keys + input positions grouped per tile,
+    # the tile group-start rows and the group totals
+    fam["part"] = 3 * (m * kbytes + m * (kbytes + 4) + ntiles * (ngroups + 1) * 4 + ngroups * 4)
+
+    def read_bytes(keys, extra_out, val_reads, hi_bytes=0):
+        # every maxBucket entry, the grouped batch (key + position), the head
+        # word (size, link) of each touched bucket, the live prefix of each
+        # touched node in whole 128-byte lines, values read, outputs
         t = touched(keys)
-        return (nb * kbytes + m * (kbytes + 4) + t.size * 16
+        return (nb * kbytes + m * (kbytes + 4) + hi_bytes + t.size * 8
                 + float(live_line(size_of[t]).sum()) + val_reads * vbytes + extra_out)
 
     hits = np.isin(wl["lookup"], build_sorted).sum()
@@ -107,13 +119,8 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     lo, hi = wl["range_lo"], wl["range_hi"]
     cnt = (np.searchsorted(build_sorted, hi, side="right")
            - np.searchsorted(build_sorted, lo, side="left")).sum()
-    rng = read_bytes(lo, m * (4 + vbytes) + cnt * (kbytes + vbytes), cnt)
-    fam["read_apply"] = look + succ + rng
-    # cut list of each read call: one u32 per share boundary, found by a
-    # 64-ary search whose probes read one batch key and one MKBA entry each
-    ncuts = -(-(m + nb) // 512) + 1
-    rounds = int(np.ceil(np.log(max(m, 2)) / np.log(65)))
-    fam["read_cuts"] = 3 * ncuts * (4 + rounds * 64 * (kbytes + kbytes))
+    rng = read_bytes(lo, m * 4 + cnt * (kbytes + vbytes), cnt, hi_bytes=m * kbytes)
+    fam["group_read"] = look + succ + rng
 
     ins = wl["insert_keys"]
     bi = np.searchsorted(mkba, ins, side="left")
@@ -372,8 +379,8 @@ def main():
         raise RuntimeError("device error during warmup")
     log("[bench] warmup done")
 
-    fams = ["sort_hist", "sort_pass", "sort_local", "read_cuts", "read_apply", "slices",
-            "insert_apply", "delete_apply"]
+    fams = ["sort_hist", "sort_pass", "sort_local", "read_cuts", "read_apply", "part",
+            "group_read", "slices", "insert_apply", "delete_apply"]
 
     def run_steps(k):
         torch.cuda.synchronize()

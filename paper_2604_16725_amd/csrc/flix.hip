@@ -13,6 +13,7 @@
 #include "flix_device.hpp"
 #include "flix_drain.hpp"
 #include "flix_epoch.hpp"
+#include "flix_group.hpp"
 #include "flix_read.hpp"
 #include "flix_read2.hpp"
 #include "flix_sort.hpp"
@@ -22,12 +23,13 @@ using namespace flix;
 
 namespace {
 
-constexpr int kFamilies = 8;
+constexpr int kFamilies = 10;
 const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
-                                       "insert_apply", "delete_apply", "read_cuts", "sort_local"};
+                                       "insert_apply", "delete_apply", "read_cuts", "sort_local",
+                                       "part", "group_read"};
 enum Family {
   F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6,
-  F_LOCAL = 7
+  F_LOCAL = 7, F_PART = 8, F_GROUP = 9
 };
 int sort_family(int fam) { return fam == 0 ? F_HIST : fam == 1 ? F_PASS : F_LOCAL; }
 
@@ -81,6 +83,13 @@ struct flix_store {
   void* nvals = nullptr;
   u32* bnodes = nullptr;
   u32* cuts = nullptr;   // read-share cuts [(max_batch + nb_alloc) / 512 + 2]
+  // bucket groups of the read path (flix_group.hpp)
+  bool grp_ok = false;   // the store's shape fits the group kernels
+  u32 ngrp = 1, bpg = 1;
+  void* split = nullptr; // [kGroupMax] group upper bounds
+  u32* gpre = nullptr;   // [tiles(max_batch)][kGroupMax + 1] tile group starts
+  u32* gtot = nullptr;   // [2][kGroupMax] group totals, two slots
+  u32 gslot = 0;         // totals slot of the next read call
   u32* free_ids = nullptr;
   Ctl* ctl = nullptr;
   // scratch
@@ -214,6 +223,12 @@ int alloc_pool(flix_store* s, u32 pool) {
 
 // Entries of the read-share cut list for batches of up to n keys over nb buckets.
 u64 cuts_for(u64 n, u64 nb) { return (n + nb) / 512u + 2u; }
+
+// Partition tiles of a batch of up to n items, capped at the group kernels' limit.
+u64 group_tiles(u64 n) {
+  const u64 t = (n + kPartTile - 1) / kPartTile;
+  return t < kGroupTilesMax ? t : kGroupTilesMax;
+}
 
 int alloc_dir(flix_store* s, u32 nb) {
   if (nb <= s->nb_alloc) return FLIX_OK;
@@ -370,9 +385,122 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   return FLIX_OK;
 }
 
+// Group read kernel for lanes per bucket GL and keys per lane KPL: U buckets
+// in a lane group's registers at a time.
+template <typename K, int GL, int KPL>
+void launch_group_k(const GroupArgs<K>& ga, const ReadArgs<K>& a, int op, u32 grid,
+                    hipStream_t st, const TmTok& t) {
+  constexpr int KW = KPL * (int)(sizeof(K) / 4);
+  constexpr int U = KW >= 16 ? 2 : 4;
+  auto fn = k_group_read<K, 256, 8, GL, KPL, U>;
+  const GroupLds<K> L(2048, 256, kGroupBucketsMax, op == kOpRange);
+  static size_t attr = 0;
+  if (L.bytes > 65536 && L.bytes > attr) {
+    if (hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes) == hipSuccess)
+      attr = L.bytes;
+    (void)hipGetLastError();
+  }
+  launch_timed(t.b, t.e, fn, dim3(grid), dim3(256), (uint32_t)L.bytes, st, ga, a, op);
+}
+
+template <typename K>
+void launch_group(const flix_store* s, const GroupArgs<K>& ga, const ReadArgs<K>& a, int op,
+                  u32 grid, hipStream_t st, const TmTok& t) {
+  const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
+  switch (s->gl * 100 + kpl) {
+    case 1601: launch_group_k<K, 16, 1>(ga, a, op, grid, st, t); break;
+    case 1602: launch_group_k<K, 16, 2>(ga, a, op, grid, st, t); break;
+    case 1604: launch_group_k<K, 16, 4>(ga, a, op, grid, st, t); break;
+    case 1608: launch_group_k<K, 16, 8>(ga, a, op, grid, st, t); break;
+    case 1616: launch_group_k<K, 16, 16>(ga, a, op, grid, st, t); break;
+    case 3201: launch_group_k<K, 32, 1>(ga, a, op, grid, st, t); break;
+    case 3202: launch_group_k<K, 32, 2>(ga, a, op, grid, st, t); break;
+    case 3204: launch_group_k<K, 32, 4>(ga, a, op, grid, st, t); break;
+    case 3208: launch_group_k<K, 32, 8>(ga, a, op, grid, st, t); break;
+    case 6401: launch_group_k<K, 64, 1>(ga, a, op, grid, st, t); break;
+    case 6402: launch_group_k<K, 64, 2>(ga, a, op, grid, st, t); break;
+    default: launch_group_k<K, 64, 4>(ga, a, op, grid, st, t); break;
+  }
+}
+
+// Read batch on the bucket-group path: k_part, then k_group_read.
+template <typename K>
+int read_batch_groups(flix_store* s, int op, const K* keys, u64 n, void* out_k, void* out_v,
+                      const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
+  const u32 ntiles = (u32)((n + kPartTile - 1) / kPartTile);
+  u32* gtot = s->gtot + (size_t)s->gslot * kGroupMax;
+  u32* gnext = s->gtot + (size_t)(s->gslot ^ 1u) * kGroupMax;
+  s->gslot ^= 1u;
+  PartArgs<K, u32> pa;
+  pa.keys = keys;
+  pa.vin = nullptr;
+  pa.n = (u32)n;
+  pa.split = (const K*)s->split;
+  pa.ngroups = s->ngrp;
+  pa.gbits = group_bits(s->ngrp);
+  pa.tk = (K*)s->bk[0];
+  pa.tp = (u32*)s->bp[0];
+  pa.gpre = s->gpre;
+  pa.gtot = gtot;
+  pa.gtot_clear = gnext;
+  {
+    using L = PartLds<K, u32, kPayIndex>;
+    static bool attr = false;
+    if (!attr && L::bytes > 65536) {
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_part<K, u32, kPayIndex>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L::bytes));
+      attr = true;
+    }
+    const TmTok t = tm_arm(s, F_PART);
+    launch_timed(t.b, t.e, k_part<K, u32, kPayIndex>, dim3(ntiles), dim3(kPartNT),
+                 (uint32_t)L::bytes, st, pa);
+    tm_done(s, F_PART, t);
+    HIP_TRY(hipGetLastError());
+  }
+  GroupArgs<K> ga;
+  ga.tk = (const K*)s->bk[0];
+  ga.tp = (const u32*)s->bp[0];
+  ga.gpre = s->gpre;
+  ga.gtot = gtot;
+  ga.split = (const K*)s->split;
+  ga.n = (u32)n;
+  ga.ntiles = ntiles;
+  ga.ngroups = s->ngrp;
+  ga.bpg = s->bpg;
+  ga.chunk_items = 2048;
+  ReadArgs<K> a;
+  a.skeys = nullptr;
+  a.sidx = nullptr;
+  a.m = (u32)n;
+  a.mkba = (const K*)s->mkba;
+  a.nb = s->nb;
+  a.hdr = s->hdr;
+  a.nkeys = (const K*)s->nkeys;
+  a.nvals = (const K*)s->nvals;
+  a.cap = s->cap;
+  a.share = 0;
+  a.out_v = (K*)out_v;
+  a.out_k = (K*)out_k;
+  a.hi = (const K*)hi;
+  a.counts = counts;
+  a.maxpq = maxpq;
+  a.pool = s->pool;
+  a.err = &s->ctl->status;
+  a.cuts = nullptr;
+  const u32 grid = group_chunk_bound((u32)n, s->ngrp, 2048);
+  const TmTok t = tm_arm(s, F_GROUP);
+  launch_group<K>(s, ga, a, op, grid, st, t);
+  tm_done(s, F_GROUP, t);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
 template <typename K>
 int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void* out_v,
                const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
+  if (s->grp_ok && n <= (u64)kGroupTilesMax * kPartTile)
+    return read_batch_groups<K>(s, op, (const K*)keys, n, out_k, out_v, hi, counts, maxpq, st);
   int r;
   int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r);
   if (rc) return rc;
@@ -789,14 +917,34 @@ int bulk_load_body(flix_store* s, const K* keys, const K* vals, u64 n, hipStream
   return FLIX_OK;
 }
 
-// Bulk load, then the layout record, also after a failure part way (the
-// directory or the pool may have been reallocated already).
+// Bucket groups of the read path for the current directory: their shape,
+// upper bounds and cleared totals.  Synchronous (the store is idle).
+template <typename K>
+int rebuild_groups(flix_store* s, hipStream_t st) {
+  u32 g = 1, bpg = 1;
+  s->grp_ok = group_shape(s->nb, &g, &bpg) && s->gpre && s->split && s->gtot;
+  s->ngrp = g;
+  s->bpg = bpg;
+  s->gslot = 0;
+  if (!s->grp_ok) return FLIX_OK;
+  if (g > 1)
+    hipLaunchKernelGGL((k_build_split<K>), dim3((g + 255) / 256), dim3(256), 0, st,
+                       (const K*)s->mkba, s->nb, bpg, g, (K*)s->split);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemsetAsync(s->gtot, 0, 2ull * kGroupMax * sizeof(u32), st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return FLIX_OK;
+}
+
+// Bulk load, then the layout record and the bucket groups, also after a
+// failure part way (the directory or the pool may have been reallocated).
 template <typename K>
 int bulk_load_t(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t st) {
   const int rc = bulk_load_body<K>(s, keys, vals, n, st);
   (void)hipStreamSynchronize(st);
   const int rp = publish_layout(s);
-  return rc ? rc : rp;
+  const int rg = rebuild_groups<K>(s, st);
+  return rc ? rc : (rp ? rp : rg);
 }
 
 int check_args(flix_store* s, u64 n, std::initializer_list<const void*> ptrs) {
@@ -811,6 +959,9 @@ int check_args(flix_store* s, u64 n, std::initializer_list<const void*> ptrs) {
 void destroy_all(flix_store* s) {
   dev_free(&s->mkba);
   dev_free(&s->cuts);
+  dev_free(&s->split);
+  dev_free(&s->gpre);
+  dev_free(&s->gtot);
   dev_free(&s->hdr);
   dev_free(&s->nkeys);
   dev_free(&s->nvals);
@@ -981,10 +1132,18 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
       (rc = dev_alloc(&s->bk[1], mb * s->ksz)) || (rc = dev_alloc(&s->bp[0], mb * 8)) ||
       (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, work_slots(mb) * sizeof(WorkItem))) ||
       (rc = dev_alloc(&s->ss.hist, 2 * 2048 * sizeof(u32))) ||
-      (rc = dev_alloc(&s->ss.tile_ctr, 64)) || (rc = dev_alloc(&s->ss.err, 16))) {
+      (rc = dev_alloc(&s->ss.tile_ctr, 64)) || (rc = dev_alloc(&s->ss.err, 16)) ||
+      (rc = dev_alloc(&s->split, (u64)kGroupMax * s->ksz)) ||
+      (rc = dev_alloc(&s->gpre, group_tiles(mb) * (kGroupMax + 1) * sizeof(u32))) ||
+      (rc = dev_alloc(&s->gtot, 2ull * kGroupMax * sizeof(u32)))) {
     destroy_all(s);
     delete s;
     return rc;
+  }
+  if (hipMemset(s->gtot, 0, 2ull * kGroupMax * sizeof(u32)) != hipSuccess) {
+    destroy_all(s);
+    delete s;
+    return FLIX_EHIP;
   }
   std::snprintf(g_last_error, sizeof(g_last_error), "flix_create: initial memset");
   if (hipMemset(s->ctl, 0, sizeof(Ctl)) != hipSuccess ||

@@ -27,6 +27,22 @@ namespace flix {
 
 constexpr u32 kPosMiss = 0xFFFFu;   // lookup miss inside a single-node bucket
 constexpr u32 kPosSlow = 0xFFFEu;   // resolve on the global-memory path
+constexpr u32 kChainBit = 0x80000000u;   // head-word flag: the bucket is a chain
+
+// LDS arrays of one set of slices being resolved: the sorted keys of the
+// slices, their input positions, range upper bounds, result codes, the end
+// of every local bucket's slice, its head word and the touched-bucket list.
+template <typename K>
+struct SliceView {
+  const K* q;
+  const K* hi;
+  const u32* idx;
+  u32* pos;
+  u32* cnt;
+  const u32* e;
+  const u32* hw;
+  const unsigned short* tl;
+};
 
 template <typename K, int KPL>
 struct alignas(sizeof(K) * KPL >= 16 ? 16 : sizeof(K) * KPL) KeyVec {
@@ -42,138 +58,28 @@ struct ReadSmem {
   u32 cnt[S];       // range: results inside the node
   K mk[S];
   u32 e[S + 1];
-  u32 hsz[S + 1];
-  u32 hnx[S + 1];
+  u32 hw[S + 1];    // head node: size | kChainBit when the bucket has more nodes
   unsigned short tl[S + 1];
   u32 tmp[NT / 64 + 1];
   u32 lo[2], hiw[2], wc[4], cut[2], ntouch;
 };
 
-// One share (workgroup-sized unit) of a read batch; `vb` is the share index.
-template <typename K, int NT, int S, int GL, int KPL, int U>
-__device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, NT>& sm) {
-  static_assert(NT == 256, "merge-path search assumes 256 threads");
+// Phases A and B over the touched buckets of one set of slices (all threads
+// of the workgroup call; `ntouch` buckets listed in v.tl, local bucket lb is
+// global bucket b0 + lb, at most RQ * NT keys).
+template <typename K, int NT, int GL, int KPL, int U, int RQ>
+__device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>& v, u32 b0,
+                               u32 nq, u32 ntouch) {
   constexpr int NG = NT / GL;
-  K* s_q = sm.q;
-  K* s_hi = sm.hi;
-  u32* s_idx = sm.idx;
-  u32* s_pos = sm.pos;
-  u32* s_cnt = sm.cnt;
-  K* s_mk = sm.mk;
-  u32* s_e = sm.e;
-  u32* s_hsz = sm.hsz;
-  u32* s_hnx = sm.hnx;
-  unsigned short* s_tl = sm.tl;
-  u32* s_tmp = sm.tmp;
-  u32* s_lo = sm.lo;
-  u32* s_hiw = sm.hiw;
-  u32* s_wc = sm.wc;
-  u32* s_cut = sm.cut;
-  u32& s_ntouch = sm.ntouch;
-
   const u32 tid = threadIdx.x;
-  const u64 total = (u64)a.m + a.nb;
-  u64 d[2];
-  d[0] = (u64)vb * a.share;
-  d[1] = d[0] + a.share < total ? d[0] + a.share : total;
-  if (a.cuts) {
-    if (tid < 2) s_cut[tid] = a.cuts[vb + tid];
-    __syncthreads();
-  } else {
-    coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
-  }
-  const u32 q0 = s_cut[0], q1 = s_cut[1];
-  // Cuts of a sorted batch are ordered; anything else (an unsorted batch)
-  // is reported instead of indexing past the share.
-  if (q1 < q0 || q1 > a.m || d[0] < q0 || d[1] < q1 || d[0] - q0 > d[1] - q1 ||
-      d[1] - q1 > a.nb) {
-    if (tid == 0) atomicCAS(a.err, 0u, kErrInternal);
-    return;
-  }
-  const u32 b0 = (u32)(d[0] - q0), b1 = (u32)(d[1] - q1);
-  const u32 nq = q1 - q0;
-  if (nq == 0) return;
-  const u32 nbl = b1 - b0;
-
-  // One round of coalesced loads: a share holds at most S keys and S + 1
-  // bucket entries, and every load of a thread is issued before its first
-  // LDS store (range upper bounds follow, indexed by the input positions).
-  constexpr u32 RQ = (S + NT - 1) / NT;
-  constexpr u32 RBK = (S + 1 + NT - 1) / NT;
-  {
-    K qk[RQ];
-    u32 qi[RQ];
-#pragma unroll
-    for (u32 r = 0; r < RQ; ++r) {
-      const u32 j = tid + r * NT;
-      if (j < nq) {
-        qk[r] = a.skeys[q0 + j];
-        qi[r] = a.sidx[q0 + j];
-      }
-    }
-    K mk[RBK];
-    u64 hw[RBK];   // size | next << 32 of the bucket's head node
-#pragma unroll
-    for (u32 r = 0; r < RBK; ++r) {
-      const u32 i = tid + r * NT;
-      hw[r] = (u64)kNil << 32;
-      if (i < nbl) mk[r] = a.mkba[b0 + i];
-      if (i <= nbl && b0 + i < a.nb)
-        hw[r] = *reinterpret_cast<const u64*>(&a.hdr[b0 + i].size);
-    }
-#pragma unroll
-    for (u32 r = 0; r < RQ; ++r) {
-      const u32 j = tid + r * NT;
-      if (j < nq) {
-        s_q[j] = qk[r];
-        s_idx[j] = qi[r];
-        if (op == kOpRange) s_hi[j] = a.hi[qi[r]];
-      }
-    }
-#pragma unroll
-    for (u32 r = 0; r < RBK; ++r) {
-      const u32 i = tid + r * NT;
-      if (i <= nbl) {
-        if (i < nbl) s_mk[i] = mk[r];
-        s_hsz[i] = (u32)hw[r];
-        s_hnx[i] = (u32)(hw[r] >> 32);
-      }
-    }
-  }
-  __syncthreads();
-
-  // Bound search: every bucket pulls its slice; compact the touched buckets.
-  constexpr u32 PER = (S + 1 + NT - 1) / NT;
-  u32 flags = 0, nt = 0;
-#pragma unroll
-  for (u32 r = 0; r < PER; ++r) {
-    u32 lb = tid * PER + r;
-    if (lb <= nbl) {
-      u32 e = (lb < nbl) ? upper_bound_idx<K>(s_q, 0u, nq, s_mk[lb]) : nq;
-      s_e[lb] = e;
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (u32 r = 0; r < PER; ++r) {
-    u32 lb = tid * PER + r;
-    if (lb <= nbl) {
-      u32 s = lb ? s_e[lb - 1] : 0u;
-      if (s_e[lb] > s) {
-        flags |= 1u << r;
-        ++nt;
-      }
-    }
-  }
-  u32 ntot;
-  u32 w = block_exclusive_scan<NT>(nt, s_tmp, &ntot);
-#pragma unroll
-  for (u32 r = 0; r < PER; ++r)
-    if (flags & (1u << r)) s_tl[w++] = (unsigned short)(tid * PER + r);
-  if (tid == 0) s_ntouch = ntot;
-  __syncthreads();
-  const u32 ntouch = s_ntouch;
-
+  const K* s_q = v.q;
+  const K* s_hi = v.hi;
+  const u32* s_idx = v.idx;
+  u32* s_pos = v.pos;
+  u32* s_cnt = v.cnt;
+  const u32* s_e = v.e;
+  const u32* s_hw = v.hw;
+  const unsigned short* s_tl = v.tl;
   // Phase A: groups resolve positions inside single-node buckets.
   {
     const u32 gid = tid / GL;
@@ -188,8 +94,9 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
       for (int u = 0; u < U; ++u) {
         u32 i = i0 + u;
         lbs[u] = i < ntouch ? s_tl[i] : 0u;
-        sizes[u] = (i < ntouch) ? s_hsz[lbs[u]] : 0u;
-        single[u] = (i < ntouch) && s_hnx[lbs[u]] == kNil;
+        const u32 hw = (i < ntouch) ? s_hw[lbs[u]] : 0u;
+        sizes[u] = hw & ~kChainBit;
+        single[u] = (i < ntouch) && !(hw & kChainBit);
         if (single[u] && gl * KPL < sizes[u]) {
           const KeyVec<K, KPL>* src = reinterpret_cast<const KeyVec<K, KPL>*>(
               a.nkeys + (u64)(b0 + lbs[u]) * a.cap + (u64)gl * KPL);
@@ -395,6 +302,141 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
       a.counts[orig] = cnt;
     }
   }
+}
+
+// One share (workgroup-sized unit) of a read batch; `vb` is the share index.
+template <typename K, int NT, int S, int GL, int KPL, int U>
+__device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, NT>& sm) {
+  static_assert(NT == 256, "merge-path search assumes 256 threads");
+  constexpr int NG = NT / GL;
+  K* s_q = sm.q;
+  K* s_hi = sm.hi;
+  u32* s_idx = sm.idx;
+  u32* s_pos = sm.pos;
+  u32* s_cnt = sm.cnt;
+  K* s_mk = sm.mk;
+  u32* s_e = sm.e;
+  u32* s_hw = sm.hw;
+  unsigned short* s_tl = sm.tl;
+  u32* s_tmp = sm.tmp;
+  u32* s_lo = sm.lo;
+  u32* s_hiw = sm.hiw;
+  u32* s_wc = sm.wc;
+  u32* s_cut = sm.cut;
+  u32& s_ntouch = sm.ntouch;
+
+  const u32 tid = threadIdx.x;
+  const u64 total = (u64)a.m + a.nb;
+  u64 d[2];
+  d[0] = (u64)vb * a.share;
+  d[1] = d[0] + a.share < total ? d[0] + a.share : total;
+  if (a.cuts) {
+    if (tid < 2) s_cut[tid] = a.cuts[vb + tid];
+    __syncthreads();
+  } else {
+    coop_merge_path<K>(a.skeys, a.m, a.mkba, a.nb, d, s_lo, s_hiw, s_wc, s_cut);
+  }
+  const u32 q0 = s_cut[0], q1 = s_cut[1];
+  // Cuts of a sorted batch are ordered; anything else (an unsorted batch)
+  // is reported instead of indexing past the share.
+  if (q1 < q0 || q1 > a.m || d[0] < q0 || d[1] < q1 || d[0] - q0 > d[1] - q1 ||
+      d[1] - q1 > a.nb) {
+    if (tid == 0) atomicCAS(a.err, 0u, kErrInternal);
+    return;
+  }
+  const u32 b0 = (u32)(d[0] - q0), b1 = (u32)(d[1] - q1);
+  const u32 nq = q1 - q0;
+  if (nq == 0) return;
+  const u32 nbl = b1 - b0;
+
+  // One round of coalesced loads: a share holds at most S keys and S + 1
+  // bucket entries, and every load of a thread is issued before its first
+  // LDS store (range upper bounds follow, indexed by the input positions).
+  constexpr u32 RQ = (S + NT - 1) / NT;
+  constexpr u32 RBK = (S + 1 + NT - 1) / NT;
+  {
+    K qk[RQ];
+    u32 qi[RQ];
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if (j < nq) {
+        qk[r] = a.skeys[q0 + j];
+        qi[r] = a.sidx[q0 + j];
+      }
+    }
+    K mk[RBK];
+    u64 hw[RBK];   // size | next << 32 of the bucket's head node
+#pragma unroll
+    for (u32 r = 0; r < RBK; ++r) {
+      const u32 i = tid + r * NT;
+      hw[r] = (u64)kNil << 32;
+      if (i < nbl) mk[r] = a.mkba[b0 + i];
+      if (i <= nbl && b0 + i < a.nb)
+        hw[r] = *reinterpret_cast<const u64*>(&a.hdr[b0 + i].size);
+    }
+#pragma unroll
+    for (u32 r = 0; r < RQ; ++r) {
+      const u32 j = tid + r * NT;
+      if (j < nq) {
+        s_q[j] = qk[r];
+        s_idx[j] = qi[r];
+        if (op == kOpRange) s_hi[j] = a.hi[qi[r]];
+      }
+    }
+#pragma unroll
+    for (u32 r = 0; r < RBK; ++r) {
+      const u32 i = tid + r * NT;
+      if (i <= nbl) {
+        if (i < nbl) s_mk[i] = mk[r];
+        s_hw[i] = (u32)hw[r] | ((u32)(hw[r] >> 32) != kNil ? kChainBit : 0u);
+      }
+    }
+  }
+  __syncthreads();
+
+  // Bound search: every bucket pulls its slice; compact the touched buckets.
+  constexpr u32 PER = (S + 1 + NT - 1) / NT;
+  u32 flags = 0, nt = 0;
+#pragma unroll
+  for (u32 r = 0; r < PER; ++r) {
+    u32 lb = tid * PER + r;
+    if (lb <= nbl) {
+      u32 e = (lb < nbl) ? upper_bound_idx<K>(s_q, 0u, nq, s_mk[lb]) : nq;
+      s_e[lb] = e;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (u32 r = 0; r < PER; ++r) {
+    u32 lb = tid * PER + r;
+    if (lb <= nbl) {
+      u32 s = lb ? s_e[lb - 1] : 0u;
+      if (s_e[lb] > s) {
+        flags |= 1u << r;
+        ++nt;
+      }
+    }
+  }
+  u32 ntot;
+  u32 w = block_exclusive_scan<NT>(nt, s_tmp, &ntot);
+#pragma unroll
+  for (u32 r = 0; r < PER; ++r)
+    if (flags & (1u << r)) s_tl[w++] = (unsigned short)(tid * PER + r);
+  if (tid == 0) s_ntouch = ntot;
+  __syncthreads();
+  const u32 ntouch = s_ntouch;
+
+  SliceView<K> v;
+  v.q = s_q;
+  v.hi = s_hi;
+  v.idx = s_idx;
+  v.pos = s_pos;
+  v.cnt = s_cnt;
+  v.e = s_e;
+  v.hw = s_hw;
+  v.tl = s_tl;
+  resolve_slices<K, NT, GL, KPL, U, RQ>(a, op, v, b0, nq, ntouch);
 }
 
 // Eight waves per SIMD (64 VGPRs): the kernel is latency-bound, and the
