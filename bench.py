@@ -497,6 +497,19 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle
+        # the oracle is single-threaded; pin this process to one core for it
+        nproc = os.cpu_count()
+        model = "unknown"
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        saved_aff = os.sched_getaffinity(0)
+        core = min(saved_aff)
+        os.sched_setaffinity(0, {core})
         o = Oracle(32)
         t0 = time.time()
         o.bulk_load(wl["build_keys"], wl["build_vals"])
@@ -508,11 +521,13 @@ def main():
         o.insert(wl["insert_keys"], wl["insert_vals"])
         o.delete(wl["insert_keys"])
         cpu_s = time.perf_counter() - t0
+        os.sched_setaffinity(0, saved_aff)
         cpu = {"value": round(ops_step / cpu_s / 1e6, 3), "unit": "Mops/s", "cores": 1,
                "kind": "oracle",
                "sample": f"one step (lookup, successor, range16, insert, delete of {m} ops each) "
-                         f"on the bulk-loaded {n_keys}-key store, single thread, "
-                         f"{cpu_s:.2f}s"}
+                         f"on the bulk-loaded {n_keys}-key store, single thread pinned to core "
+                         f"{core}, {cpu_s:.2f}s",
+               "host_nproc": nproc, "host_cpu": model}
         log(f"[bench] oracle step {cpu_s:.2f}s")
 
     out = {

@@ -107,6 +107,12 @@ int flix_lookup(flix_store* s, const void* d_keys, uint64_t n, void* d_vals_out,
 int flix_successor(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
                    void* d_vals_out, void* stream);
 
+/* Predecessor queries (ordered-map ADT, Section 2.1, the mirror of the
+ * successor): largest stored key k' <= d_keys[i] and its value; (0, NOT_FOUND)
+ * when none exists (NOT_FOUND tells the miss apart from a stored key 0). */
+int flix_predecessor(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
+                     void* d_vals_out, void* stream);
+
 /* Range queries (ordered-map ADT, Section 2.1): all pairs with
  * d_lo[i] <= k <= d_hi[i], ascending.  d_counts[i] = exact number of such
  * pairs (0 when lo > hi); the first min(count, max_per_query) keys/values are
@@ -174,6 +180,7 @@ int flix_sort_pairs(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_
 #define FLIX_OP_RANGE 2
 #define FLIX_OP_INSERT 3
 #define FLIX_OP_DELETE 4
+#define FLIX_OP_PREDECESSOR 5
 typedef struct {
   uint32_t op;            /* FLIX_OP_* */
   uint32_t n;             /* operations in the batch, <= max_batch (0: skipped) */
@@ -181,8 +188,8 @@ typedef struct {
   uint32_t reserved;      /* must be 0 */
   const void* d_keys;     /* keys (range: lo) */
   const void* d_aux;      /* insert: values; range: hi; otherwise NULL */
-  void* d_vals_out;       /* lookup / successor / range values */
-  void* d_keys_out;       /* successor / range keys (range: may be NULL) */
+  void* d_vals_out;       /* lookup / successor / predecessor / range values */
+  void* d_keys_out;       /* successor / predecessor / range keys (range: may be NULL) */
   uint32_t* d_counts;     /* range counts */
   void* reserved2;        /* must be NULL */
 } flix_batch;             /* 64 bytes */

@@ -2,7 +2,10 @@
 
     python -m paper_2604_16725_amd.build_lib
 
-Every kernel is compiled for gfx950 only, without packed-FP32 instructions.
+The library is three translation units compiled in parallel (the C ABI with
+the sort, update and partition kernels; the read kernels; the persistent
+drain) and linked into one shared object.  Every kernel is compiled for
+gfx950 only, without packed-FP32 instructions.
 """
 import os
 import subprocess
@@ -10,7 +13,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "flix.hip")
+CSRC = os.path.join(HERE, "csrc")
+SOURCES = ["flix.hip", "flix_read_tu.hip", "flix_drain_tu.hip"]
+SRC = os.path.join(CSRC, SOURCES[0])
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libflix.so")
 
@@ -19,7 +24,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
 ]
@@ -27,8 +31,24 @@ HIPCC_FLAGS = [
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
+        cmd = ["hipcc", *HIPCC_FLAGS, "-c", "-o", obj + ".tmp", os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), obj))
+        objs.append(obj)
+    failed = False
+    for p, obj in procs:
+        if p.wait() != 0:
+            failed = True
+        else:
+            os.replace(obj + ".tmp", obj)
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc (one of the translation units)")
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, SRC]
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

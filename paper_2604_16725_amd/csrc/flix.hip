@@ -14,6 +14,7 @@
 #include "flix_drain.hpp"
 #include "flix_epoch.hpp"
 #include "flix_group.hpp"
+#include "flix_launch.hpp"
 #include "flix_read.hpp"
 #include "flix_read2.hpp"
 #include "flix_sort.hpp"
@@ -82,6 +83,8 @@ struct flix_store {
   void* nkeys = nullptr;
   void* nvals = nullptr;
   u32* bnodes = nullptr;
+  u64* occ = nullptr;    // bucket occupancy summary [occ_words(nb_alloc)]
+  OccLevels occl{};      // its three levels for the current bucket count
   u32* cuts = nullptr;   // read-share cuts [(max_batch + nb_alloc) / 512 + 2]
   // bucket groups of the read path (flix_group.hpp)
   bool grp_ok = false;   // the store's shape fits the group kernels
@@ -235,9 +238,11 @@ int alloc_dir(flix_store* s, u32 nb) {
   dev_free(&s->mkba);
   dev_free(&s->bnodes);
   dev_free(&s->cuts);
+  dev_free(&s->occ);
   int rc;
   if ((rc = dev_alloc(&s->mkba, (u64)nb * s->ksz))) return rc;
   if ((rc = dev_alloc(&s->bnodes, (u64)nb * sizeof(u32)))) return rc;
+  if ((rc = dev_alloc(&s->occ, occ_words(nb) * sizeof(u64)))) return rc;
   if ((rc = dev_alloc(&s->cuts, (cuts_for(s->max_batch, nb) * sizeof(u32))))) return rc;
   s->nb_alloc = nb;
   return FLIX_OK;
@@ -316,34 +321,6 @@ struct ReadCfg<u64> {
   static constexpr int S = 512;
 };
 
-template <typename K, int GL, int KPL>
-void launch_read2_k(const ReadArgs<K>& a, int op, u32 grid, hipStream_t st, const TmTok& t) {
-  constexpr int U = KPL >= 16 ? 2 : 4;
-  launch_timed(t.b, t.e, k_read_apply2<K, 256, ReadCfg<K>::S, GL, KPL, U>, dim3(grid), dim3(256),
-               0, st, a, op);
-}
-
-// Lanes per bucket GL and keys per lane KPL = max(1, cap / GL).
-template <typename K>
-void launch_read2(const flix_store* s, const ReadArgs<K>& a, int op, u32 grid, hipStream_t st,
-                  const TmTok& t) {
-  const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
-  switch (s->gl * 100 + kpl) {
-    case 1601: launch_read2_k<K, 16, 1>(a, op, grid, st, t); break;
-    case 1602: launch_read2_k<K, 16, 2>(a, op, grid, st, t); break;
-    case 1604: launch_read2_k<K, 16, 4>(a, op, grid, st, t); break;
-    case 1608: launch_read2_k<K, 16, 8>(a, op, grid, st, t); break;
-    case 1616: launch_read2_k<K, 16, 16>(a, op, grid, st, t); break;
-    case 3201: launch_read2_k<K, 32, 1>(a, op, grid, st, t); break;
-    case 3202: launch_read2_k<K, 32, 2>(a, op, grid, st, t); break;
-    case 3204: launch_read2_k<K, 32, 4>(a, op, grid, st, t); break;
-    case 3208: launch_read2_k<K, 32, 8>(a, op, grid, st, t); break;
-    case 6401: launch_read2_k<K, 64, 1>(a, op, grid, st, t); break;
-    case 6402: launch_read2_k<K, 64, 2>(a, op, grid, st, t); break;
-    default: launch_read2_k<K, 64, 4>(a, op, grid, st, t); break;
-  }
-}
-
 // Bucket kernel over an already sorted read list (keys + original index).
 template <typename K>
 int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u64 n, void* out_k,
@@ -366,6 +343,7 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   a.maxpq = maxpq;
   a.pool = s->pool;
   a.err = &s->ctl->status;
+  a.occ = s->occl;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
   // cut list: half a wave per share boundary (the list holds cuts_for(max_batch,
   // nb_alloc) >= grid + 1 entries)
@@ -379,49 +357,10 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
     a.cuts = s->cuts;
   }
   const TmTok t = tm_arm(s, F_READ);
-  launch_read2<K>(s, a, op, (u32)grid, st, t);
+  launch_read2<K>(s->gl, s->cap, a, op, (u32)grid, st, t.b, t.e);
   tm_done(s, F_READ, t);
   HIP_TRY(hipGetLastError());
   return FLIX_OK;
-}
-
-// Group read kernel for lanes per bucket GL and keys per lane KPL: U buckets
-// in a lane group's registers at a time.
-template <typename K, int GL, int KPL>
-void launch_group_k(const GroupArgs<K>& ga, const ReadArgs<K>& a, int op, u32 grid,
-                    hipStream_t st, const TmTok& t) {
-  constexpr int KW = KPL * (int)(sizeof(K) / 4);
-  constexpr int U = KW >= 16 ? 2 : 4;
-  auto fn = k_group_read<K, 256, 8, GL, KPL, U>;
-  const GroupLds<K> L(2048, 256, kGroupBucketsMax, op == kOpRange);
-  static size_t attr = 0;
-  if (L.bytes > 65536 && L.bytes > attr) {
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.bytes) == hipSuccess)
-      attr = L.bytes;
-    (void)hipGetLastError();
-  }
-  launch_timed(t.b, t.e, fn, dim3(grid), dim3(256), (uint32_t)L.bytes, st, ga, a, op);
-}
-
-template <typename K>
-void launch_group(const flix_store* s, const GroupArgs<K>& ga, const ReadArgs<K>& a, int op,
-                  u32 grid, hipStream_t st, const TmTok& t) {
-  const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
-  switch (s->gl * 100 + kpl) {
-    case 1601: launch_group_k<K, 16, 1>(ga, a, op, grid, st, t); break;
-    case 1602: launch_group_k<K, 16, 2>(ga, a, op, grid, st, t); break;
-    case 1604: launch_group_k<K, 16, 4>(ga, a, op, grid, st, t); break;
-    case 1608: launch_group_k<K, 16, 8>(ga, a, op, grid, st, t); break;
-    case 1616: launch_group_k<K, 16, 16>(ga, a, op, grid, st, t); break;
-    case 3201: launch_group_k<K, 32, 1>(ga, a, op, grid, st, t); break;
-    case 3202: launch_group_k<K, 32, 2>(ga, a, op, grid, st, t); break;
-    case 3204: launch_group_k<K, 32, 4>(ga, a, op, grid, st, t); break;
-    case 3208: launch_group_k<K, 32, 8>(ga, a, op, grid, st, t); break;
-    case 6401: launch_group_k<K, 64, 1>(ga, a, op, grid, st, t); break;
-    case 6402: launch_group_k<K, 64, 2>(ga, a, op, grid, st, t); break;
-    default: launch_group_k<K, 64, 4>(ga, a, op, grid, st, t); break;
-  }
 }
 
 // Read batch on the bucket-group path: k_part, then k_group_read.
@@ -487,10 +426,11 @@ int read_batch_groups(flix_store* s, int op, const K* keys, u64 n, void* out_k, 
   a.maxpq = maxpq;
   a.pool = s->pool;
   a.err = &s->ctl->status;
+  a.occ = s->occl;
   a.cuts = nullptr;
   const u32 grid = group_chunk_bound((u32)n, s->ngrp, 2048);
   const TmTok t = tm_arm(s, F_GROUP);
-  launch_group<K>(s, ga, a, op, grid, st, t);
+  launch_group<K>(s->gl, s->cap, ga, a, op, grid, st, t.b, t.e);
   tm_done(s, F_GROUP, t);
   HIP_TRY(hipGetLastError());
   return FLIX_OK;
@@ -639,6 +579,7 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   ua.rcap = work_region_cap(s->max_batch);
   ua.ctl = s->ctl;
   ua.status = &s->ctl->status;
+  ua.occ = s->occl;
   u32 lds_items = upd_lds_items(s);
   u64 items = std::min<u64>(n, s->nb);
   t = tm_arm(s, insert ? F_INSERT : F_DELETE);
@@ -819,6 +760,7 @@ int publish_layout(flix_store* s) {
   L.free_ids = s->free_ids;
   L.nb = s->nb;
   L.pool = s->pool;
+  L.occ = s->occl;
   HIP_TRY(hipMemcpy(s->d_layout, &L, sizeof(L), hipMemcpyHostToDevice));
   return FLIX_OK;
 }
@@ -903,6 +845,18 @@ int bulk_load_body(flix_store* s, const K* keys, const K* vals, u64 n, hipStream
                        (K*)s->mkba, s->hdr, s->bnodes);
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_dir", __LINE__); }
+    // occupancy summary of the new directory
+    s->occl.w0 = s->occ;
+    s->occl.w1 = s->occ + occ_words0(nbk);
+    s->occl.w2 = s->occl.w1 + occ_words1(nbk);
+    hipLaunchKernelGGL(k_occ_build0, dim3((u32)((occ_words0(nbk) + 255) / 256)), dim3(256), 0, st,
+                       s->hdr, (u32)nbk, s->occl.w0);
+    hipLaunchKernelGGL(k_occ_build_up, dim3((u32)((occ_words1(nbk) + 255) / 256)), dim3(256), 0,
+                       st, (const u64*)s->occl.w0, occ_words0(nbk), s->occl.w1, occ_words1(nbk));
+    hipLaunchKernelGGL(k_occ_build_up, dim3((u32)((occ_words2(nbk) + 255) / 256)), dim3(256), 0,
+                       st, (const u64*)s->occl.w1, occ_words1(nbk), s->occl.w2, occ_words2(nbk));
+    e0 = hipGetLastError();
+    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "occupancy build", __LINE__); }
     u64 g2 = std::min<u64>((pool - nbk + 255) / 256 + 1, 65536);
     hipLaunchKernelGGL(k_build_free, dim3(g2), dim3(256), 0, st, (u32)nbk, pool, nd, s->free_ids,
                        s->ctl);
@@ -962,6 +916,7 @@ void destroy_all(flix_store* s) {
   dev_free(&s->split);
   dev_free(&s->gpre);
   dev_free(&s->gtot);
+  dev_free(&s->occ);
   dev_free(&s->hdr);
   dev_free(&s->nkeys);
   dev_free(&s->nvals);
@@ -995,84 +950,38 @@ void destroy_all(flix_store* s) {
 }
 
 // ---- persistent drain -------------------------------------------------------
-template <typename K, int RB, int GL, int KPL>
-int drain_launch_t(flix_store* s, const DrainBatch* d_batches, u32 nbatch,
-                   unsigned long long* d_ts, hipStream_t st) {
-  const u32 lds_items = upd_lds_items(s);
-  size_t shm = DrainSmemSize<K, RB, GL, KPL>::fixed();
-  size_t upd = (size_t)(256 / GL) * 2 * lds_items * sizeof(K);
-  if (upd > shm) shm = upd;
-  auto kfn = k_drain<K, RB, GL, KPL>;
-  if (s->drain_grid == 0 || s->drain_shm != shm) {
-    if (shm > 65536)
-      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kfn),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-    int per_cu = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 256, shm));
-    int dev = 0, cus = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    if (per_cu < 1) return FLIX_EINVAL;
-    // At most two workgroups per CU: every batch pays several grid barriers,
-    // whose cost grows with the arrivals; measured on the mixed-batch stream,
-    // two per CU beat three (540 vs 475 Mops/s) and one (537, slower on large
-    // batches).
-    s->drain_grid = std::min(per_cu, 2) * cus;
-    s->drain_shm = shm;
-  }
-  DrainArgs<K> a;
-  a.batches = d_batches;
-  a.nbatch = nbatch;
-  a.layout = s->d_layout;
-  a.cap = s->cap;
-  a.ctl = s->ctl;
-  a.bk[0] = (K*)s->bk[0];
-  a.bk[1] = (K*)s->bk[1];
-  a.bp[0] = s->bp[0];
-  a.bp[1] = s->bp[1];
-  a.hist = s->d_hist;
-  a.status = s->d_status;
-  a.status_cl = s->d_status_cl;
-  a.status_words = s->d_status_words;
-  a.cluster_words = s->d_cluster_words;
-  a.work = s->work;
-  a.lds_items = lds_items;
-  a.chunk = upd_chunk(s);
-  a.dctl = s->dctl;
-  a.tstamp = d_ts;
-  a.max_batch = (u32)s->max_batch;
-  hipLaunchKernelGGL(kfn, dim3(s->drain_grid), dim3(256), shm, st, a);
-  HIP_TRY(hipGetLastError());
-  return FLIX_OK;
-}
-
-template <typename K, int RB>
-int drain_launch_rb(flix_store* s, const DrainBatch* b, u32 nb, unsigned long long* ts,
-                    hipStream_t st) {
-  const u32 kpl = std::max<u32>(1u, s->cap / s->gl);
-  switch (s->gl * 100 + kpl) {
-    case 1601: return drain_launch_t<K, RB, 16, 1>(s, b, nb, ts, st);
-    case 1602: return drain_launch_t<K, RB, 16, 2>(s, b, nb, ts, st);
-    case 1604: return drain_launch_t<K, RB, 16, 4>(s, b, nb, ts, st);
-    case 1608: return drain_launch_t<K, RB, 16, 8>(s, b, nb, ts, st);
-    case 1616: return drain_launch_t<K, RB, 16, 16>(s, b, nb, ts, st);
-    case 3201: return drain_launch_t<K, RB, 32, 1>(s, b, nb, ts, st);
-    case 3202: return drain_launch_t<K, RB, 32, 2>(s, b, nb, ts, st);
-    case 3204: return drain_launch_t<K, RB, 32, 4>(s, b, nb, ts, st);
-    case 3208: return drain_launch_t<K, RB, 32, 8>(s, b, nb, ts, st);
-    case 6401: return drain_launch_t<K, RB, 64, 1>(s, b, nb, ts, st);
-    case 6402: return drain_launch_t<K, RB, 64, 2>(s, b, nb, ts, st);
-    default: return drain_launch_t<K, RB, 64, 4>(s, b, nb, ts, st);
-  }
-}
-
 int drain_launch(flix_store* s, const DrainBatch* b, u32 nb, unsigned long long* ts,
                  hipStream_t st) {
-  if (s->kb == 32)
-    return s->rb == 4 ? drain_launch_rb<u32, 4>(s, b, nb, ts, st)
-                      : drain_launch_rb<u32, 8>(s, b, nb, ts, st);
-  return s->rb == 4 ? drain_launch_rb<u64, 4>(s, b, nb, ts, st)
-                    : drain_launch_rb<u64, 8>(s, b, nb, ts, st);
+  DrainLaunch d;
+  d.key_bits = s->kb;
+  d.radix_bits = s->rb;
+  d.gl = s->gl;
+  d.cap = s->cap;
+  d.lds_items = upd_lds_items(s);
+  d.chunk = upd_chunk(s);
+  d.max_batch = (u32)s->max_batch;
+  d.batches = b;
+  d.nbatch = nb;
+  d.layout = s->d_layout;
+  d.ctl = s->ctl;
+  d.bk[0] = s->bk[0];
+  d.bk[1] = s->bk[1];
+  d.bp[0] = s->bp[0];
+  d.bp[1] = s->bp[1];
+  d.hist = s->d_hist;
+  d.status = s->d_status;
+  d.status_cl = s->d_status_cl;
+  d.status_words = s->d_status_words;
+  d.cluster_words = s->d_cluster_words;
+  d.work = s->work;
+  d.dctl = s->dctl;
+  d.tstamp = ts;
+  d.grid = &s->drain_grid;
+  d.shm = &s->drain_shm;
+  const hipError_t e = flix::drain_launch(d, st);
+  if (e == hipErrorInvalidConfiguration) return FLIX_EINVAL;
+  if (e != hipSuccess) return note_hip_error(e, "drain launch", __LINE__);
+  return FLIX_OK;
 }
 
 int drain_validate(flix_store* s, const flix_batch* h, u32 nbatch) {
@@ -1080,12 +989,13 @@ int drain_validate(flix_store* s, const flix_batch* h, u32 nbatch) {
   if (nbatch > (1u << 24)) return FLIX_EINVAL;
   for (u32 i = 0; i < nbatch; ++i) {
     const flix_batch& b = h[i];
-    if (b.op > FLIX_OP_DELETE) return FLIX_EINVAL;
+    if (b.op > FLIX_OP_PREDECESSOR) return FLIX_EINVAL;
     if (b.n == 0) continue;
     if (b.n > s->max_batch || !b.d_keys) return FLIX_EINVAL;
     if ((b.op == FLIX_OP_INSERT || b.op == FLIX_OP_RANGE) && !b.d_aux) return FLIX_EINVAL;
-    if (b.op <= FLIX_OP_SUCCESSOR && !b.d_vals_out) return FLIX_EINVAL;
-    if (b.op == FLIX_OP_SUCCESSOR && !b.d_keys_out) return FLIX_EINVAL;
+    const bool keyed = b.op == FLIX_OP_SUCCESSOR || b.op == FLIX_OP_PREDECESSOR;
+    if ((b.op == FLIX_OP_LOOKUP || keyed) && !b.d_vals_out) return FLIX_EINVAL;
+    if (keyed && !b.d_keys_out) return FLIX_EINVAL;
     if (b.op == FLIX_OP_RANGE && !b.d_counts) return FLIX_EINVAL;
   }
   return FLIX_OK;
@@ -1245,6 +1155,17 @@ int flix_successor(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_o
                                        nullptr, 0, S(stream));
 }
 
+int flix_predecessor(flix_store* s, const void* d_keys, uint64_t n, void* d_keys_out,
+                     void* d_vals_out, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  int c = check_args(s, n, {d_keys, d_keys_out, d_vals_out});
+  if (c) return c > 0 ? FLIX_OK : c;
+  return s->kb == 32 ? read_batch<u32>(s, kOpPredecessor, d_keys, n, d_keys_out, d_vals_out,
+                                       nullptr, nullptr, 0, S(stream))
+                     : read_batch<u64>(s, kOpPredecessor, d_keys, n, d_keys_out, d_vals_out,
+                                       nullptr, nullptr, 0, S(stream));
+}
+
 int flix_range(flix_store* s, const void* d_lo, const void* d_hi, uint64_t n,
                uint32_t max_per_query, uint32_t* d_counts, void* d_keys_out, void* d_vals_out,
                void* stream) {
@@ -1365,6 +1286,8 @@ int flix_check(flix_store* s, void* stream) {
                        counters, err);
   hipLaunchKernelGGL(k_check_free, dim3(std::min<u32>((s->pool + 255) / 256, 65535)), dim3(256), 0,
                      st, s->free_ids, s->ctl, s->pool, mark, err);
+  hipLaunchKernelGGL(k_occ_check, dim3((u32)std::min<u64>((occ_words(s->nb) + 255) / 256, 65535)),
+                     dim3(256), 0, st, s->hdr, s->nb, s->occl, err);
   u32 herr = 0;
   unsigned long long hc[2] = {0, 0};
   Ctl hctl;

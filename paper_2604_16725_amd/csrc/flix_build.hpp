@@ -2,6 +2,7 @@
 #pragma once
 
 #include "flix_device.hpp"
+#include "flix_occ.hpp"
 
 namespace flix {
 
@@ -263,6 +264,64 @@ __global__ void k_check_free(const u32* __restrict__ free_ids, const Ctl* __rest
   for (u32 j = blockIdx.x * blockDim.x + threadIdx.x; j < top; j += gridDim.x * blockDim.x) {
     u32 id = free_ids[j];
     if (id >= pool || atomicAdd(&mark[id], 1u) != 0u) atomicCAS(err, 0u, 11u);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Occupancy summary (flix_occ.hpp): build at bulk load, invariant check.
+// ---------------------------------------------------------------------------
+// Level 0 from the head sizes (a bucket is empty exactly when its head node is
+// empty: an empty head never has a successor node).
+__global__ void k_occ_build0(const NodeHdr* __restrict__ hdr, u32 nb, u64* __restrict__ w0) {
+  const u64 w = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= occ_words0(nb)) return;
+  u64 bits = 0;
+  for (u32 i = 0; i < 64; ++i) {
+    const u64 b = w * 64 + i;
+    if (b < nb && hdr[b].size > 0) bits |= 1ull << i;
+  }
+  w0[w] = bits;
+}
+
+// Level l+1 from level l (`n_hi` words above `n_lo` words below).
+__global__ void k_occ_build_up(const u64* __restrict__ lo, u64 n_lo, u64* __restrict__ hi,
+                               u64 n_hi) {
+  const u64 w = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= n_hi) return;
+  u64 bits = 0;
+  for (u32 i = 0; i < 64; ++i) {
+    const u64 j = w * 64 + i;
+    if (j < n_lo && lo[j] != 0) bits |= 1ull << i;
+  }
+  hi[w] = bits;
+}
+
+// Invariant check: level 0 equals the head sizes, upper levels summarise the
+// lower ones.  Records error 12 in *err.
+__global__ void k_occ_check(const NodeHdr* __restrict__ hdr, u32 nb, OccLevels o,
+                            u32* __restrict__ err) {
+  const u64 n0 = occ_words0(nb), n1 = occ_words1(nb), n2 = occ_words2(nb);
+  for (u64 w = (u64)blockIdx.x * blockDim.x + threadIdx.x; w < n0 + n1 + n2;
+       w += (u64)gridDim.x * blockDim.x) {
+    u64 want = 0, got;
+    if (w < n0) {
+      for (u32 i = 0; i < 64; ++i) {
+        const u64 b = w * 64 + i;
+        if (b < nb && hdr[b].size > 0) want |= 1ull << i;
+      }
+      got = o.w0[w];
+    } else if (w < n0 + n1) {
+      const u64 v = w - n0;
+      for (u32 i = 0; i < 64; ++i)
+        if (v * 64 + i < n0 && o.w0[v * 64 + i] != 0) want |= 1ull << i;
+      got = o.w1[v];
+    } else {
+      const u64 v = w - n0 - n1;
+      for (u32 i = 0; i < 64; ++i)
+        if (v * 64 + i < n1 && o.w1[v * 64 + i] != 0) want |= 1ull << i;
+      got = o.w2[v];
+    }
+    if (want != got) atomicCAS(err, 0u, 12u);
   }
 }
 

@@ -23,6 +23,7 @@ namespace flix {
 
 constexpr u32 kOpInsert = 3;
 constexpr u32 kOpDelete = 4;
+constexpr u32 kOpLast = 5;   // predecessor
 
 struct alignas(16) DrainBatch {
   u32 op;
@@ -65,6 +66,7 @@ struct alignas(16) StoreLayout {
   u32 nb;
   u32 pool;
   u32 pad[2];
+  OccLevels occ;
 };
 
 template <typename K>
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   for (u32 bi = 0; bi < a.nbatch; ++bi) {
     const DrainBatch d = a.batches[bi];
     const u32 n = d.n;
-    if (n > a.max_batch || d.op > kOpDelete) {   // rewritten descriptor out of range
+    if (n > a.max_batch || d.op > kOpLast) {   // rewritten descriptor out of range
       if (blk == 0 && threadIdx.x == 0) atomicOr(&dc->err, 4u);
       continue;
     }
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (blk == 0 && threadIdx.x == 0 && a.tstamp) a.tstamp[bi + 1] = wall_clock64();
       continue;
     }
-    const bool is_update = d.op >= kOpInsert;
+    const bool is_update = d.op == kOpInsert || d.op == kOpDelete;
     const u32 slot = nz & 1u;
     ++nz;
     u32* hist = a.hist + slot * (P * R);
@@ -305,6 +307,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ra.maxpq = d.maxpq;
       ra.pool = L.pool;
       ra.err = &a.ctl->status;
+      ra.occ = L.occ;
       ra.cuts = nullptr;   // each share searches its own cuts
       const u32 nshares = (u32)(((u64)n + L.nb + SR - 1) / SR);
       for (u32 vb = blk; vb < nshares; vb += G) {
@@ -351,6 +354,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ua.rcap = work_region_cap(a.max_batch);
       ua.ctl = a.ctl;
       ua.status = &a.ctl->status;
+      ua.occ = L.occ;
       if (d.op == kOpInsert)
         insert_items<K, GL, 256>(ua, a.lds_items, blk, G, smem, s_upd);
       else

@@ -11,12 +11,14 @@
 #pragma once
 
 #include "flix_device.hpp"
+#include "flix_occ.hpp"
 
 namespace flix {
 
 constexpr int kOpLookup = 0;
 constexpr int kOpSuccessor = 1;
 constexpr int kOpRange = 2;
+constexpr int kOpPredecessor = 5;   // 3 and 4 are the update operations
 
 template <typename K>
 struct ReadArgs {
@@ -37,6 +39,7 @@ struct ReadArgs {
   u32 maxpq;           // range output stride
   u32 pool;            // nodes in the pool (bound of every link)
   u32* err;            // sticky status word for internal errors
+  OccLevels occ;       // which buckets hold keys (flix_occ.hpp)
   const u32* cuts;     // merge-path cut of every share boundary [nshares + 1], or
                        // nullptr: each workgroup searches its own two cuts
 };
@@ -155,24 +158,57 @@ __device__ __forceinline__ u32 locate_node(const NodeHdr* hdr, u32 pool, u32 b, 
 
 // First node after (bucket b, node with header h) that holds a key: the next
 // node of the chain (non-head nodes are never empty), else the head of the
-// next non-empty bucket.  Returns kNil when none exists, kBadLink for a link
-// outside the pool.
-__device__ __forceinline__ u32 next_nonempty(const NodeHdr* hdr, u32 nb, u32 pool, u32* b,
-                                             const NodeHdr& h, NodeHdr* out) {
+// next bucket that holds a key (occupancy summary).  Returns kNil when none
+// exists, kBadLink for a link outside the pool.
+__device__ __forceinline__ u32 next_nonempty(const NodeHdr* hdr, const OccLevels& occ, u32 nb,
+                                             u32 pool, u32* b, const NodeHdr& h, NodeHdr* out) {
   if (h.next != kNil) {
     if (h.next >= pool) return kBadLink;
     *out = hdr[h.next];
     return h.next;
   }
-  for (u32 bb = *b + 1; bb < nb; ++bb) {
-    NodeHdr g = hdr[bb];
-    if (g.size > 0) {
-      *b = bb;
-      *out = g;
-      return bb;
-    }
+  const u32 bb = occ_next(occ, nb, *b);
+  if (bb >= nb) return kNil;
+  *b = bb;
+  *out = hdr[bb];
+  return bb;
+}
+
+// Predecessor of x in the store, x owned by bucket b (Section 2.1): the
+// largest stored key <= x.  Walks b's chain to the node whose range holds x,
+// remembering the node before it; if that node has no key <= x the answer is
+// the last key of the previous node, else of the last node of the previous
+// bucket that holds keys.  Returns the slot (node * cap + position) or
+// ~0ull when there is none; kBadLink in *bad for a link outside the pool.
+template <typename K>
+__device__ inline u64 predecessor_slot(const NodeHdr* hdr, const K* nkeys, const OccLevels& occ,
+                                       u32 pool, u32 cap, u32 b, K x, bool* bad) {
+  u32 node = b, prevn = kNil;
+  NodeHdr h = hdr[node], hp;
+  hp.size = 0;
+  while ((u64)x > h.fence && h.next != kNil) {
+    prevn = node;
+    hp = h;
+    node = h.next;
+    if (node >= pool) { *bad = true; return ~0ull; }
+    h = hdr[node];
   }
-  return kNil;
+  if (h.size > cap || hp.size > cap) { *bad = true; return ~0ull; }   // never expected
+  const u32 p = upper_bound_idx<K>(nkeys + (u64)node * cap, 0u, h.size, x);
+  if (p > 0) return (u64)node * cap + (p - 1);
+  if (prevn != kNil && hp.size > 0) return (u64)prevn * cap + (hp.size - 1);
+  const u32 pb = occ_prev(occ, b);
+  if (pb == kNil) return ~0ull;
+  node = pb;
+  h = hdr[node];
+  u32 steps = 0;
+  while (h.next != kNil) {
+    node = h.next;
+    if (node >= pool || ++steps > pool) { *bad = true; return ~0ull; }
+    h = hdr[node];
+  }
+  if (h.size == 0 || h.size > cap) { *bad = true; return ~0ull; }   // summary or node corrupt
+  return (u64)node * cap + (h.size - 1);
 }
 
 }  // namespace flix

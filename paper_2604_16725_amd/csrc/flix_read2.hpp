@@ -148,20 +148,26 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
             // so the lanes whose first key is below x form a prefix of L
             // lanes and the bound lies in lane L-1: one ballot over first
             // keys plus that lane's own count.
+            // A predecessor needs the upper bound of x itself.
             const bool v0 = gl * KPL < size;
+            const K ub = (op == kOpRange) ? hi : x;
+            const bool need_ub = op == kOpRange || op == kOpPredecessor;
             u32 c_lt = 0, c_le = 0;
 #pragma unroll
             for (int k = 0; k < KPL; ++k) {
               const bool v = gl * KPL + k < size;
               c_lt += (v && kv[u].k[k] < x) ? 1u : 0u;
-              if (op == kOpRange) c_le += (v && kv[u].k[k] <= hi) ? 1u : 0u;
+              if (need_ub) c_le += (v && kv[u].k[k] <= ub) ? 1u : 0u;
             }
-            const u32 L1 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] < x) & gmask);
-            const u32 s_lt = (u32)__shfl((int)c_lt, (int)(gbase + (L1 ? L1 - 1 : 0)), 64);
-            const u32 lt = L1 ? (L1 - 1) * KPL + s_lt : 0u;
+            u32 lt = 0;
+            if (op != kOpPredecessor) {
+              const u32 L1 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] < x) & gmask);
+              const u32 s_lt = (u32)__shfl((int)c_lt, (int)(gbase + (L1 ? L1 - 1 : 0)), 64);
+              lt = L1 ? (L1 - 1) * KPL + s_lt : 0u;
+            }
             u32 le = 0;
-            if (op == kOpRange) {
-              const u32 L2 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] <= hi) & gmask);
+            if (need_ub) {
+              const u32 L2 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] <= ub) & gmask);
               const u32 s_le = (u32)__shfl((int)c_le, (int)(gbase + (L2 ? L2 - 1 : 0)), 64);
               le = L2 ? (L2 - 1) * KPL + s_le : 0u;
             }
@@ -169,6 +175,8 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
               u32 code;
               if (op == kOpSuccessor) {
                 code = lt < size ? lt : kPosSlow;
+              } else if (op == kOpPredecessor) {
+                code = le > 0 ? le - 1 : kPosSlow;   // none in this node: look before it
               } else {
                 if (x > hi) {
                   code = 0;
@@ -189,9 +197,11 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
   }
   __syncthreads();
 
-  // Phase B: one lane per key.  Lookups and successors resolved in phase A
-  // issue all of a thread's value (and key) loads before its output writes.
+  // Phase B: one lane per key.  Lookups, successors and predecessors resolved
+  // in phase A issue all of a thread's value (and key) loads before its
+  // output writes.
   const K NF = key_max<K>();
+  const bool with_key = op == kOpSuccessor || op == kOpPredecessor;
   if (op != kOpRange) {
     K rv[RQ], rk[RQ];
     u32 pc[RQ];
@@ -205,7 +215,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
       if (pos != kPosSlow && pos != kPosMiss) {
         const u64 at = (u64)(b0 + (pc[r] >> 16)) * a.cap + pos;
         rv[r] = a.nvals[at];
-        if (op == kOpSuccessor) rk[r] = a.nkeys[at];
+        if (with_key) rk[r] = a.nkeys[at];
       }
     }
 #pragma unroll
@@ -214,7 +224,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
       if ((pc[r] & 0xFFFFu) != kPosSlow) {
         const u32 orig = s_idx[j];
         a.out_v[orig] = rv[r];
-        if (op == kOpSuccessor) a.out_k[orig] = rk[r];
+        if (with_key) a.out_k[orig] = rk[r];
       }
     }
   }
@@ -241,6 +251,14 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
       }
       continue;
     }
+    if (op == kOpPredecessor) {
+      bool bad = false;
+      const u64 at = predecessor_slot<K>(a.hdr, a.nkeys, a.occ, a.pool, a.cap, b, x, &bad);
+      if (bad) atomicCAS(a.err, 0u, kErrInternal);
+      a.out_k[orig] = at == ~0ull ? K(0) : a.nkeys[at];
+      a.out_v[orig] = at == ~0ull ? NF : a.nvals[at];
+      continue;
+    }
     // Global-memory path: walk the chain to the node holding x.
     NodeHdr h;
     u32 node = locate_node(a.hdr, a.pool, b, (u64)x, &h);
@@ -262,7 +280,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
         rv = a.nvals[(u64)node * a.cap + p];
       } else {
         NodeHdr g;
-        u32 nn = next_nonempty(a.hdr, a.nb, a.pool, &b, h, &g);
+        u32 nn = next_nonempty(a.hdr, a.occ, a.nb, a.pool, &b, h, &g);
         if (nn == kBadLink) {
           atomicCAS(a.err, 0u, kErrInternal);
         } else if (nn != kNil) {
@@ -287,7 +305,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
           }
           if (ub < h.size) break;
           NodeHdr g;
-          u32 nn = next_nonempty(a.hdr, a.nb, a.pool, &b, h, &g);
+          u32 nn = next_nonempty(a.hdr, a.occ, a.nb, a.pool, &b, h, &g);
           if (nn == kBadLink) {
             atomicCAS(a.err, 0u, kErrInternal);
             break;

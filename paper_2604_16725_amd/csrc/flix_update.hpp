@@ -17,6 +17,7 @@
 #pragma once
 
 #include "flix_device.hpp"
+#include "flix_occ.hpp"
 #include "flix_read.hpp"
 
 namespace flix {
@@ -365,6 +366,7 @@ struct UpdArgs {
   u32 rcap;           // work_region_cap(max_batch)
   Ctl* ctl;
   u32* status;        // sticky status word (== &ctl->status)
+  OccLevels occ;      // bucket occupancy summary, kept current here
 };
 
 // Workgroup-shared state of the apply kernels: a key counter and the map of
@@ -462,6 +464,8 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
     bool fresh = false;   // this group has written nodes of this bucket: read coherently
     u32 j = w.s;
     u32 nodes_added = 0;
+    const u64 added_before = added;
+    const bool was_empty = (w.head & kSingleNode) && (w.head & ~kSingleNode) == 0;
     while (j < w.e) {
       bool broken = false;
       if (hX.next != kNil) {   // chain: walk to the node holding skeys[j]
@@ -708,6 +712,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       wave_lds_sync();
     }
     if (nodes_added && g.lane == 0) a.bnodes[w.b] += nodes_added;
+    if (was_empty && added > added_before && g.lane == 0) occ_set(a.occ, w.b);
   }
   // per-lane `added` is identical across a group's lanes: count once per group
   if (g.lane == 0 && added) atomicAdd(&s_added, added);
@@ -785,6 +790,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
     }
     u32 j = w.s;
     int freed = 0;
+    const bool was_empty = (w.head & kSingleNode) && (w.head & ~kSingleNode) == 0;
     while (true) {
       // the last node of a chain takes every remaining key of the slice
       u32 j2 = (j >= w.e) ? j
@@ -941,6 +947,10 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
     }
     if (P != kNil && p_dirty && g.lane == 0) write_hdr(a.hdr + P, hP, p_fence_known);
     if (freed && g.lane == 0) a.bnodes[w.b] -= (u32)freed;
+    // the head stays the predecessor while it is empty, so an emptied bucket
+    // ends with P at its head, size 0 and no link
+    if (!was_empty && P == w.b && hP.size == 0 && hP.next == kNil && g.lane == 0)
+      occ_clear(a.occ, w.b);
   }
   if (g.lane == 0 && removed) atomicAdd(&s_removed, removed);
   __syncthreads();

@@ -86,9 +86,9 @@ class FlixEpoch(ctypes.Structure):
 
 
 EPOCH_SLOTS = 2
-OP_LOOKUP, OP_SUCCESSOR, OP_RANGE, OP_INSERT, OP_DELETE = 0, 1, 2, 3, 4
+OP_LOOKUP, OP_SUCCESSOR, OP_RANGE, OP_INSERT, OP_DELETE, OP_PREDECESSOR = 0, 1, 2, 3, 4, 5
 OPS = {"lookup": OP_LOOKUP, "successor": OP_SUCCESSOR, "range": OP_RANGE,
-       "insert": OP_INSERT, "delete": OP_DELETE}
+       "insert": OP_INSERT, "delete": OP_DELETE, "predecessor": OP_PREDECESSOR}
 
 _lib = None
 
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "flix_delete": (i32, [vp, vp, u64, vp]),
         "flix_lookup": (i32, [vp, vp, u64, vp, vp]),
         "flix_successor": (i32, [vp, vp, u64, vp, vp, vp]),
+        "flix_predecessor": (i32, [vp, vp, u64, vp, vp, vp]),
         "flix_range": (i32, [vp, vp, vp, u64, u32, vp, vp, vp, vp]),
         "flix_destroy": (i32, [vp]),
         "flix_size": (i32, [vp, ctypes.POINTER(u64), vp]),
@@ -238,6 +239,14 @@ class Store:
         out_v = self._empty(n) if out_v is None else out_v
         self._chk(self.lib.flix_successor(self.h, _ptr(self._dev(keys)), n, _ptr(out_k),
                                           _ptr(out_v), _stream(stream)), "flix_successor")
+        return out_k, out_v
+
+    def predecessor(self, keys, out_k=None, out_v=None, stream=None):
+        n = keys.numel()
+        out_k = self._empty(n) if out_k is None else out_k
+        out_v = self._empty(n) if out_v is None else out_v
+        self._chk(self.lib.flix_predecessor(self.h, _ptr(self._dev(keys)), n, _ptr(out_k),
+                                            _ptr(out_v), _stream(stream)), "flix_predecessor")
         return out_k, out_v
 
     def range(self, lo, hi, max_per_query: int, counts=None, out_k=None, out_v=None,

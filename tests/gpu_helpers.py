@@ -56,7 +56,7 @@ def assert_same_contents(store, orc, kb, where=""):
 
 
 def check_reads(store, orc, kb, q, maxpq=8, lo=None, hi=None, where=""):
-    """Lookup, successor and range on the same keys, bit-exact."""
+    """Lookup, successor, predecessor and range on the same keys, bit-exact."""
     dq = to_dev(q)
     g = to_host(store.lookup(dq), kb)
     o = orc.lookup(q)
@@ -67,6 +67,11 @@ def check_reads(store, orc, kb, q, maxpq=8, lo=None, hi=None, where=""):
     ok, ov = orc.successor(q)
     bad = np.nonzero((gk != ok) | (gv != ov))[0]
     assert bad.size == 0, f"{where} successor mismatch at {bad[:5]}: q={q[bad[:3]]} {gk[bad[:3]]} vs {ok[bad[:3]]}"
+    gk, gv = store.predecessor(dq)
+    gk, gv = to_host(gk, kb), to_host(gv, kb)
+    ok, ov = orc.predecessor(q)
+    bad = np.nonzero((gk != ok) | (gv != ov))[0]
+    assert bad.size == 0, f"{where} predecessor mismatch at {bad[:5]}: q={q[bad[:3]]} {gk[bad[:3]]} vs {ok[bad[:3]]}"
     if lo is None:
         lo = q
         mx = (1 << kb) - 1

@@ -484,3 +484,42 @@ def test_range_edge_cases(kb):
                 assert np.array_equal(got[mask], ref[mask]), f"maxpq={maxpq} results"
                 assert (got[~mask] == sent_u).all(), f"maxpq={maxpq}: slot beyond count written"
     assert s.status() == 0
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_reads_across_long_runs_of_empty_buckets(kb):
+    """Successor, predecessor and range across more than 10^4 consecutive
+    empty buckets (a contiguous key range deleted), and at both ends of the
+    key space; the occupancy summary is part of the device invariant check."""
+    log(f"empty-bucket gaps kb={kb}")
+    dt = ktype(kb)
+    s, o = new_pair(kb, cap=16, max_batch=1 << 19)
+    n = 1 << 19
+    keys = (np.arange(n, dtype=np.uint64) * np.uint64(7) + np.uint64(100)).astype(dt)
+    vals = (keys.astype(np.uint64) ^ np.uint64(0x5A5A)).astype(dt)
+    s.bulk_load(to_dev(keys), to_dev(vals))
+    o.bulk_load(keys, vals)
+    # 8 keys per bucket: deleting 160000 consecutive keys empties 20000 buckets;
+    # also empty the first and the last 2000 buckets
+    gone = np.concatenate([keys[100000:260000], keys[:16000], keys[-16000:]])
+    rng = np.random.default_rng(3 + kb)
+    rng.shuffle(gone)
+    s.delete(to_dev(gone))
+    o.delete(gone)
+    assert_same_contents(s, o, kb, "after the gap deletes")
+    lo_gap, hi_gap = int(keys[100000]), int(keys[259999])
+    q = np.concatenate([
+        rng.integers(lo_gap - 50, hi_gap + 50, 3000, dtype=np.uint64).astype(dt),
+        rng.integers(0, int(keys[16000]) + 10, 500, dtype=np.uint64).astype(dt),
+        rng.integers(int(keys[-16000]) - 10, int(keys[-1]) + 10, 500, dtype=np.uint64).astype(dt),
+        np.array([0, (1 << kb) - 1], dtype=dt)])
+    lo = q.copy()
+    hi = np.minimum(q.astype(np.uint64) + np.uint64(hi_gap - lo_gap + 40),
+                    np.uint64((1 << kb) - 1)).astype(dt)
+    check_reads(s, o, kb, q, maxpq=4, lo=lo, hi=hi, where="gap")
+    # refill part of the gap: buckets become non-empty again
+    back = keys[150000:150100]
+    s.insert(to_dev(back), to_dev(vals[150000:150100]))
+    o.insert(back, vals[150000:150100])
+    assert_same_contents(s, o, kb, "after refilling")
+    check_reads(s, o, kb, q, maxpq=4, lo=lo, hi=hi, where="gap refilled")
