@@ -71,10 +71,24 @@ typedef struct {
   uint64_t pool_bytes;      /* node pool budget in bytes; 0 = automatic (see below) */
   uint32_t fill;            /* keys per node at bulk load (Section 3.2: p = NS/2);
                                0 = bucket_capacity/2; at most bucket_capacity */
-  uint32_t reserved;        /* must be 0 */
+  uint32_t insert_algo;     /* insert kernel, one of FLIX_INSERT_* (0 = TL-Bulk) */
 } flix_config;
 
-/* Create an empty store (one bucket covering every key).  Allocates the
+/* Insert kernels (Section 4.2.1 ST-Shift-Right, Section 4.3.2 TL-Bulk,
+ * Section 5.3.5 ST-TL-Mixed, Section 3.4 adaptive compute per bucket).  All
+ * give the same contents; they differ in how lanes are assigned to buckets. */
+#define FLIX_INSERT_TL_BULK 0        /* a group of lanes_per_bucket lanes per bucket */
+#define FLIX_INSERT_ST_SHIFT_RIGHT 1 /* one lane per bucket, key by key */
+#define FLIX_INSERT_ST_TL_MIXED 2    /* per call: ST-Shift-Right when the call averages at
+                                        most FLIX_ST_MAX_KEYS batch keys per touched
+                                        bucket, TL-Bulk otherwise */
+#define FLIX_INSERT_ADAPTIVE 3       /* per bucket: one lane for a slice of at most
+                                        FLIX_ST_MAX_KEYS batch keys, a lane group otherwise */
+#define FLIX_ST_MAX_KEYS 4
+
+/* Create an empty store (Section 3.2 layout: a maxBucket directory over
+ * buckets of chained fixed-capacity nodes; empty, it is one bucket covering
+ * every key).  Allocates the
  * directory, the node pool and scratch sized by cfg->max_batch.  With
  * pool_bytes == 0 the pool is sized automatically: 2x the nodes a bulk load
  * needs plus room for one max_batch of inserts, re-sized by flix_bulk_load.
@@ -122,7 +136,19 @@ int flix_range(flix_store* s, const void* d_lo, const void* d_hi, uint64_t n,
                uint32_t max_per_query, uint32_t* d_counts, void* d_keys_out, void* d_vals_out,
                void* stream);
 
-/* Free every resource of the store.  Synchronizes with the device. */
+/* Restructuring (Section 3.5, evaluated in Section 6.6): the live pairs are
+ * laid out again by the initial-build rule (Section 3.2) at the bulk-load fill,
+ * so every bucket is one node again: chains are flattened, underfull nodes are
+ * merged into nodes of `fill` keys, and maxBucket follows the current key
+ * distribution.  Contents are unchanged.  The pool keeps its size.
+ * *nodes_before / *nodes_after (either may be NULL) receive the nodes in use
+ * before and after.  A pool with fewer than ceil(keys / fill) nodes ->
+ * FLIX_ENOMEM, nothing changed.  Synchronizes; the store must be idle. */
+int flix_restructure(flix_store* s, uint64_t* nodes_before, uint64_t* nodes_after, void* stream);
+
+/* Free every resource of the store (Section 3.2 lists what a store holds: the
+ * maxBucket directory and the node pool; here also the scratch).
+ * Synchronizes with the device. */
 int flix_destroy(flix_store* s);
 
 /* Number of stored keys.  Synchronizes `stream`. */

@@ -24,13 +24,13 @@ using namespace flix;
 
 namespace {
 
-constexpr int kFamilies = 10;
+constexpr int kFamilies = 11;
 const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
                                        "insert_apply", "delete_apply", "read_cuts", "sort_local",
-                                       "part", "group_read"};
+                                       "part", "group_read", "insert_st"};
 enum Family {
   F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6,
-  F_LOCAL = 7, F_PART = 8, F_GROUP = 9
+  F_LOCAL = 7, F_PART = 8, F_GROUP = 9, F_INSERT_ST = 10
 };
 int sort_family(int fam) { return fam == 0 ? F_HIST : fam == 1 ? F_PASS : F_LOCAL; }
 
@@ -233,17 +233,29 @@ u64 group_tiles(u64 n) {
   return t < kGroupTilesMax ? t : kGroupTilesMax;
 }
 
+// Directory arrays for nb buckets.  The new arrays are allocated before the
+// old ones are freed, so a failed allocation leaves the directory as it was.
 int alloc_dir(flix_store* s, u32 nb) {
   if (nb <= s->nb_alloc) return FLIX_OK;
+  void* mk = nullptr;
+  u32* bn = nullptr;
+  u64* oc = nullptr;
+  u32* cu = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&mk, (u64)nb * s->ksz)) || (rc = dev_alloc(&bn, (u64)nb * sizeof(u32))) ||
+      (rc = dev_alloc(&oc, occ_words(nb) * sizeof(u64))) ||
+      (rc = dev_alloc(&cu, (cuts_for(s->max_batch, nb) * sizeof(u32))))) {
+    dev_free(&mk); dev_free(&bn); dev_free(&oc); dev_free(&cu);
+    return rc;
+  }
   dev_free(&s->mkba);
   dev_free(&s->bnodes);
   dev_free(&s->cuts);
   dev_free(&s->occ);
-  int rc;
-  if ((rc = dev_alloc(&s->mkba, (u64)nb * s->ksz))) return rc;
-  if ((rc = dev_alloc(&s->bnodes, (u64)nb * sizeof(u32)))) return rc;
-  if ((rc = dev_alloc(&s->occ, occ_words(nb) * sizeof(u64)))) return rc;
-  if ((rc = dev_alloc(&s->cuts, (cuts_for(s->max_batch, nb) * sizeof(u32))))) return rc;
+  s->mkba = mk;
+  s->bnodes = bn;
+  s->occ = oc;
+  s->cuts = cu;
   s->nb_alloc = nb;
   return FLIX_OK;
 }
@@ -582,6 +594,24 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   ua.occ = s->occl;
   u32 lds_items = upd_lds_items(s);
   u64 items = std::min<u64>(n, s->nb);
+  // insert kernel choice: the single-lane kernel takes the items its selector
+  // names, the lane-group kernel the complement
+  const u32 algo = (insert && !m_dev) ? s->cfg.insert_algo : (u32)FLIX_INSERT_TL_BULK;
+  if (algo != FLIX_INSERT_TL_BULK) {
+    UpdArgs<K> us = ua;
+    us.sel = algo == FLIX_INSERT_ST_SHIFT_RIGHT ? kSelAll
+           : algo == FLIX_INSERT_ST_TL_MIXED    ? kSelRound
+                                                : kSelShort;
+    us.st_max = FLIX_ST_MAX_KEYS;
+    const u32 grid = (u32)std::max<u64>(1, (items + 255) / 256);
+    const TmTok ts = tm_arm(s, F_INSERT_ST);
+    launch_timed(ts.b, ts.e, k_insert_st<K, 256>, dim3(grid), dim3(256), 0, st, us);
+    tm_done(s, F_INSERT_ST, ts);
+    HIP_TRY(hipGetLastError());
+    if (algo == FLIX_INSERT_ST_SHIFT_RIGHT) return FLIX_OK;
+    ua.sel = algo == FLIX_INSERT_ST_TL_MIXED ? kSelRoundL : kSelLong;
+    ua.st_max = FLIX_ST_MAX_KEYS;
+  }
   t = tm_arm(s, insert ? F_INSERT : F_DELETE);
   switch (s->gl) {
     case 16: launch_update<K, 16>(s, insert, ua, items, st, lds_items, m_dev, t); break;
@@ -765,6 +795,76 @@ int publish_layout(flix_store* s) {
   return FLIX_OK;
 }
 
+// Every pair in ascending key order into ko / vo (at most `capacity` of them):
+// per-bucket totals, their scan, then one wave per bucket copies its chain.
+// Synchronizes st.
+int dump_body(flix_store* s, void* ko, void* vo, u64 capacity, hipStream_t st) {
+  u32 nb = s->nb;
+  u32 nblk = (nb + 255) / 256;
+  u32 *tot = nullptr, *off = nullptr, *bs = nullptr, *dummy = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&tot, (u64)nb * 4)) || (rc = dev_alloc(&off, (u64)nb * 4)) ||
+      (rc = dev_alloc(&bs, (u64)nblk * 4)) || (rc = dev_alloc(&dummy, 16))) {
+    dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
+    return rc;
+  }
+  u32 g = std::min<u32>(nblk, 65535);
+  hipLaunchKernelGGL(k_bucket_totals, dim3(g), dim3(256), 0, st, s->hdr, nb, s->pool, tot);
+  hipLaunchKernelGGL(k_scan_blocks_u32, dim3(nblk), dim3(256), 0, st, tot, nb, off, bs);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bs, nblk, dummy);
+  hipLaunchKernelGGL(k_scan_addback, dim3(nblk), dim3(256), 0, st, off, nb, bs);
+  u32 gw = std::min<u32>((nb + 3) / 4, 65535);
+  if (s->kb == 32)
+    hipLaunchKernelGGL((k_dump_copy<u32>), dim3(gw), dim3(256), 0, st, s->hdr, (const u32*)s->nkeys,
+                       (const u32*)s->nvals, nb, s->cap, s->pool, off, (u32*)ko,
+                       (u32*)vo, (u64)capacity);
+  else
+    hipLaunchKernelGGL((k_dump_copy<u64>), dim3(gw), dim3(256), 0, st, s->hdr, (const u64*)s->nkeys,
+                       (const u64*)s->nvals, nb, s->cap, s->pool, off, (u64*)ko,
+                       (u64*)vo, (u64)capacity);
+  hipError_t e1 = hipGetLastError();
+  hipError_t e2 = hipStreamSynchronize(st);
+  dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
+  return (e1 == hipSuccess && e2 == hipSuccess) ? FLIX_OK : FLIX_EHIP;
+}
+
+// Nodes, directory, occupancy summary and free stack from nd sorted, distinct
+// pairs (Section 3.2 build rule: groups of `fill` consecutive keys, one node
+// per bucket, the last key of a group is its maxBucket, KEY_MAX for the last
+// bucket).  The pool and a directory of at least nbk buckets are allocated.
+// Asynchronous on st.
+template <typename K>
+int build_layout(flix_store* s, const K* ck, const K* cv, u64 nd, u32 nbk, hipStream_t st) {
+  const u32 pool = s->pool;
+  HIP_TRY(hipGetLastError());
+  s->nb = nbk;
+  if (nd) {
+    u64 g = std::min<u64>((nd + 255) / 256, 65536);
+    hipLaunchKernelGGL((k_build_nodes<K>), dim3(g), dim3(256), 0, st, ck, cv, nd, s->fill, s->cap,
+                       (K*)s->nkeys, (K*)s->nvals);
+    HIP_TRY(hipGetLastError());
+  }
+  u64 g = std::min<u64>((nbk + 255) / 256, 65536);
+  hipLaunchKernelGGL((k_build_dir<K>), dim3(g), dim3(256), 0, st, ck, nd, s->fill, nbk,
+                     (K*)s->mkba, s->hdr, s->bnodes);
+  HIP_TRY(hipGetLastError());
+  // occupancy summary of the new directory
+  s->occl.w0 = s->occ;
+  s->occl.w1 = s->occ + occ_words0(nbk);
+  s->occl.w2 = s->occl.w1 + occ_words1(nbk);
+  hipLaunchKernelGGL(k_occ_build0, dim3((u32)((occ_words0(nbk) + 255) / 256)), dim3(256), 0, st,
+                     s->hdr, nbk, s->occl.w0);
+  hipLaunchKernelGGL(k_occ_build_up, dim3((u32)((occ_words1(nbk) + 255) / 256)), dim3(256), 0,
+                     st, (const u64*)s->occl.w0, occ_words0(nbk), s->occl.w1, occ_words1(nbk));
+  hipLaunchKernelGGL(k_occ_build_up, dim3((u32)((occ_words2(nbk) + 255) / 256)), dim3(256), 0,
+                     st, (const u64*)s->occl.w1, occ_words1(nbk), s->occl.w2, occ_words2(nbk));
+  HIP_TRY(hipGetLastError());
+  u64 g2 = std::min<u64>((pool - nbk + 255) / 256 + 1, 65536);
+  hipLaunchKernelGGL(k_build_free, dim3(g2), dim3(256), 0, st, nbk, pool, nd, s->free_ids, s->ctl);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
 template <typename K>
 int bulk_load_body(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t st) {
   if (n > 0xFFFFFFF0ull) return FLIX_EINVAL;
@@ -829,40 +929,7 @@ int bulk_load_body(flix_store* s, const K* keys, const K* vals, u64 n, hipStream
     if ((rc = alloc_pool(s, pool))) { cleanup(); return rc; }
   }
   if ((rc = alloc_dir(s, (u32)nbk))) { cleanup(); return rc; }
-  HIP_TRY(hipGetLastError());
-  s->nb = (u32)nbk;
-  (void)hipGetLastError();
-  if (nd) {
-    u64 g = std::min<u64>((nd + 255) / 256, 65536);
-    hipLaunchKernelGGL((k_build_nodes<K>), dim3(g), dim3(256), 0, st, ck, cv, nd, s->fill, s->cap,
-                       (K*)s->nkeys, (K*)s->nvals);
-    hipError_t e0 = hipGetLastError();
-    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_nodes", __LINE__); }
-  }
-  {
-    u64 g = std::min<u64>((nbk + 255) / 256, 65536);
-    hipLaunchKernelGGL((k_build_dir<K>), dim3(g), dim3(256), 0, st, ck, nd, s->fill, (u32)nbk,
-                       (K*)s->mkba, s->hdr, s->bnodes);
-    hipError_t e0 = hipGetLastError();
-    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_dir", __LINE__); }
-    // occupancy summary of the new directory
-    s->occl.w0 = s->occ;
-    s->occl.w1 = s->occ + occ_words0(nbk);
-    s->occl.w2 = s->occl.w1 + occ_words1(nbk);
-    hipLaunchKernelGGL(k_occ_build0, dim3((u32)((occ_words0(nbk) + 255) / 256)), dim3(256), 0, st,
-                       s->hdr, (u32)nbk, s->occl.w0);
-    hipLaunchKernelGGL(k_occ_build_up, dim3((u32)((occ_words1(nbk) + 255) / 256)), dim3(256), 0,
-                       st, (const u64*)s->occl.w0, occ_words0(nbk), s->occl.w1, occ_words1(nbk));
-    hipLaunchKernelGGL(k_occ_build_up, dim3((u32)((occ_words2(nbk) + 255) / 256)), dim3(256), 0,
-                       st, (const u64*)s->occl.w1, occ_words1(nbk), s->occl.w2, occ_words2(nbk));
-    e0 = hipGetLastError();
-    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "occupancy build", __LINE__); }
-    u64 g2 = std::min<u64>((pool - nbk + 255) / 256 + 1, 65536);
-    hipLaunchKernelGGL(k_build_free, dim3(g2), dim3(256), 0, st, (u32)nbk, pool, nd, s->free_ids,
-                       s->ctl);
-    e0 = hipGetLastError();
-    if (e0 != hipSuccess) { cleanup(); return note_hip_error(e0, "k_build_free", __LINE__); }
-  }
+  if ((rc = build_layout<K>(s, ck, cv, nd, (u32)nbk, st))) { cleanup(); return rc; }
   hipError_t e1 = hipGetLastError();
   hipError_t e2 = hipStreamSynchronize(st);
   cleanup();
@@ -899,6 +966,45 @@ int bulk_load_t(flix_store* s, const K* keys, const K* vals, u64 n, hipStream_t 
   const int rp = publish_layout(s);
   const int rg = rebuild_groups<K>(s, st);
   return rc ? rc : (rp ? rp : rg);
+}
+
+// Restructuring (Section 3.5): the live pairs are read out in key order and laid
+// out again by the build rule, so every bucket is one node at the bulk-load
+// fill, chains are gone, underfull nodes are merged and maxBucket follows the
+// current key distribution.  The pool keeps its size; a pool smaller than the
+// new bucket count -> FLIX_ENOMEM with nothing changed.  Synchronizes.
+template <typename K>
+int restructure_t(flix_store* s, hipStream_t st, u64* before, u64* after) {
+  Ctl hctl;
+  HIP_TRY(hipMemcpyAsync(&hctl, s->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const u64 n = hctl.nkeys;
+  if (before) *before = (u64)s->pool - hctl.free_top;
+  const u64 nbk = n ? (n + s->fill - 1) / s->fill : 1;
+  if (nbk > 0xFFFFFF00ull) return FLIX_EINVAL;
+  if (nbk > s->pool) return FLIX_ENOMEM;
+  K *ck = nullptr, *cv = nullptr;
+  auto cleanup = [&]() { dev_free(&ck); dev_free(&cv); };
+  int rc = FLIX_OK;
+  if (n) {
+    if ((rc = dev_alloc(&ck, n * sizeof(K))) || (rc = dev_alloc(&cv, n * sizeof(K))) ||
+        (rc = dump_body(s, ck, cv, n, st))) {
+      cleanup();
+      return rc;
+    }
+  }
+  // the old layout is no longer read: the directory may be replaced
+  if ((rc = alloc_dir(s, (u32)nbk))) { cleanup(); return rc; }
+  rc = build_layout<K>(s, ck, cv, n, (u32)nbk, st);
+  const hipError_t e = hipStreamSynchronize(st);
+  cleanup();
+  const int rp = publish_layout(s);
+  const int rg = rebuild_groups<K>(s, st);
+  if (rc) return rc;
+  if (e != hipSuccess) return note_hip_error(e, "restructure", __LINE__);
+  if (rp || rg) return rp ? rp : rg;
+  if (after) *after = nbk;
+  return FLIX_OK;
 }
 
 int check_args(flix_store* s, u64 n, std::initializer_list<const void*> ptrs) {
@@ -1025,7 +1131,7 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   u32 fill = cfg->fill ? cfg->fill : cap / 2;
   if (fill > cap || fill == 0) return FLIX_EINVAL;
   if (cfg->max_batch == 0 || cfg->max_batch > 0x7FFFFFFFull) return FLIX_EINVAL;
-  if (cfg->reserved != 0) return FLIX_EINVAL;
+  if (cfg->insert_algo > FLIX_INSERT_ADAPTIVE) return FLIX_EINVAL;
   flix_store* s = new (std::nothrow) flix_store;
   if (!s) return FLIX_ENOMEM;
   s->cfg = *cfg;
@@ -1116,6 +1222,13 @@ int flix_bulk_load(flix_store* s, const void* d_keys, const void* d_vals, uint64
   if (n && (!d_keys || !d_vals)) return FLIX_EINVAL;
   return s->kb == 32 ? bulk_load_t<u32>(s, (const u32*)d_keys, (const u32*)d_vals, n, S(stream))
                      : bulk_load_t<u64>(s, (const u64*)d_keys, (const u64*)d_vals, n, S(stream));
+}
+
+int flix_restructure(flix_store* s, uint64_t* nodes_before, uint64_t* nodes_after, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  if (!s) return FLIX_ESTATE;
+  return s->kb == 32 ? restructure_t<u32>(s, S(stream), nodes_before, nodes_after)
+                     : restructure_t<u64>(s, S(stream), nodes_before, nodes_after);
 }
 
 int flix_insert(flix_store* s, const void* d_keys, const void* d_vals, uint64_t n,
@@ -1230,33 +1343,7 @@ int flix_dump(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capaci
   if (n > capacity) return FLIX_EINVAL;
   if (n == 0) return FLIX_OK;
   if (!d_keys_out || !d_vals_out) return FLIX_EINVAL;
-  u32 nb = s->nb;
-  u32 nblk = (nb + 255) / 256;
-  u32 *tot = nullptr, *off = nullptr, *bs = nullptr, *dummy = nullptr;
-  int rc;
-  if ((rc = dev_alloc(&tot, (u64)nb * 4)) || (rc = dev_alloc(&off, (u64)nb * 4)) ||
-      (rc = dev_alloc(&bs, (u64)nblk * 4)) || (rc = dev_alloc(&dummy, 16))) {
-    dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
-    return rc;
-  }
-  u32 g = std::min<u32>(nblk, 65535);
-  hipLaunchKernelGGL(k_bucket_totals, dim3(g), dim3(256), 0, st, s->hdr, nb, s->pool, tot);
-  hipLaunchKernelGGL(k_scan_blocks_u32, dim3(nblk), dim3(256), 0, st, tot, nb, off, bs);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bs, nblk, dummy);
-  hipLaunchKernelGGL(k_scan_addback, dim3(nblk), dim3(256), 0, st, off, nb, bs);
-  u32 gw = std::min<u32>((nb + 3) / 4, 65535);
-  if (s->kb == 32)
-    hipLaunchKernelGGL((k_dump_copy<u32>), dim3(gw), dim3(256), 0, st, s->hdr, (const u32*)s->nkeys,
-                       (const u32*)s->nvals, nb, s->cap, s->pool, off, (u32*)d_keys_out,
-                       (u32*)d_vals_out, (u64)capacity);
-  else
-    hipLaunchKernelGGL((k_dump_copy<u64>), dim3(gw), dim3(256), 0, st, s->hdr, (const u64*)s->nkeys,
-                       (const u64*)s->nvals, nb, s->cap, s->pool, off, (u64*)d_keys_out,
-                       (u64*)d_vals_out, (u64)capacity);
-  hipError_t e1 = hipGetLastError();
-  hipError_t e2 = hipStreamSynchronize(st);
-  dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
-  return (e1 == hipSuccess && e2 == hipSuccess) ? FLIX_OK : FLIX_EHIP;
+  return dump_body(s, d_keys_out, d_vals_out, capacity, st);
 }
 
 int flix_check(flix_store* s, void* stream) {

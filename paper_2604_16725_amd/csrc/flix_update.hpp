@@ -348,6 +348,29 @@ __device__ __forceinline__ void stage_items(K* dk, K* dv, const K* sk, const K* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Insert kernel choice.  The work list of an insert call can be split between
+// the single-lane kernel (k_insert_st) and the lane-group kernel
+// (k_insert_apply):
+//   kSelAll     every item
+//   kSelShort   items whose slice holds at most `st_max` batch keys
+//   kSelLong    the other items
+//   kSelRound   every item when the call averages at most `st_max` batch keys
+//               per touched bucket, else none
+//   kSelRoundL  the complement of kSelRound
+// ---------------------------------------------------------------------------
+constexpr u32 kSelAll = 0, kSelShort = 1, kSelLong = 2, kSelRound = 3, kSelRoundL = 4;
+
+__device__ __forceinline__ bool sel_takes(u32 sel, u32 st_max, u32 len, u32 m, u32 nitems) {
+  switch (sel) {
+    case kSelShort: return len <= st_max;
+    case kSelLong: return len > st_max;
+    case kSelRound: return (u64)m <= (u64)st_max * nitems;
+    case kSelRoundL: return (u64)m > (u64)st_max * nitems;
+    default: return true;
+  }
+}
+
 template <typename K>
 struct UpdArgs {
   const K* mkba;
@@ -367,6 +390,8 @@ struct UpdArgs {
   Ctl* ctl;
   u32* status;        // sticky status word (== &ctl->status)
   OccLevels occ;      // bucket occupancy summary, kept current here
+  u32 sel = 0;        // insert kernels: which work items this launch takes (kSel*)
+  u32 st_max = 0;     // slice-length threshold of the kernel choice
 };
 
 // Workgroup-shared state of the apply kernels: a key counter and the map of
@@ -450,6 +475,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       cur.move(sh.pre, it + stride);
       wnext = a.work[cur.slot(it + stride, a.rcap)];
     }
+    if (!sel_takes(a.sel, a.st_max, w.e - w.s, a.m, nitems)) continue;
     u32 X = w.b;
     NodeHdr hX;
     bool fence_known = true;
@@ -731,6 +757,137 @@ __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 6 : 1))) void k_insert_apply
   extern __shared__ unsigned char s_dyn[];
   __shared__ UpdShared sh;
   insert_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, sh);
+}
+
+// ---------------------------------------------------------------------------
+// ST-Shift-Right insert (Section 4.2.1): one lane owns one bucket.  For every
+// live batch key of its slice (last of each equal-key run), in ascending
+// order, the lane walks the chain to the node whose fence covers the key,
+// binary-searches the node: an equal key takes the new value; otherwise the
+// keys from the insertion point on shift right by one slot and the pair is
+// written.  A full node first splits into two halves (left half floor(c/2),
+// Section 5.3.1): the right half goes to a node popped from the free list and
+// linked after it, the left node is fenced by its last key, the right one
+// inherits the old fence and link.  The lane's own writes are re-read only by
+// the same lane, so program order keeps them visible.
+// ---------------------------------------------------------------------------
+template <typename K>
+__device__ void st_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, u64& added) {
+  u32 X = w.b;
+  NodeHdr hX;
+  if (w.head & kSingleNode) {
+    hX.size = w.head & ~kSingleNode;
+    hX.next = kNil;
+    hX.fence = (u64)a.mkba[w.b];
+  } else {
+    hX = a.hdr[X];
+  }
+  const bool was_empty = (w.head & kSingleNode) && (w.head & ~kSingleNode) == 0;
+  const u64 added_before = added;
+  u32 nodes_added = 0;
+  for (u32 j = w.s; j < w.e; ++j) {
+    const K k = a.skeys[j];
+    if (j + 1 < a.m && a.skeys[j + 1] == k) continue;   // a later pair of the key wins
+    const K v = a.svals[j];
+    // the slice is ascending, so the walk only moves forward
+    bool broken = false;
+    while ((u64)k > hX.fence) {
+      if (hX.next >= a.pool) { broken = true; break; }
+      X = hX.next;
+      hX = a.hdr[X];
+    }
+    if (broken || hX.size > a.cap) {
+      atomicCAS(a.status, 0u, kErrInternal);
+      break;
+    }
+    K* xk = a.nkeys + (u64)X * a.cap;
+    K* xv = a.nvals + (u64)X * a.cap;
+    u32 p = lower_bound_idx<K>(xk, 0u, hX.size, k);
+    if (p < hX.size && xk[p] == k) {   // upsert in place
+      xv[p] = v;
+      continue;
+    }
+    if (hX.size == a.cap) {
+      // split into halves; the new node takes the right one
+      const u32 top = atomicSub(&a.ctl->free_top, 1u);
+      if (top == 0 || top > a.pool) {   // budget bound violated: never expected
+        atomicCAS(a.status, 0u, kErrInternal);
+        break;
+      }
+      const u32 Y = a.free_ids[top - 1];
+      if (Y >= a.pool) {
+        atomicCAS(a.status, 0u, kErrInternal);
+        break;
+      }
+      const u32 h = a.cap / 2;
+      K* yk = a.nkeys + (u64)Y * a.cap;
+      K* yv = a.nvals + (u64)Y * a.cap;
+      for (u32 i = h; i < a.cap; ++i) {
+        yk[i - h] = xk[i];
+        yv[i - h] = xv[i];
+      }
+      NodeHdr hY;
+      hY.fence = hX.fence;
+      hY.size = a.cap - h;
+      hY.next = hX.next;
+      a.hdr[Y] = hY;
+      hX.fence = (u64)xk[h - 1];
+      hX.size = h;
+      hX.next = Y;
+      a.hdr[X] = hX;
+      ++nodes_added;
+      if ((u64)k > hX.fence) {   // the key belongs to the right half
+        X = Y;
+        hX = hY;
+        xk = yk;
+        xv = yv;
+        p -= h;
+      }
+    }
+    for (u32 i = hX.size; i > p; --i) {
+      xk[i] = xk[i - 1];
+      xv[i] = xv[i - 1];
+    }
+    xk[p] = k;
+    xv[p] = v;
+    ++hX.size;
+    a.hdr[X].size = hX.size;
+    ++added;
+  }
+  if (nodes_added) a.bnodes[w.b] += nodes_added;
+  if (was_empty && added > added_before) occ_set(a.occ, w.b);
+}
+
+// One lane per work item taken by `sel`; the node budget was checked by the
+// slice kernel's bound exactly as for the lane-group kernel (a split-produced
+// node holds at least cap/2 keys, so the same per-bucket bound holds).
+template <typename K, int NT>
+__global__ __launch_bounds__(NT) void k_insert_st(UpdArgs<K> a) {
+  __shared__ UpdShared sh;
+  if (threadIdx.x == 0) sh.counter = 0;
+  __syncthreads();
+  const Ctl* ctl = a.ctl;
+  if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot) {
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      atomicCAS(a.status, 0u, ctl->call_err != 0 ? ctl->call_err : kErrNomem);
+    return;
+  }
+  const u32 nitems = load_work_map(ctl, sh.pre);
+  u64 added = 0;
+  const u32 stride = gridDim.x * NT;
+  u32 it = blockIdx.x * NT + threadIdx.x;
+  WorkCursor cur;
+  cur.seek(sh.pre, it);
+  for (; it < nitems; it += stride) {
+    cur.move(sh.pre, it);
+    const WorkItem w = a.work[cur.slot(it, a.rcap)];
+    if (!sel_takes(a.sel, a.st_max, w.e - w.s, a.m, nitems)) continue;
+    st_insert_bucket<K>(a, w, added);
+  }
+  for (int off = 32; off > 0; off >>= 1) added += __shfl_xor(added, off, 64);
+  if ((threadIdx.x & 63u) == 0 && added) atomicAdd(&sh.counter, added);
+  __syncthreads();
+  if (threadIdx.x == 0 && sh.counter) atomicAdd((unsigned long long*)&a.ctl->nkeys, sh.counter);
 }
 
 // ---------------------------------------------------------------------------

@@ -35,8 +35,11 @@ class FlixConfig(ctypes.Structure):
         ("max_batch", ctypes.c_uint64),
         ("pool_bytes", ctypes.c_uint64),
         ("fill", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("insert_algo", ctypes.c_uint32),
     ]
+
+
+INSERT_ALGOS = {"tl_bulk": 0, "st_shift_right": 1, "st_tl_mixed": 2, "adaptive": 3}
 
 
 class FlixStats(ctypes.Structure):
@@ -120,6 +123,7 @@ def load_library(path: str = LIB_PATH):
         "flix_predecessor": (i32, [vp, vp, u64, vp, vp, vp]),
         "flix_range": (i32, [vp, vp, vp, u64, u32, vp, vp, vp, vp]),
         "flix_destroy": (i32, [vp]),
+        "flix_restructure": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), vp]),
         "flix_size": (i32, [vp, ctypes.POINTER(u64), vp]),
         "flix_dump": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
         "flix_check": (i32, [vp, vp]),
@@ -168,7 +172,7 @@ class Store:
 
     def __init__(self, key_bits: int = 32, capacity: int = 128, lanes: int = 16,
                  radix_bits: int = 8, max_batch: int = 1 << 20, pool_bytes: int = 0,
-                 fill: int = 0, stream=None):
+                 fill: int = 0, insert_algo="tl_bulk", stream=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -176,8 +180,9 @@ class Store:
         self.dtype = torch.int32 if key_bits == 32 else torch.int64
         self._ok_dtypes = ((torch.int32, torch.uint32) if key_bits == 32
                            else (torch.int64, torch.uint64))
+        algo = INSERT_ALGOS[insert_algo] if isinstance(insert_algo, str) else int(insert_algo)
         self.cfg = FlixConfig(key_bits, capacity, lanes, radix_bits, max_batch, pool_bytes,
-                              fill, 0)
+                              fill, algo)
         h = ctypes.c_void_p()
         rc = self.lib.flix_create(ctypes.byref(self.cfg), _stream(stream), ctypes.byref(h))
         if rc != FLIX_OK:
@@ -263,6 +268,14 @@ class Store:
                                       _ptr(out_v if want_vals else None), _stream(stream)),
                   "flix_range")
         return counts, out_k, out_v
+
+    def restructure(self, stream=None):
+        """Lay the store out again by the build rule; returns the nodes in use
+        before and after."""
+        b, a = ctypes.c_uint64(), ctypes.c_uint64()
+        self._chk(self.lib.flix_restructure(self.h, ctypes.byref(b), ctypes.byref(a),
+                                            _stream(stream)), "flix_restructure")
+        return int(b.value), int(a.value)
 
     def size(self, stream=None) -> int:
         v = ctypes.c_uint64()
