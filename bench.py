@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--capacity", type=int, default=128)
     ap.add_argument("--lanes", type=int, default=16)
     ap.add_argument("--radix-bits", type=int, default=8)
+    ap.add_argument("--read-path", choices=["sorted", "groups"], default="sorted",
+                    help="read-batch pipeline of the store (device-wide sort, or bucket groups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-breakdown", action="store_true")
     ap.add_argument("--no-batching", action="store_true",
@@ -55,6 +57,12 @@ def parse():
                     help="skip the serving comparison (request loop vs plain per-request form)")
     ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
     ap.add_argument("--serve-keys-log2", type=int, default=25)
+    ap.add_argument("--no-grown", action="store_true",
+                    help="skip the reads on a store grown by +100% and restructured")
+    ap.add_argument("--update-rounds", type=int, default=20,
+                    help="rounds of the update-heavy workload (0 skips it)")
+    ap.add_argument("--no-insert-kernels", action="store_true",
+                    help="skip the insert-kernel comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MiB",
                     help="first copy a MiB-sized device buffer 4 times (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
@@ -70,7 +78,7 @@ def ensure_built():
 # ----------------------------------------------------------------------------
 # Algorithmic byte model (what the method must move)
 # ----------------------------------------------------------------------------
-def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
+def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8, read_path="sorted"):
     """Bytes per step for every kernel family, from the actual batches."""
     m = wl["lookup"].size
     nb = mkba.size
@@ -83,12 +91,13 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
 
     build_sorted = wl["_build_sorted"]
     size_of = sizes_cap  # keys per bucket after bulk load (array over buckets)
+    groups = read_path == "groups"
 
     fam = {}
-    # update batches sort on the onesweep path (2 sorts per step: insert with
-    # values, delete keys only); read batches take the bucket-group path
-    fam["sort_hist"] = 2 * m * kbytes
-    pay = [vbytes, 0]
+    # sorts per step: insert (key + value) and delete (key only), plus the
+    # three read batches (key + input position) on the sorted read path
+    pay = [vbytes, 0] if groups else [4, 4, 4, vbytes, 0]
+    fam["sort_hist"] = len(pay) * m * kbytes
     # batches of up to 2^22 keys with 8-bit digits: one device-wide pass on
     # the top digit, then one read and one write of every pair by the
     # per-run sort; otherwise P device-wide passes
@@ -97,30 +106,43 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8):
     if local:
         fam["sort_local"] = sum(m * 2 * (kbytes + p) for p in pay)
 
-    # bucket groups: at most 1024 groups of equal bucket counts
-    bpg = -(-nb // 1024)
-    ngroups = -(-nb // bpg)
-    ntiles = -(-m // 4096)
-    # k_part: read the keys, write keys + input positions grouped per tile,
-    # the tile group-start rows and the group totals
-    fam["part"] = 3 * (m * kbytes + m * (kbytes + 4) + ntiles * (ngroups + 1) * 4 + ngroups * 4)
-
-    def read_bytes(keys, extra_out, val_reads, hi_bytes=0):
-        # every maxBucket entry, the grouped batch (key + position), the head
-        # word (size, link) of each touched bucket, the live prefix of each
-        # touched node in whole 128-byte lines, values read, outputs
+    def read_bytes(keys, extra_out, val_reads, hi_bytes=0, head_bytes=16):
+        # every maxBucket entry, the sorted (or grouped) batch (key +
+        # position), the header of each touched bucket, the live prefix of
+        # each touched node in whole 128-byte lines, values read, outputs
         t = touched(keys)
-        return (nb * kbytes + m * (kbytes + 4) + hi_bytes + t.size * 8
+        return (nb * kbytes + m * (kbytes + 4) + hi_bytes + t.size * head_bytes
                 + float(live_line(size_of[t]).sum()) + val_reads * vbytes + extra_out)
 
     hits = np.isin(wl["lookup"], build_sorted).sum()
-    look = read_bytes(wl["lookup"], m * vbytes, hits)
-    succ = read_bytes(wl["successor"], m * (kbytes + vbytes), m)
     lo, hi = wl["range_lo"], wl["range_hi"]
     cnt = (np.searchsorted(build_sorted, hi, side="right")
            - np.searchsorted(build_sorted, lo, side="left")).sum()
-    rng = read_bytes(lo, m * 4 + cnt * (kbytes + vbytes), cnt, hi_bytes=m * kbytes)
-    fam["group_read"] = look + succ + rng
+    if groups:
+        # bucket groups: at most 1024 groups of equal bucket counts; k_part
+        # reads the keys, writes keys + input positions grouped per tile, the
+        # tile group-start rows and the group totals
+        bpg = -(-nb // 1024)
+        ngroups = -(-nb // bpg)
+        ntiles = -(-m // 4096)
+        fam["part"] = 3 * (m * kbytes + m * (kbytes + 4) + ntiles * (ngroups + 1) * 4
+                           + ngroups * 4)
+        look = read_bytes(wl["lookup"], m * vbytes, hits, head_bytes=8)
+        succ = read_bytes(wl["successor"], m * (kbytes + vbytes), m, head_bytes=8)
+        rng = read_bytes(lo, m * 4 + cnt * (kbytes + vbytes), cnt, hi_bytes=m * kbytes,
+                         head_bytes=8)
+        fam["group_read"] = look + succ + rng
+    else:
+        look = read_bytes(wl["lookup"], m * vbytes, hits)
+        succ = read_bytes(wl["successor"], m * (kbytes + vbytes), m)
+        rng = read_bytes(lo, m * (4 + kbytes) + cnt * (kbytes + vbytes), cnt)
+        fam["read_apply"] = look + succ + rng
+        # cut list of each read call: one u32 per share boundary, found by a
+        # 33-ary search (32 probes per round, half a wave per cut) whose
+        # probes read one batch key and one maxBucket entry each
+        ncuts = -(-(m + nb) // 512) + 1
+        rounds = int(np.ceil(np.log(max(m + nb, 2)) / np.log(33)))
+        fam["read_cuts"] = 3 * ncuts * (4 + rounds * 32 * (kbytes + kbytes))
 
     ins = wl["insert_keys"]
     bi = np.searchsorted(mkba, ins, side="left")
@@ -169,6 +191,249 @@ def counter_traffic(kernel):
     if h.hexdigest() != rec["sources_sha256"]:
         return None
     return fam["traffic_bytes_per_launch"]
+
+
+def timed_calls(fn, reps):
+    """Median and p99 of `reps` calls of fn, each bracketed by events on the
+    current stream (one untimed call first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    gc.disable()
+    try:
+        for a, b in evs:
+            a.record()
+            fn()
+            b.record()
+    finally:
+        gc.enable()
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in evs])
+    return float(np.median(ms)), float(np.percentile(ms, 99))
+
+
+def grown_store_reads(args, wl, dev, bufs):
+    """Reads after growth and restructuring after deletes (the paper's queries
+    after update rounds, and its restructuring experiment): the 2^keys_log2
+    store grows by +100% through 2^batch_log2-key insert batches of new uniform
+    keys (about half the buckets become chains); the step's read batches are
+    timed there.  Then half of all keys, drawn uniformly, are deleted, which
+    leaves underfull nodes; restructuring lays the store out again at the
+    bulk-load fill (nodes before and after), and the reads are timed again."""
+    import torch
+    from paper_2604_16725_amd import flix
+    n_keys, m = 1 << args.keys_log2, 1 << args.batch_log2
+    ks = wl["keyspace"]
+    node_bytes = 16 + 2 * args.capacity * 4
+    st = flix.Store(key_bits=32, capacity=args.capacity, lanes=args.lanes,
+                    radix_bits=args.radix_bits, max_batch=m,
+                    pool_bytes=node_bytes * (4 * n_keys // args.capacity + 4096))
+    st.bulk_load(dev(wl["build_keys"]), dev(wl["build_vals"]))
+    t0 = time.time()
+    nbatches = n_keys // m
+    grown_keys = []
+    for i in range(nbatches):
+        k = ks.fresh(m)
+        v = k ^ np.uint32(0x2545F491)
+        v[v == np.uint32(0xFFFFFFFF)] = 0
+        st.insert(dev(k), dev(v))
+        grown_keys.append(k)
+    torch.cuda.synchronize()
+    if st.status() != 0:
+        raise RuntimeError("device error while growing the store")
+    log(f"[bench] grown store: +{nbatches * m} keys in {time.time() - t0:.1f}s")
+    dl, ds, dlo, dhi = bufs["lookup"], bufs["successor"], bufs["range_lo"], bufs["range_hi"]
+    ol, sk, sv, rc, rk, rv, L = (bufs[x] for x in ("ol", "sk", "sv", "rc", "rk", "rv", "L"))
+    reps = max(5, args.steps)
+    calls = {"lookup": lambda: st.lookup(dl, out=ol),
+             "successor": lambda: st.successor(ds, out_k=sk, out_v=sv),
+             "range16": lambda: st.range(dlo, dhi, L, counts=rc, out_k=rk, out_v=rv)}
+
+    def measure(tag):
+        stt = st.stats()
+        nb, keys, live = stt["buckets"], stt["keys"], stt["live_nodes"]
+        # algorithmic bytes of the bucket kernel per read batch: every
+        # maxBucket entry, the sorted batch, the header of every node of a
+        # touched bucket and its live keys in whole lines, values, outputs
+        touched = nb * (1.0 - np.exp(-m / nb))
+        per_bucket = keys / nb
+        chain = live / nb
+        lines = np.ceil(per_bucket * 4 / 128.0) * 128.0 + (chain - 1) * 64.0
+        base = nb * 4 + m * 8 + touched * (16 * chain + lines)
+        outb = {"lookup": m * 4 + 0.9 * m * 4, "successor": m * 8 + m * 4,
+                "range16": m * 4 + m * 4 + m * 8}
+        rows = {}
+        for name, fn in calls.items():
+            st.set_timing(True, only="read_apply")
+            p50, p99 = timed_calls(fn, reps)
+            kms, kn = st.kernel_time("read_apply")
+            st.set_timing(False)
+            kus = 1000.0 * kms / kn if kn else None
+            ab = base + outb[name]
+            rows[name] = {"Mops_s": round(m / (p50 / 1000) / 1e6, 1), "p50_ms": round(p50, 4),
+                          "p99_ms": round(p99, 4),
+                          "bucket_kernel_us": round(kus, 2) if kus else None,
+                          "bucket_kernel_alg_MB": round(ab / 1e6, 1),
+                          "bucket_kernel_frac": (round(ab / (kus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                                 if kus else None)}
+        log(f"[bench] {tag}: buckets {nb}, keys {keys}, nodes {live}: {rows}")
+        return {"buckets": nb, "keys": keys, "live_nodes": live, "reads": rows}
+
+    grown = measure("grown")
+    # delete half of all keys, uniformly
+    t0 = time.time()
+    present = np.concatenate([wl["build_keys"]] + grown_keys)
+    del grown_keys
+    rng = np.random.default_rng(0xF11C0D)
+    gone = present[rng.permutation(present.size)[: present.size // 2]]
+    del present
+    for i in range(0, gone.size, m):
+        st.delete(dev(gone[i:i + m]))
+    torch.cuda.synchronize()
+    if st.status() != 0:
+        raise RuntimeError("device error while deleting")
+    log(f"[bench] deleted {gone.size} keys in {time.time() - t0:.1f}s")
+    del gone
+    after_deletes = st.stats()
+    t0 = time.perf_counter()
+    before, after = st.restructure()
+    rs_ms = (time.perf_counter() - t0) * 1000.0
+    restructured = measure("restructured")
+    if st.status() != 0 or st.check() != 0:
+        raise RuntimeError("device error or invariant violation in the grown-store runs")
+    st.close()
+    return {"workload": f"2^{args.keys_log2} u32 keys grown by +100% ({nbatches} insert batches of "
+                        f"2^{args.batch_log2} new uniform keys), reads; then half of all keys "
+                        f"deleted, restructured, reads",
+            "grown": grown,
+            "after_deletes": {"keys": after_deletes["keys"],
+                              "live_nodes": after_deletes["live_nodes"],
+                              "buckets": after_deletes["buckets"]},
+            "restructure": {"ms": round(rs_ms, 2), "nodes_before": before, "nodes_after": after,
+                            "recovered_frac": round((before - after) / before, 4)},
+            "restructured": restructured}
+
+
+def update_heavy_rounds(args):
+    """The update-heavy workload: u64 keys and values, bulk load 2^24 keys,
+    rounds of 2^20 inserts of new keys then 2^20 deletes of present keys,
+    uniform (even rounds) and clustered into 64 runs (odd rounds); every call
+    timed with events.  Algorithmic bytes per op follow the byte model of the
+    update kernels (sort of key+value, slices, node reads and writes)."""
+    import torch
+    from paper_2604_16725_amd import flix
+    from paper_2604_16725_amd import workloads as w
+    t0 = time.time()
+    u = w.UpdateHeavy(n_keys=1 << 24, batch=1 << 20, runs=64)
+    st = flix.Store(key_bits=64, capacity=128, lanes=16, radix_bits=8, max_batch=1 << 20)
+    st.bulk_load(torch.from_numpy(u.build_keys.view(np.int64)).cuda(),
+                 torch.from_numpy(u.build_vals.view(np.int64)).cuda())
+    rows = {"uniform": {"insert": [], "delete": []}, "clustered": {"insert": [], "delete": []}}
+    kern = {"uniform": {"insert_apply": [], "delete_apply": []},
+            "clustered": {"insert_apply": [], "delete_apply": []}}
+    m = 1 << 20
+    for r in range(args.update_rounds):
+        ins, iv, dele = u.round(r)
+        di = torch.from_numpy(ins.view(np.int64)).cuda()
+        dv = torch.from_numpy(iv.view(np.int64)).cuda()
+        dd = torch.from_numpy(dele.view(np.int64)).cuda()
+        kind = "uniform" if r % 2 == 0 else "clustered"
+        for name, fn, fam in (("insert", lambda: st.insert(di, dv), "insert_apply"),
+                              ("delete", lambda: st.delete(dd), "delete_apply")):
+            st.set_timing(True, only=fam)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            kms, kn = st.kernel_time(fam)
+            st.set_timing(False)
+            rows[kind][name].append(a.elapsed_time(b))
+            kern[kind][fam].append(kms / max(kn, 1))
+        if st.status() != 0:
+            raise RuntimeError(f"device error in update round {r}")
+    stt = st.stats()
+    st.close()
+    # algorithmic bytes per op (u64 keys and values, capacity 128, bulk fill 64)
+    sort_b = 8 + (8 + 16) + 7 * 2 * 16      # histogram read, top-digit pass, local passes
+    ins_b = sort_b + 8 + 12 + 3 + 0.98 * (64 + 68) * 16 / 4
+    del_b = sort_b - 7 * 2 * 8 + 8 + 3 + 0.98 * (64 + 68) * 16 / 4
+    out = {"workload": f"u64 store, bulk load 2^24 keys, {args.update_rounds} rounds of 2^20 "
+                       f"inserts then 2^20 deletes, even rounds uniform, odd rounds clustered "
+                       f"into 64 runs",
+           "final": stt}
+    for kind in rows:
+        d = {}
+        for name in ("insert", "delete"):
+            ms = np.array(rows[kind][name])
+            if ms.size == 0:
+                continue
+            d[name] = {"Mops_s_median": round(m / (np.median(ms) / 1000) / 1e6, 1),
+                       "ms_median": round(float(np.median(ms)), 4),
+                       "ms_max": round(float(ms.max()), 4), "rounds": int(ms.size)}
+            fam = "insert_apply" if name == "insert" else "delete_apply"
+            kms = np.array(kern[kind][fam])
+            d[name]["apply_kernel_ms_median"] = round(float(np.median(kms)), 4)
+        if d:
+            d["alg_bytes_per_op_model"] = {"insert": ins_b, "delete": del_b} if kind == "uniform" \
+                else "sort-dominated (about 230 B/op)"
+            if kind == "uniform" and "insert" in d:
+                d["insert"]["frac_whole_call"] = round(
+                    ins_b * m / (d["insert"]["ms_median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                d["delete"]["frac_whole_call"] = round(
+                    del_b * m / (d["delete"]["ms_median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            out[kind] = d
+    log(f"[bench] update heavy ({time.time() - t0:.0f}s): {out}")
+    return out
+
+
+def insert_kernel_choice(args):
+    """Insert throughput of each insert kernel (TL-Bulk, ST-Shift-Right,
+    ST-TL-Mixed, adaptive) at light and heavy loads per bucket: one 2^20-key
+    batch of new uniform u32 keys into stores of 2^22 keys at capacity 8
+    (about one key per touched bucket) and 2^24 keys at capacity 128 (about
+    four keys per bucket).  Each batch is deleted again between samples."""
+    import torch
+    from paper_2604_16725_amd import flix
+    from paper_2604_16725_amd import workloads as w
+    m = 1 << 20
+    res = {}
+    for keys_log2, cap in ((22, 8), (24, 128)):
+        ks = w.KeySpace(32, 0xF11C7000 + cap)
+        bk = ks.build(1 << keys_log2)
+        ins = ks.fresh(m)
+        dbk = torch.from_numpy(bk.view(np.int32)).cuda()
+        di = torch.from_numpy(ins.view(np.int32)).cuda()
+        row = {}
+        for algo in ("tl_bulk", "st_shift_right", "st_tl_mixed", "adaptive"):
+            st = flix.Store(key_bits=32, capacity=cap, lanes=16 if cap >= 16 else 16,
+                            max_batch=m, insert_algo=algo)
+            st.bulk_load(dbk, dbk)
+
+            def one():
+                st.insert(di, di)
+                st.delete(di)
+            times = []
+            for _ in range(max(5, args.steps // 2)):
+                st.delete(di)
+                torch.cuda.synchronize()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                st.insert(di, di)
+                b.record()
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b))
+            if st.status() != 0:
+                raise RuntimeError(f"device error in the {algo} insert runs")
+            ms = float(np.median(times[1:]))
+            row[algo] = {"Mops_s": round(m / (ms / 1000) / 1e6, 1), "ms": round(ms, 4)}
+            st.close()
+        res[f"2^{keys_log2} keys, capacity {cap}"] = row
+        log(f"[bench] insert kernels at 2^{keys_log2} keys, capacity {cap}: {row}")
+    return res
 
 
 def batching_compare(args):
@@ -347,7 +612,7 @@ def main():
         return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
 
     st = flix.Store(key_bits=32, capacity=args.capacity, lanes=args.lanes,
-                    radix_bits=args.radix_bits, max_batch=m)
+                    radix_bits=args.radix_bits, max_batch=m, read_path=args.read_path)
     bk, bv = dev(wl["build_keys"]), dev(wl["build_vals"])
     t0 = time.time()
     st.bulk_load(bk, bv)
@@ -380,7 +645,7 @@ def main():
     log("[bench] warmup done")
 
     fams = ["sort_hist", "sort_pass", "sort_local", "read_cuts", "read_apply", "part",
-            "group_read", "slices", "insert_apply", "delete_apply"]
+            "group_read", "slices", "insert_apply", "delete_apply", "insert_st"]
 
     def run_steps(k):
         torch.cuda.synchronize()
@@ -426,7 +691,7 @@ def main():
     assert mkba.size == nb, (mkba.size, nb)
     sizes = np.full(nb, f, dtype=np.int64)
     sizes[-1] = n_keys - f * (nb - 1)
-    model = byte_model(wl, mkba, sizes, rb=args.radix_bits)
+    model = byte_model(wl, mkba, sizes, rb=args.radix_bits, read_path=args.read_path)
     per_fam = {}
     for fam, (ms, n) in fam_all.items():
         if n == 0:
@@ -490,8 +755,28 @@ def main():
             raise RuntimeError("device error during breakdown")
 
     st.close()
-    batching = None if args.no_batching else batching_compare(args)
-    serving = None if args.no_serving else serving_compare(args)
+    del st
+    def leg(name, fn, *a):
+        # a secondary measurement that fails is reported in the JSON line
+        # instead of taking the headline number with it
+        try:
+            return fn(*a)
+        except Exception as e:  # noqa: BLE001
+            import traceback
+            traceback.print_exc()
+            log(f"[bench] {name} failed: {e!r}")
+            return {"error": repr(e)}
+
+    grown = None
+    if not args.no_grown:
+        bufs = {"lookup": dl, "successor": ds, "range_lo": dlo, "range_hi": dhi, "ol": ol,
+                "sk": sk, "sv": sv, "rc": rc, "rk": rk, "rv": rv, "L": L}
+        grown = leg("grown_store", grown_store_reads, args, wl, dev, bufs)
+    update_heavy = leg("update_heavy", update_heavy_rounds, args) if args.update_rounds > 0 else None
+    insert_kernels = None if args.no_insert_kernels else leg("insert_kernels", insert_kernel_choice,
+                                                               args)
+    batching = None if args.no_batching else leg("batching", batching_compare, args)
+    serving = None if args.no_serving else leg("serving", serving_compare, args)
 
     # -- CPU baseline: the oracle on a bounded sample -----------------------
     cpu = None
@@ -546,7 +831,8 @@ def main():
         "config": {"workload": "flix read-path store, 2^26 uniform u32 keys, capacity 128, "
                                "step = lookup+successor+range16+insert+delete of 2^20 ops each",
                    "keys": n_keys, "batch": m, "capacity": args.capacity, "lanes": args.lanes,
-                   "radix_bits": args.radix_bits, "ops_per_step": ops_step,
+                   "radix_bits": args.radix_bits, "read_path": args.read_path,
+                   "ops_per_step": ops_step,
                    "global_batch": m, "parallelism": "single-gpu"},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -554,6 +840,9 @@ def main():
         "ms_per_step_events_on_every_family": round(ms_step_all, 4),
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_fam.items()},
         "breakdown": breakdown,
+        "grown_store": grown,
+        "update_heavy": update_heavy,
+        "insert_kernels": insert_kernels,
         "batching": batching,
         "serving": serving,
     }

@@ -72,7 +72,17 @@ typedef struct {
   uint32_t fill;            /* keys per node at bulk load (Section 3.2: p = NS/2);
                                0 = bucket_capacity/2; at most bucket_capacity */
   uint32_t insert_algo;     /* insert kernel, one of FLIX_INSERT_* (0 = TL-Bulk) */
+  uint32_t read_path;       /* read batches: FLIX_READ_SORTED (0) or FLIX_READ_GROUPS */
+  uint32_t reserved;        /* must be 0 */
 } flix_config;
+
+/* Read-batch pipelines (both Section 3.3 / 4.1: sort, per-bucket slice search,
+ * per-bucket resolve; same results).  SORTED sorts the whole batch on the
+ * device (onesweep + per-run sort), then merge-path shares resolve it.  GROUPS
+ * splits the batch by groups of consecutive buckets in one pass and sorts each
+ * group's items in LDS inside the resolving workgroup (no device-wide sort). */
+#define FLIX_READ_SORTED 0
+#define FLIX_READ_GROUPS 1
 
 /* Insert kernels (Section 4.2.1 ST-Shift-Right, Section 4.3.2 TL-Bulk,
  * Section 5.3.5 ST-TL-Mixed, Section 3.4 adaptive compute per bucket).  All
@@ -83,7 +93,8 @@ typedef struct {
                                         most FLIX_ST_MAX_KEYS batch keys per touched
                                         bucket, TL-Bulk otherwise */
 #define FLIX_INSERT_ADAPTIVE 3       /* per bucket: one lane for a slice of at most
-                                        FLIX_ST_MAX_KEYS batch keys, a lane group otherwise */
+                                        FLIX_ST_MAX_KEYS batch keys when nodes hold at most
+                                        16 keys, a lane group otherwise */
 #define FLIX_ST_MAX_KEYS 4
 
 /* Create an empty store (Section 3.2 layout: a maxBucket directory over

@@ -24,13 +24,13 @@ using namespace flix;
 
 namespace {
 
-constexpr int kFamilies = 11;
+constexpr int kFamilies = 12;
 const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
                                        "insert_apply", "delete_apply", "read_cuts", "sort_local",
-                                       "part", "group_read", "insert_st"};
+                                       "part", "group_read", "insert_st", "insert_wide"};
 enum Family {
   F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6,
-  F_LOCAL = 7, F_PART = 8, F_GROUP = 9, F_INSERT_ST = 10
+  F_LOCAL = 7, F_PART = 8, F_GROUP = 9, F_INSERT_ST = 10, F_INSERT_WIDE = 11
 };
 int sort_family(int fam) { return fam == 0 ? F_HIST : fam == 1 ? F_PASS : F_LOCAL; }
 
@@ -355,7 +355,7 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   a.maxpq = maxpq;
   a.pool = s->pool;
   a.err = &s->ctl->status;
-  a.occ = s->occl;
+  a.occ = s->occl.w0;
   u64 grid = ((u64)n + s->nb + a.share - 1) / a.share;
   // cut list: half a wave per share boundary (the list holds cuts_for(max_batch,
   // nb_alloc) >= grid + 1 entries)
@@ -438,7 +438,7 @@ int read_batch_groups(flix_store* s, int op, const K* keys, u64 n, void* out_k, 
   a.maxpq = maxpq;
   a.pool = s->pool;
   a.err = &s->ctl->status;
-  a.occ = s->occl;
+  a.occ = s->occl.w0;
   a.cuts = nullptr;
   const u32 grid = group_chunk_bound((u32)n, s->ngrp, 2048);
   const TmTok t = tm_arm(s, F_GROUP);
@@ -451,7 +451,7 @@ int read_batch_groups(flix_store* s, int op, const K* keys, u64 n, void* out_k, 
 template <typename K>
 int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void* out_v,
                const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
-  if (s->grp_ok && n <= (u64)kGroupTilesMax * kPartTile)
+  if (s->cfg.read_path == FLIX_READ_GROUPS && s->grp_ok && n <= (u64)kGroupTilesMax * kPartTile)
     return read_batch_groups<K>(s, op, (const K*)keys, n, out_k, out_v, hi, counts, maxpq, st);
   int r;
   int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r);
@@ -473,6 +473,16 @@ struct SliceCfg<u64> {
 };
 
 constexpr int kUpdNT = 256;
+
+// Slice length up to which the adaptive insert gives a bucket one lane: the
+// single-lane kernel moves up to a node of keys per insert, so it only pays
+// for nodes of at most 16 keys.
+u32 adaptive_st_max(u32 cap) { return cap <= 16 ? (u32)FLIX_ST_MAX_KEYS : 0u; }
+
+// Slice length from which a single-node bucket is merged by a whole workgroup
+// (k_insert_wide): the lane-group kernel would walk such a slice in more than
+// eight node-sized chunks, one after another.
+u32 wide_min_keys(u32 cap) { return std::max<u32>(4 * cap, 256u); }
 
 // Batch items staged per merge step: half a node (at least 64).  With
 // capacity 128 a group's LDS is then 1.5 KB, so six workgroups fit a CU.
@@ -596,13 +606,29 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   u64 items = std::min<u64>(n, s->nb);
   // insert kernel choice: the single-lane kernel takes the items its selector
   // names, the lane-group kernel the complement
-  const u32 algo = (insert && !m_dev) ? s->cfg.insert_algo : (u32)FLIX_INSERT_TL_BULK;
+  u32 algo = (insert && !m_dev) ? s->cfg.insert_algo : (u32)FLIX_INSERT_TL_BULK;
+  // a long slice into a single-node bucket (a dense run of new keys) is merged
+  // by a whole workgroup; the lane-group kernel skips those items
+  if (insert && !m_dev && (algo == FLIX_INSERT_TL_BULK || algo == FLIX_INSERT_ADAPTIVE)) {
+    const u32 wmin = wide_min_keys(s->cap);
+    if (n >= wmin) {
+      ua.wide_min = wmin;
+      const u32 grid = (u32)std::min<u64>(2048, std::max<u64>(1, (items + 255) / 256));
+      const TmTok tw = tm_arm(s, F_INSERT_WIDE);
+      launch_timed(tw.b, tw.e, k_insert_wide<K, 256>, dim3(grid), dim3(256), 0, st, ua);
+      tm_done(s, F_INSERT_WIDE, tw);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  if (algo == FLIX_INSERT_ADAPTIVE && adaptive_st_max(s->cap) == 0) algo = FLIX_INSERT_TL_BULK;
   if (algo != FLIX_INSERT_TL_BULK) {
     UpdArgs<K> us = ua;
     us.sel = algo == FLIX_INSERT_ST_SHIFT_RIGHT ? kSelAll
            : algo == FLIX_INSERT_ST_TL_MIXED    ? kSelRound
                                                 : kSelShort;
-    us.st_max = FLIX_ST_MAX_KEYS;
+    // adaptive: one lane per bucket only where a node is a few cache lines
+    // (a lane shifts the node serially); larger nodes keep the lane group
+    us.st_max = algo == FLIX_INSERT_ADAPTIVE ? adaptive_st_max(s->cap) : (u32)FLIX_ST_MAX_KEYS;
     const u32 grid = (u32)std::max<u64>(1, (items + 255) / 256);
     const TmTok ts = tm_arm(s, F_INSERT_ST);
     launch_timed(ts.b, ts.e, k_insert_st<K, 256>, dim3(grid), dim3(256), 0, st, us);
@@ -610,7 +636,7 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
     HIP_TRY(hipGetLastError());
     if (algo == FLIX_INSERT_ST_SHIFT_RIGHT) return FLIX_OK;
     ua.sel = algo == FLIX_INSERT_ST_TL_MIXED ? kSelRoundL : kSelLong;
-    ua.st_max = FLIX_ST_MAX_KEYS;
+    ua.st_max = us.st_max;
   }
   t = tm_arm(s, insert ? F_INSERT : F_DELETE);
   switch (s->gl) {
@@ -795,37 +821,48 @@ int publish_layout(flix_store* s) {
   return FLIX_OK;
 }
 
+// Dump kernels on caller-provided scratch: tot and off [nb], bs [ceil(nb/256)],
+// total [1].  Asynchronous on st.
+int dump_launch(flix_store* s, void* ko, void* vo, u64 capacity, u32* tot, u32* off, u32* bs,
+                u32* total, hipStream_t st) {
+  const u32 nb = s->nb;
+  const u32 nblk = (nb + 255) / 256;
+  const u32 g = std::min<u32>(nblk, 65535);
+  hipLaunchKernelGGL(k_bucket_totals, dim3(g), dim3(256), 0, st, s->hdr, nb, s->pool, tot);
+  hipLaunchKernelGGL(k_scan_blocks_u32, dim3(nblk), dim3(256), 0, st, tot, nb, off, bs);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bs, nblk, total);
+  hipLaunchKernelGGL(k_scan_addback, dim3(nblk), dim3(256), 0, st, off, nb, bs);
+  const u32 gw = std::min<u32>((nb + 3) / 4, 65535);
+  if (s->kb == 32)
+    hipLaunchKernelGGL((k_dump_copy<u32>), dim3(gw), dim3(256), 0, st, s->hdr, (const u32*)s->nkeys,
+                       (const u32*)s->nvals, nb, s->cap, s->pool, off, (u32*)ko, (u32*)vo,
+                       (u64)capacity);
+  else
+    hipLaunchKernelGGL((k_dump_copy<u64>), dim3(gw), dim3(256), 0, st, s->hdr, (const u64*)s->nkeys,
+                       (const u64*)s->nvals, nb, s->cap, s->pool, off, (u64*)ko, (u64*)vo,
+                       (u64)capacity);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
 // Every pair in ascending key order into ko / vo (at most `capacity` of them):
 // per-bucket totals, their scan, then one wave per bucket copies its chain.
 // Synchronizes st.
 int dump_body(flix_store* s, void* ko, void* vo, u64 capacity, hipStream_t st) {
-  u32 nb = s->nb;
-  u32 nblk = (nb + 255) / 256;
-  u32 *tot = nullptr, *off = nullptr, *bs = nullptr, *dummy = nullptr;
+  const u32 nb = s->nb;
+  const u32 nblk = (nb + 255) / 256;
+  u32 *tot = nullptr, *off = nullptr, *bs = nullptr, *total = nullptr;
   int rc;
   if ((rc = dev_alloc(&tot, (u64)nb * 4)) || (rc = dev_alloc(&off, (u64)nb * 4)) ||
-      (rc = dev_alloc(&bs, (u64)nblk * 4)) || (rc = dev_alloc(&dummy, 16))) {
-    dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
+      (rc = dev_alloc(&bs, (u64)nblk * 4)) || (rc = dev_alloc(&total, 16))) {
+    dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&total);
     return rc;
   }
-  u32 g = std::min<u32>(nblk, 65535);
-  hipLaunchKernelGGL(k_bucket_totals, dim3(g), dim3(256), 0, st, s->hdr, nb, s->pool, tot);
-  hipLaunchKernelGGL(k_scan_blocks_u32, dim3(nblk), dim3(256), 0, st, tot, nb, off, bs);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, st, bs, nblk, dummy);
-  hipLaunchKernelGGL(k_scan_addback, dim3(nblk), dim3(256), 0, st, off, nb, bs);
-  u32 gw = std::min<u32>((nb + 3) / 4, 65535);
-  if (s->kb == 32)
-    hipLaunchKernelGGL((k_dump_copy<u32>), dim3(gw), dim3(256), 0, st, s->hdr, (const u32*)s->nkeys,
-                       (const u32*)s->nvals, nb, s->cap, s->pool, off, (u32*)ko,
-                       (u32*)vo, (u64)capacity);
-  else
-    hipLaunchKernelGGL((k_dump_copy<u64>), dim3(gw), dim3(256), 0, st, s->hdr, (const u64*)s->nkeys,
-                       (const u64*)s->nvals, nb, s->cap, s->pool, off, (u64*)ko,
-                       (u64*)vo, (u64)capacity);
-  hipError_t e1 = hipGetLastError();
-  hipError_t e2 = hipStreamSynchronize(st);
-  dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&dummy);
-  return (e1 == hipSuccess && e2 == hipSuccess) ? FLIX_OK : FLIX_EHIP;
+  rc = dump_launch(s, ko, vo, capacity, tot, off, bs, total, st);
+  const hipError_t e2 = hipStreamSynchronize(st);
+  dev_free(&tot); dev_free(&off); dev_free(&bs); dev_free(&total);
+  if (rc) return rc;
+  return e2 == hipSuccess ? FLIX_OK : note_hip_error(e2, "dump", __LINE__);
 }
 
 // Nodes, directory, occupancy summary and free stack from nd sorted, distinct
@@ -1132,6 +1169,7 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   if (fill > cap || fill == 0) return FLIX_EINVAL;
   if (cfg->max_batch == 0 || cfg->max_batch > 0x7FFFFFFFull) return FLIX_EINVAL;
   if (cfg->insert_algo > FLIX_INSERT_ADAPTIVE) return FLIX_EINVAL;
+  if (cfg->read_path > FLIX_READ_GROUPS || cfg->reserved != 0) return FLIX_EINVAL;
   flix_store* s = new (std::nothrow) flix_store;
   if (!s) return FLIX_ENOMEM;
   s->cfg = *cfg;

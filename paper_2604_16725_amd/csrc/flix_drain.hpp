@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       ra.maxpq = d.maxpq;
       ra.pool = L.pool;
       ra.err = &a.ctl->status;
-      ra.occ = L.occ;
+      ra.occ = L.occ.w0;
       ra.cuts = nullptr;   // each share searches its own cuts
       const u32 nshares = (u32)(((u64)n + L.nb + SR - 1) / SR);
       for (u32 vb = blk; vb < nshares; vb += G) {

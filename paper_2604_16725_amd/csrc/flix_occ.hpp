@@ -37,6 +37,16 @@ __host__ __device__ inline u64 occ_words(u64 nb) {
   return occ_words0(nb) + occ_words1(nb) + occ_words2(nb);
 }
 
+// The three levels of a summary laid out one after another from w0 (as the
+// store allocates them), for nb buckets.
+__host__ __device__ inline OccLevels occ_levels(u64* w0, u64 nb) {
+  OccLevels o;
+  o.w0 = w0;
+  o.w1 = w0 + occ_words0(nb);
+  o.w2 = o.w1 + occ_words1(nb);
+  return o;
+}
+
 __host__ __device__ __forceinline__ u32 ctz64(u64 x) { return (u32)__builtin_ctzll(x); }
 __host__ __device__ __forceinline__ u32 top64(u64 x) { return 63u - (u32)__builtin_clzll(x); }
 

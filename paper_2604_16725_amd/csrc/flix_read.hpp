@@ -39,7 +39,8 @@ struct ReadArgs {
   u32 maxpq;           // range output stride
   u32 pool;            // nodes in the pool (bound of every link)
   u32* err;            // sticky status word for internal errors
-  OccLevels occ;       // which buckets hold keys (flix_occ.hpp)
+  u64* occ;            // occupancy summary of the nb buckets, its three levels
+                       // laid out from here (flix_occ.hpp: occ_levels)
   const u32* cuts;     // merge-path cut of every share boundary [nshares + 1], or
                        // nullptr: each workgroup searches its own two cuts
 };

@@ -253,7 +253,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
     }
     if (op == kOpPredecessor) {
       bool bad = false;
-      const u64 at = predecessor_slot<K>(a.hdr, a.nkeys, a.occ, a.pool, a.cap, b, x, &bad);
+      const u64 at = predecessor_slot<K>(a.hdr, a.nkeys, occ_levels(a.occ, a.nb), a.pool, a.cap, b, x, &bad);
       if (bad) atomicCAS(a.err, 0u, kErrInternal);
       a.out_k[orig] = at == ~0ull ? K(0) : a.nkeys[at];
       a.out_v[orig] = at == ~0ull ? NF : a.nvals[at];
@@ -280,7 +280,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
         rv = a.nvals[(u64)node * a.cap + p];
       } else {
         NodeHdr g;
-        u32 nn = next_nonempty(a.hdr, a.occ, a.nb, a.pool, &b, h, &g);
+        u32 nn = next_nonempty(a.hdr, occ_levels(a.occ, a.nb), a.nb, a.pool, &b, h, &g);
         if (nn == kBadLink) {
           atomicCAS(a.err, 0u, kErrInternal);
         } else if (nn != kNil) {
@@ -305,7 +305,7 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
           }
           if (ub < h.size) break;
           NodeHdr g;
-          u32 nn = next_nonempty(a.hdr, a.occ, a.nb, a.pool, &b, h, &g);
+          u32 nn = next_nonempty(a.hdr, occ_levels(a.occ, a.nb), a.nb, a.pool, &b, h, &g);
           if (nn == kBadLink) {
             atomicCAS(a.err, 0u, kErrInternal);
             break;

@@ -392,7 +392,14 @@ struct UpdArgs {
   OccLevels occ;      // bucket occupancy summary, kept current here
   u32 sel = 0;        // insert kernels: which work items this launch takes (kSel*)
   u32 st_max = 0;     // slice-length threshold of the kernel choice
+  u32 wide_min = 0;   // > 0: single-node buckets with at least this many batch
+                      // keys belong to the workgroup-wide insert kernel
 };
+
+// Work items of the workgroup-wide insert kernel (k_insert_wide).
+__device__ __forceinline__ bool is_wide(u32 wide_min, const WorkItem& w) {
+  return wide_min != 0 && (w.head & kSingleNode) && w.e - w.s >= wide_min;
+}
 
 // Workgroup-shared state of the apply kernels: a key counter and the map of
 // the work list's regions.
@@ -461,6 +468,9 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
     return;
   }
   const u32 nitems = load_work_map(ctl, sh.pre);
+  // a call-level choice that gives this kernel nothing ends it here (uniform)
+  if ((a.sel == kSelRound || a.sel == kSelRoundL) && !sel_takes(a.sel, a.st_max, 0u, a.m, nitems))
+    return;
   const u32 f = a.cap / 2;
   u64 added = 0;
   const u32 stride = nblk * GPB;
@@ -475,7 +485,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       cur.move(sh.pre, it + stride);
       wnext = a.work[cur.slot(it + stride, a.rcap)];
     }
-    if (!sel_takes(a.sel, a.st_max, w.e - w.s, a.m, nitems)) continue;
+    if (!sel_takes(a.sel, a.st_max, w.e - w.s, a.m, nitems) || is_wide(a.wide_min, w)) continue;
     u32 X = w.b;
     NodeHdr hX;
     bool fence_known = true;
@@ -873,6 +883,8 @@ __global__ __launch_bounds__(NT) void k_insert_st(UpdArgs<K> a) {
     return;
   }
   const u32 nitems = load_work_map(ctl, sh.pre);
+  if ((a.sel == kSelRound || a.sel == kSelRoundL) && !sel_takes(a.sel, a.st_max, 0u, a.m, nitems))
+    return;
   u64 added = 0;
   const u32 stride = gridDim.x * NT;
   u32 it = blockIdx.x * NT + threadIdx.x;
@@ -888,6 +900,225 @@ __global__ __launch_bounds__(NT) void k_insert_st(UpdArgs<K> a) {
   if ((threadIdx.x & 63u) == 0 && added) atomicAdd(&sh.counter, added);
   __syncthreads();
   if (threadIdx.x == 0 && sh.counter) atomicAdd((unsigned long long*)&a.ctl->nkeys, sh.counter);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-wide insert (elastic compute for a hot bucket, Section 3.4): a
+// single-node bucket whose slice holds at least `wide_min` batch keys (a dense
+// run of new keys) is merged by a whole workgroup instead of one lane group
+// walking the slice in node-sized chunks.  The node's keys A[0, S) are staged
+// in LDS; every live slice key (last of its equal-key run) and every kept node
+// key gets its merged position from counts, so all of them are written in
+// parallel:
+//   pos(live slice key k) = rank of k among live slice keys
+//                           + #{node keys < k} - #{dropped node keys < k}
+//   pos(node key i)       = i - #{dropped node keys before i}
+//                           + #{live slice keys < A[i]}
+// where a node key is dropped when a live slice key equals it (the batch pair
+// replaces it).  The c merged pairs form k = max(1, floor(c / (cap/2))) pieces
+// of near-equal size (the split rule of the lane-group kernel); pieces 1..k-1
+// come from the free list and are chained after the head, the last piece
+// keeps the bucket's maxBucket as its fence.  The node budget bound of the
+// slice kernel, floor((S + t) / (cap/2)) - 1 for a single-node bucket, covers
+// the k - 1 new nodes.
+// ---------------------------------------------------------------------------
+template <typename K>
+struct WideLds {
+  K ak[256], av[256];       // staged node
+  u32 cnt[257];             // live slice keys by lower bound in the node
+  u32 eq[257];              // node key i is replaced by a slice key
+  u32 qinc[257];            // inclusive prefix of cnt
+  u32 dropx[257];           // exclusive prefix of eq
+  u32 tmp[8];
+  u32 list[256];            // wide items found in the current window
+  u32 nlist;
+  u32 live_total, match_total;
+  u32 base_id;
+  u32 bad;
+};
+
+template <typename K, int NT>
+__device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideLds<K>& L,
+                                   unsigned long long& added_total) {
+  const u32 tid = threadIdx.x, lane = tid & 63u;
+  const u32 f = a.cap / 2;
+  const u32 X = w.b;
+  const u32 S = w.head & ~kSingleNode;
+  const u32 t = w.e - w.s;
+  K* const xk = a.nkeys + (u64)X * a.cap;
+  K* const xv = a.nvals + (u64)X * a.cap;
+  for (u32 i = tid; i < S; i += NT) {
+    L.ak[i] = xk[i];
+    L.av[i] = xv[i];
+  }
+  for (u32 i = tid; i <= S; i += NT) {
+    L.cnt[i] = 0;
+    L.eq[i] = 0;
+  }
+  if (tid == 0) {
+    L.live_total = 0;
+    L.match_total = 0;
+    L.bad = 0;
+  }
+  __syncthreads();
+  // 1. counts: live keys by lower bound in the node (wave-aggregated: the
+  //    slice is sorted, so a wave's lower bounds form runs), matches
+  u32 my_live = 0, my_match = 0;
+  for (u32 j0 = 0; j0 < t; j0 += NT) {
+    const u32 j = j0 + tid;
+    const bool valid = j < t;
+    K k = K(0);
+    bool live = false;
+    u32 lb = 0;
+    if (valid) {
+      const u32 g = w.s + j;
+      k = a.skeys[g];
+      live = (g + 1 == a.m) || a.skeys[g + 1] != k;
+      lb = lower_bound_idx<K>(L.ak, 0u, S, k);
+      if (live && lb < S && L.ak[lb] == k) {
+        L.eq[lb] = 1;
+        ++my_match;
+      }
+    }
+    my_live += live ? 1u : 0u;
+    const u64 live_m = wave_ballot(live);
+    const u32 lb_next = (u32)__shfl_down((int)lb, 1, 64);
+    const bool valid_next = lane < 63 && j + 1 < t;
+    const bool seg_end = valid && (!valid_next || lb_next != lb);
+    const u64 end_m = wave_ballot(seg_end);
+    if (seg_end) {
+      const u64 below = end_m & ((1ull << lane) - 1ull);
+      const u32 first = below ? 64u - (u32)__clzll(below) : 0u;   // one past the previous end
+      const u64 span = (lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull)) & ~((1ull << first) - 1ull);
+      const u32 c = (u32)__popcll(live_m & span);
+      if (c) atomicAdd(&L.cnt[lb], c);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    my_live += __shfl_xor(my_live, off, 64);
+    my_match += __shfl_xor(my_match, off, 64);
+  }
+  if (lane == 0) {
+    if (my_live) atomicAdd(&L.live_total, my_live);
+    if (my_match) atomicAdd(&L.match_total, my_match);
+  }
+  __syncthreads();
+  // prefixes over the node positions (at most 257 entries, one thread)
+  if (tid == 0) {
+    u32 q = 0, d = 0;
+    for (u32 i = 0; i <= S; ++i) {
+      q += L.cnt[i];
+      L.qinc[i] = q;
+      L.dropx[i] = d;
+      d += L.eq[i];
+    }
+  }
+  __syncthreads();
+  const u32 c = S + L.live_total - L.match_total;
+  const u32 k = c > a.cap ? c / f : 1u;
+  if (k > 1) {
+    if (tid == 0) {
+      const u32 top = atomicSub(&a.ctl->free_top, k - 1);
+      L.base_id = top;
+      if (top < k - 1 || top > a.pool) {   // budget bound violated: never expected
+        atomicCAS(a.status, 0u, kErrInternal);
+        L.bad = 1;
+      }
+    }
+    __syncthreads();
+    if (L.bad) return;
+  }
+  const u32 base_id = k > 1 ? L.base_id : 0u;
+  const u64 fence_last = (u64)a.mkba[w.b];
+  auto node_of = [&](u32 p) -> u32 { return p == 0 ? X : a.free_ids[base_id - p]; };
+  auto put = [&](u32 pos, K kk, K vv) {
+    const u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
+    const u32 node = node_of(pc);
+    if (node >= a.pool) {
+      atomicCAS(a.status, 0u, kErrInternal);
+      return;
+    }
+    const u32 slot = (k == 1) ? pos : pos - piece_start(pc, c, k);
+    a.nkeys[(u64)node * a.cap + slot] = kk;
+    a.nvals[(u64)node * a.cap + slot] = vv;
+    if (k > 1 && pc + 1 < k && slot + 1 == piece_start(pc + 1, c, k) - piece_start(pc, c, k))
+      a.hdr[node].fence = (u64)kk;
+  };
+  // 2. kept node keys
+  for (u32 i = tid; i < S; i += NT) {
+    if (L.eq[i]) continue;
+    const u32 q = L.qinc[i];   // live keys with lower bound <= i; none equals A[i]
+    put(i - L.dropx[i] + q, L.ak[i], L.av[i]);
+  }
+  // 3. live slice keys, ranked by a running block scan
+  u32 run = 0;
+  for (u32 j0 = 0; j0 < t; j0 += NT) {
+    const u32 j = j0 + tid;
+    bool live = false;
+    K kk = K(0);
+    if (j < t) {
+      const u32 g = w.s + j;
+      kk = a.skeys[g];
+      live = (g + 1 == a.m) || a.skeys[g + 1] != kk;
+    }
+    u32 tot;
+    const u32 r = block_exclusive_scan<NT>(live ? 1u : 0u, L.tmp, &tot);
+    if (live) {
+      const u32 lb = lower_bound_idx<K>(L.ak, 0u, S, kk);
+      put(run + r + lb - L.dropx[lb], kk, a.svals[w.s + j]);
+    }
+    run += tot;
+  }
+  // 4. headers: sizes and links of the pieces; the last keeps the fence
+  for (u32 p = tid; p < k; p += NT) {
+    const u32 node = node_of(p);
+    if (node >= a.pool) {
+      atomicCAS(a.status, 0u, kErrInternal);
+      continue;
+    }
+    a.hdr[node].size = piece_start(p + 1, c, k) - piece_start(p, c, k);
+    a.hdr[node].next = (p + 1 < k) ? node_of(p + 1) : kNil;
+    if (p + 1 == k) a.hdr[node].fence = fence_last;
+  }
+  if (tid == 0) {
+    if (k > 1) a.bnodes[w.b] += k - 1;
+    if (S == 0 && c > 0) occ_set(a.occ, w.b);
+    added_total += c - S;
+  }
+  __syncthreads();   // LDS is reused by the next item
+}
+
+// Every workgroup scans its windows of the work list for wide items and
+// merges each of them with all its threads.
+template <typename K, int NT>
+__global__ __launch_bounds__(NT) void k_insert_wide(UpdArgs<K> a) {
+  __shared__ UpdShared sh;
+  __shared__ WideLds<K> L;
+  const Ctl* ctl = a.ctl;
+  if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot) return;   // the other kernels report it
+  const u32 nitems = load_work_map(ctl, sh.pre);
+  unsigned long long added = 0;
+  for (u32 base = blockIdx.x * NT; base < nitems; base += gridDim.x * NT) {
+    if (threadIdx.x == 0) L.nlist = 0;
+    __syncthreads();
+    const u32 it = base + threadIdx.x;
+    if (it < nitems) {
+      WorkCursor cur;
+      cur.seek(sh.pre, it);
+      const WorkItem w = a.work[cur.slot(it, a.rcap)];
+      if (is_wide(a.wide_min, w)) L.list[atomicAdd(&L.nlist, 1u)] = it;
+    }
+    __syncthreads();
+    const u32 nl = L.nlist;
+    for (u32 q = 0; q < nl; ++q) {
+      const u32 it2 = L.list[q];
+      WorkCursor cur;
+      cur.seek(sh.pre, it2);
+      const WorkItem w = a.work[cur.slot(it2, a.rcap)];
+      wide_insert_bucket<K, NT>(a, w, L, added);
+    }
+  }
+  if (threadIdx.x == 0 && added) atomicAdd((unsigned long long*)&a.ctl->nkeys, added);
 }
 
 // ---------------------------------------------------------------------------

@@ -36,10 +36,13 @@ class FlixConfig(ctypes.Structure):
         ("pool_bytes", ctypes.c_uint64),
         ("fill", ctypes.c_uint32),
         ("insert_algo", ctypes.c_uint32),
+        ("read_path", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
 INSERT_ALGOS = {"tl_bulk": 0, "st_shift_right": 1, "st_tl_mixed": 2, "adaptive": 3}
+READ_PATHS = {"sorted": 0, "groups": 1}
 
 
 class FlixStats(ctypes.Structure):
@@ -172,7 +175,7 @@ class Store:
 
     def __init__(self, key_bits: int = 32, capacity: int = 128, lanes: int = 16,
                  radix_bits: int = 8, max_batch: int = 1 << 20, pool_bytes: int = 0,
-                 fill: int = 0, insert_algo="tl_bulk", stream=None):
+                 fill: int = 0, insert_algo="tl_bulk", read_path="sorted", stream=None):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -181,8 +184,9 @@ class Store:
         self._ok_dtypes = ((torch.int32, torch.uint32) if key_bits == 32
                            else (torch.int64, torch.uint64))
         algo = INSERT_ALGOS[insert_algo] if isinstance(insert_algo, str) else int(insert_algo)
+        rp = READ_PATHS[read_path] if isinstance(read_path, str) else int(read_path)
         self.cfg = FlixConfig(key_bits, capacity, lanes, radix_bits, max_batch, pool_bytes,
-                              fill, algo)
+                              fill, algo, rp, 0)
         h = ctypes.c_void_p()
         rc = self.lib.flix_create(ctypes.byref(self.cfg), _stream(stream), ctypes.byref(h))
         if rc != FLIX_OK:

@@ -202,7 +202,7 @@ def read_path(n_keys: int = 1 << 26, batch: int = 1 << 20, range_len: int = 16,
     hi = np.minimum(lo + np.uint64(range_len - 1), np.uint64(0xFFFFFFFF))
     out = dict(key_bits=kb, capacity=128, build_keys=build, build_vals=build_v,
                lookup=look, successor=succ, range_lo=lo.astype(np.uint32),
-               range_hi=hi.astype(np.uint32), range_len=range_len)
+               range_hi=hi.astype(np.uint32), range_len=range_len, keyspace=ks)
     if with_zipf:
         zr = zipf_ranks(n_keys, n_hit, zipf_s, rng)
         zl = np.concatenate([build[zr], ks.absent(batch - n_hit)])
