@@ -172,6 +172,17 @@ int flix_size(flix_store* s, uint64_t* out, void* stream);
 int flix_dump(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capacity,
               uint64_t* out_n, void* stream);
 
+/* flix_dump without any allocation, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid it).
+ * Same arguments, results and errors as flix_dump.  Its per-bucket scratch is
+ * a fixed 16 MiB device array of the library on each GPU (looked up by
+ * flix_create or by the first call on that GPU), so stores of more than 2^21
+ * buckets -> FLIX_EINVAL.  Calls on one GPU share that array: calls that
+ * overlap in time on one GPU (other streams, other threads) race and must not
+ * be issued.  Synchronizes `stream`. */
+int flix_dump_noalloc(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capacity,
+                      uint64_t* out_n, void* stream);
+
 /* Device invariant checker: node keys strictly increasing and inside their
  * node's (previous maxKey, maxKey] range, chain fences increasing and ending at
  * maxBucket, sizes within capacity, no empty non-head node, chain lengths,

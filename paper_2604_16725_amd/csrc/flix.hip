@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -21,6 +22,15 @@
 #include "flix_update.hpp"
 
 using namespace flix;
+
+// Scratch of flix_dump_noalloc: per-bucket totals, their offsets, the block
+// sums of the offset scan and the scan total, for stores of at most
+// kNoAllocBuckets buckets (16 MiB, held by every GPU the library runs on
+// until the process ends).
+constexpr u64 kNoAllocBuckets = 1ull << 21;
+constexpr u64 kNoAllocBlocks = kNoAllocBuckets / 256;
+constexpr u64 kNoAllocWords = 2 * kNoAllocBuckets + kNoAllocBlocks + 64;
+static __device__ __align__(256) u32 scratch[kNoAllocWords];
 
 namespace {
 
@@ -821,6 +831,27 @@ int publish_layout(flix_store* s) {
   return FLIX_OK;
 }
 
+// Device address of `scratch` on each GPU (in host code the array's name is
+// not a device address), looked up once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+u32* g_scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(u32** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return FLIX_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return note_hip_error(e, "scratch symbol address", __LINE__);
+    g_scratch_ptr[dev] = static_cast<u32*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return FLIX_OK;
+}
+
 // Dump kernels on caller-provided scratch: tot and off [nb], bs [ceil(nb/256)],
 // total [1].  Asynchronous on st.
 int dump_launch(flix_store* s, void* ko, void* vo, u64 capacity, u32* tot, u32* off, u32* bs,
@@ -1170,6 +1201,13 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   if (cfg->max_batch == 0 || cfg->max_batch > 0x7FFFFFFFull) return FLIX_EINVAL;
   if (cfg->insert_algo > FLIX_INSERT_ADAPTIVE) return FLIX_EINVAL;
   if (cfg->read_path > FLIX_READ_GROUPS || cfg->reserved != 0) return FLIX_EINVAL;
+  {
+    // device address of the allocation-free entry point's scratch on this GPU;
+    // a failed lookup is reported by that entry point (it retries), stores
+    // do not depend on it
+    u32* sc = nullptr;
+    if (noalloc_scratch(&sc) != FLIX_OK) (void)hipGetLastError();
+  }
   flix_store* s = new (std::nothrow) flix_store;
   if (!s) return FLIX_ENOMEM;
   s->cfg = *cfg;
@@ -1382,6 +1420,37 @@ int flix_dump(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capaci
   if (n == 0) return FLIX_OK;
   if (!d_keys_out || !d_vals_out) return FLIX_EINVAL;
   return dump_body(s, d_keys_out, d_vals_out, capacity, st);
+}
+
+int flix_dump_noalloc(flix_store* s, void* d_keys_out, void* d_vals_out, uint64_t capacity,
+                      uint64_t* out_n, void* stream) {
+  (void)hipGetLastError();  // drop errors left by other code on this thread
+  if (!s) return FLIX_ESTATE;
+  if (!out_n) return FLIX_EINVAL;
+  if (s->nb > kNoAllocBuckets) {
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "flix_dump_noalloc: %u buckets, at most %llu supported", s->nb,
+                  (unsigned long long)kNoAllocBuckets);
+    return FLIX_EINVAL;
+  }
+  u32* sc = nullptr;
+  int rc = noalloc_scratch(&sc);
+  if (rc) return rc;
+  hipStream_t st = S(stream);
+  u64 n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, &s->ctl->nkeys, sizeof(u64), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *out_n = n;
+  if (n > capacity) return FLIX_EINVAL;
+  if (n == 0) return FLIX_OK;
+  if (!d_keys_out || !d_vals_out) return FLIX_EINVAL;
+  u32* tot = sc;
+  u32* off = sc + kNoAllocBuckets;
+  u32* bs = sc + 2 * kNoAllocBuckets;
+  u32* total = bs + kNoAllocBlocks;
+  if ((rc = dump_launch(s, d_keys_out, d_vals_out, capacity, tot, off, bs, total, st))) return rc;
+  HIP_TRY(hipStreamSynchronize(st));
+  return FLIX_OK;
 }
 
 int flix_check(flix_store* s, void* stream) {

@@ -129,6 +129,7 @@ def load_library(path: str = LIB_PATH):
         "flix_restructure": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), vp]),
         "flix_size": (i32, [vp, ctypes.POINTER(u64), vp]),
         "flix_dump": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
+        "flix_dump_noalloc": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
         "flix_check": (i32, [vp, vp]),
         "flix_status": (i32, [vp, vp]),
         "flix_get_stats": (i32, [vp, ctypes.POINTER(FlixStats), vp]),
@@ -294,6 +295,16 @@ class Store:
                                      _stream(stream)), "flix_dump")
         m = int(out_n.value)
         return k[:m], v[:m]
+
+    def dump_into(self, keys_out, vals_out, noalloc=False, stream=None) -> int:
+        """Contents into caller-provided device buffers (flix_dump, or
+        flix_dump_noalloc which allocates nothing); returns the key count."""
+        fn = self.lib.flix_dump_noalloc if noalloc else self.lib.flix_dump
+        out_n = ctypes.c_uint64()
+        cap = min(keys_out.numel(), vals_out.numel())
+        self._chk(fn(self.h, _ptr(keys_out), _ptr(vals_out), cap, ctypes.byref(out_n),
+                     _stream(stream)), "flix_dump_noalloc" if noalloc else "flix_dump")
+        return int(out_n.value)
 
     def check(self, stream=None) -> int:
         return int(self.lib.flix_check(self.h, _stream(stream)))
