@@ -320,72 +320,96 @@ def update_heavy_rounds(args):
     """The update-heavy workload: u64 keys and values, bulk load 2^24 keys,
     rounds of 2^20 inserts of new keys then 2^20 deletes of present keys,
     uniform (even rounds) and clustered into 64 runs (odd rounds); every call
-    timed with events.  Algorithmic bytes per op follow the byte model of the
-    update kernels (sort of key+value, slices, node reads and writes)."""
+    timed with events.  The rounds run twice on fresh stores: as they come,
+    and with a restructuring after every clustered round (the paper's knob
+    against the long chains the dense runs leave), timed on its own.
+    Algorithmic bytes per op follow the byte model of the update kernels."""
     import torch
     from paper_2604_16725_amd import flix
     from paper_2604_16725_amd import workloads as w
     t0 = time.time()
     u = w.UpdateHeavy(n_keys=1 << 24, batch=1 << 20, runs=64)
-    st = flix.Store(key_bits=64, capacity=128, lanes=16, radix_bits=8, max_batch=1 << 20)
-    st.bulk_load(torch.from_numpy(u.build_keys.view(np.int64)).cuda(),
-                 torch.from_numpy(u.build_vals.view(np.int64)).cuda())
-    rows = {"uniform": {"insert": [], "delete": []}, "clustered": {"insert": [], "delete": []}}
-    kern = {"uniform": {"insert_apply": [], "delete_apply": []},
-            "clustered": {"insert_apply": [], "delete_apply": []}}
-    m = 1 << 20
+    build_k = torch.from_numpy(u.build_keys.view(np.int64)).cuda()
+    build_v = torch.from_numpy(u.build_vals.view(np.int64)).cuda()
+    rounds = []
     for r in range(args.update_rounds):
         ins, iv, dele = u.round(r)
-        di = torch.from_numpy(ins.view(np.int64)).cuda()
-        dv = torch.from_numpy(iv.view(np.int64)).cuda()
-        dd = torch.from_numpy(dele.view(np.int64)).cuda()
-        kind = "uniform" if r % 2 == 0 else "clustered"
-        for name, fn, fam in (("insert", lambda: st.insert(di, dv), "insert_apply"),
-                              ("delete", lambda: st.delete(dd), "delete_apply")):
-            st.set_timing(True, only=fam)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            a.record()
-            fn()
-            b.record()
-            torch.cuda.synchronize()
-            kms, kn = st.kernel_time(fam)
-            st.set_timing(False)
-            rows[kind][name].append(a.elapsed_time(b))
-            kern[kind][fam].append(kms / max(kn, 1))
-        if st.status() != 0:
-            raise RuntimeError(f"device error in update round {r}")
-    stt = st.stats()
-    st.close()
+        rounds.append((torch.from_numpy(ins.view(np.int64)).cuda(),
+                       torch.from_numpy(iv.view(np.int64)).cuda(),
+                       torch.from_numpy(dele.view(np.int64)).cuda()))
+    log(f"[bench] update heavy: {len(rounds)} rounds generated ({time.time() - t0:.0f}s)")
+    m = 1 << 20
+
+    def run(restructure):
+        st = flix.Store(key_bits=64, capacity=128, lanes=16, radix_bits=8, max_batch=m)
+        st.bulk_load(build_k, build_v)
+        rows = {"uniform": {"insert": [], "delete": []},
+                "clustered": {"insert": [], "delete": []}}
+        kern = {"uniform": {"insert": [], "delete": []},
+                "clustered": {"insert": [], "delete": []}}
+        rs = []
+        for r, (di, dv, dd) in enumerate(rounds):
+            kind = "uniform" if r % 2 == 0 else "clustered"
+            for name, fn, fams in (("insert", lambda: st.insert(di, dv),
+                                    ("insert_apply", "insert_wide")),
+                                   ("delete", lambda: st.delete(dd), ("delete_apply",))):
+                st.set_timing(True)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                a.record()
+                fn()
+                b.record()
+                torch.cuda.synchronize()
+                kms = sum(st.kernel_time(f)[0] for f in fams)
+                st.set_timing(False)
+                rows[kind][name].append(a.elapsed_time(b))
+                kern[kind][name].append(kms)
+            if restructure and kind == "clustered":
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                before, after = st.restructure()
+                rs.append(((time.perf_counter() - t1) * 1e3, before, after))
+            if st.status() != 0:
+                raise RuntimeError(f"device error in update round {r}")
+        stt = st.stats()
+        st.close()
+        res = {"final": stt}
+        for kind in rows:
+            d = {}
+            for name in ("insert", "delete"):
+                ms = np.array(rows[kind][name])
+                if ms.size == 0:
+                    continue
+                d[name] = {"Mops_s_median": round(m / (np.median(ms) / 1000) / 1e6, 1),
+                           "ms_median": round(float(np.median(ms)), 4),
+                           "ms_max": round(float(ms.max()), 4), "rounds": int(ms.size),
+                           "apply_kernels_ms_median": round(float(np.median(kern[kind][name])), 4)}
+            if d:
+                res[kind] = d
+        if rs:
+            a = np.array(rs)
+            res["restructure"] = {"count": len(rs), "ms_median": round(float(np.median(a[:, 0])), 2),
+                                  "nodes_recovered_frac_median":
+                                      round(float(np.median((a[:, 1] - a[:, 2]) / a[:, 1])), 4)}
+        return res
+
+    plain = run(False)
+    with_rs = run(True)
     # algorithmic bytes per op (u64 keys and values, capacity 128, bulk fill 64)
     sort_b = 8 + (8 + 16) + 7 * 2 * 16      # histogram read, top-digit pass, local passes
     ins_b = sort_b + 8 + 12 + 3 + 0.98 * (64 + 68) * 16 / 4
     del_b = sort_b - 7 * 2 * 8 + 8 + 3 + 0.98 * (64 + 68) * 16 / 4
+    for res in (plain, with_rs):
+        if "uniform" in res and "insert" in res["uniform"]:
+            for name, b_ in (("insert", ins_b), ("delete", del_b)):
+                res["uniform"][name]["frac_whole_call"] = round(
+                    b_ * m / (res["uniform"][name]["ms_median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     out = {"workload": f"u64 store, bulk load 2^24 keys, {args.update_rounds} rounds of 2^20 "
                        f"inserts then 2^20 deletes, even rounds uniform, odd rounds clustered "
                        f"into 64 runs",
-           "final": stt}
-    for kind in rows:
-        d = {}
-        for name in ("insert", "delete"):
-            ms = np.array(rows[kind][name])
-            if ms.size == 0:
-                continue
-            d[name] = {"Mops_s_median": round(m / (np.median(ms) / 1000) / 1e6, 1),
-                       "ms_median": round(float(np.median(ms)), 4),
-                       "ms_max": round(float(ms.max()), 4), "rounds": int(ms.size)}
-            fam = "insert_apply" if name == "insert" else "delete_apply"
-            kms = np.array(kern[kind][fam])
-            d[name]["apply_kernel_ms_median"] = round(float(np.median(kms)), 4)
-        if d:
-            d["alg_bytes_per_op_model"] = {"insert": ins_b, "delete": del_b} if kind == "uniform" \
-                else "sort-dominated (about 230 B/op)"
-            if kind == "uniform" and "insert" in d:
-                d["insert"]["frac_whole_call"] = round(
-                    ins_b * m / (d["insert"]["ms_median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                d["delete"]["frac_whole_call"] = round(
-                    del_b * m / (d["delete"]["ms_median"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-            out[kind] = d
+           "alg_bytes_per_op_model_uniform": {"insert": ins_b, "delete": del_b},
+           "rounds_as_they_come": plain,
+           "restructure_after_clustered_rounds": with_rs}
     log(f"[bench] update heavy ({time.time() - t0:.0f}s): {out}")
     return out
 
@@ -645,7 +669,7 @@ def main():
     log("[bench] warmup done")
 
     fams = ["sort_hist", "sort_pass", "sort_local", "read_cuts", "read_apply", "part",
-            "group_read", "slices", "insert_apply", "delete_apply", "insert_st"]
+            "group_read", "slices", "insert_apply", "delete_apply", "insert_st", "insert_wide"]
 
     def run_steps(k):
         torch.cuda.synchronize()

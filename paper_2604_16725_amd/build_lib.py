@@ -2,9 +2,9 @@
 
     python -m paper_2604_16725_amd.build_lib
 
-The library is three translation units compiled in parallel (the C ABI with
-the sort, update and partition kernels; the read kernels; the persistent
-drain) and linked into one shared object.  Every kernel is compiled for
+The library is four objects compiled in parallel (the C ABI with the sort,
+update and partition kernels; the read kernels for 32-bit and for 64-bit keys;
+the persistent drain) and linked into one shared object.  Every kernel is compiled for
 gfx950 only, without packed-FP32 instructions.
 """
 import os
@@ -14,7 +14,12 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["flix.hip", "flix_read_tu.hip", "flix_drain_tu.hip"]
+# (source, object, extra flags)
+UNITS = [("flix.hip", "flix.o", []),
+         ("flix_read_tu.hip", "flix_read32.o", ["-DFLIX_READ_KEY_BITS=32"]),
+         ("flix_read_tu.hip", "flix_read64.o", ["-DFLIX_READ_KEY_BITS=64"]),
+         ("flix_drain_tu.hip", "flix_drain_tu.o", [])]
+SOURCES = sorted({u[0] for u in UNITS})
 SRC = os.path.join(CSRC, SOURCES[0])
 OUT_DIR = os.path.join(HERE, "lib")
 LIB = os.path.join(OUT_DIR, "libflix.so")
@@ -32,9 +37,9 @@ HIPCC_FLAGS = [
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     objs, procs = [], []
-    for src in SOURCES:
-        obj = os.path.join(OUT_DIR, src.replace(".hip", ".o"))
-        cmd = ["hipcc", *HIPCC_FLAGS, "-c", "-o", obj + ".tmp", os.path.join(CSRC, src)]
+    for src, o, extra in UNITS:
+        obj = os.path.join(OUT_DIR, o)
+        cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-c", "-o", obj + ".tmp", os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), obj))

@@ -68,7 +68,7 @@ struct ReadSmem {
 // of the workgroup call; `ntouch` buckets listed in v.tl, local bucket lb is
 // global bucket b0 + lb, at most RQ * NT keys).
 template <typename K, int NT, int GL, int KPL, int U, int RQ>
-__device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>& v, u32 b0,
+__device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>& v, u32 b0,
                                u32 nq, u32 ntouch) {
   constexpr int NG = NT / GL;
   const u32 tid = threadIdx.x;
@@ -324,7 +324,8 @@ __device__ void resolve_slices(const ReadArgs<K>& a, int op, const SliceView<K>&
 
 // One share (workgroup-sized unit) of a read batch; `vb` is the share index.
 template <typename K, int NT, int S, int GL, int KPL, int U>
-__device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, NT>& sm) {
+__device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
+                                           ReadSmem<K, S, NT>& sm) {
   static_assert(NT == 256, "merge-path search assumes 256 threads");
   constexpr int NG = NT / GL;
   K* s_q = sm.q;
@@ -458,12 +459,15 @@ __device__ void read_share(const ReadArgs<K>& a, int op, u32 vb, ReadSmem<K, S, 
 }
 
 // Eight waves per SIMD (64 VGPRs): the kernel is latency-bound, and the
-// register budget, not LDS, otherwise caps it at six workgroups per CU.
-template <typename K, int NT, int S, int GL, int KPL, int U>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_read_apply2(
-    ReadArgs<K> a, int op) {
+// register budget, not LDS, otherwise caps it at six workgroups per CU.  One
+// instantiation per operation: the paths of the other operations are compiled
+// out, which keeps the register and scalar-register budget for the one that
+// runs.
+template <typename K, int NT, int S, int GL, int KPL, int U, int OP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OP == kOpRange ? 6 : 8))) void k_read_apply2(
+    ReadArgs<K> a) {
   __shared__ ReadSmem<K, S, NT> sm;
-  read_share<K, NT, S, GL, KPL, U>(a, op, blockIdx.x, sm);
+  read_share<K, NT, S, GL, KPL, U>(a, OP, blockIdx.x, sm);
 }
 
 }  // namespace flix

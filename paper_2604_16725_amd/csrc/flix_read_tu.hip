@@ -18,8 +18,25 @@ template <typename K, int GL, int KPL>
 void read2_k(const ReadArgs<K>& a, int op, u32 grid, hipStream_t st, hipEvent_t e0,
              hipEvent_t e1) {
   constexpr int U = KPL >= 16 ? 2 : 4;
-  launch_timed(e0, e1, k_read_apply2<K, 256, ReadShare<K>::S, GL, KPL, U>, dim3(grid), dim3(256),
-               0, st, a, op);
+  constexpr int S = ReadShare<K>::S;
+  switch (op) {
+    case kOpLookup:
+      launch_timed(e0, e1, k_read_apply2<K, 256, S, GL, KPL, U, kOpLookup>, dim3(grid), dim3(256),
+                   0, st, a);
+      break;
+    case kOpSuccessor:
+      launch_timed(e0, e1, k_read_apply2<K, 256, S, GL, KPL, U, kOpSuccessor>, dim3(grid),
+                   dim3(256), 0, st, a);
+      break;
+    case kOpRange:
+      launch_timed(e0, e1, k_read_apply2<K, 256, S, GL, KPL, U, kOpRange>, dim3(grid), dim3(256),
+                   0, st, a);
+      break;
+    default:
+      launch_timed(e0, e1, k_read_apply2<K, 256, S, GL, KPL, U, kOpPredecessor>, dim3(grid),
+                   dim3(256), 0, st, a);
+      break;
+  }
 }
 
 // U buckets in a lane group's registers at a time.
@@ -83,13 +100,20 @@ void launch_group(u32 gl, u32 cap, const GroupArgs<K>& ga, const ReadArgs<K>& a,
   }
 }
 
+// The library builds this file once per key width (FLIX_READ_KEY_BITS = 32 or
+// 64), so the two halves of the read kernels compile in parallel.
+#if FLIX_READ_KEY_BITS == 32
 template void launch_read2<u32>(u32, u32, const ReadArgs<u32>&, int, u32, hipStream_t, hipEvent_t,
-                                hipEvent_t);
-template void launch_read2<u64>(u32, u32, const ReadArgs<u64>&, int, u32, hipStream_t, hipEvent_t,
                                 hipEvent_t);
 template void launch_group<u32>(u32, u32, const GroupArgs<u32>&, const ReadArgs<u32>&, int, u32,
                                 hipStream_t, hipEvent_t, hipEvent_t);
+#elif FLIX_READ_KEY_BITS == 64
+template void launch_read2<u64>(u32, u32, const ReadArgs<u64>&, int, u32, hipStream_t, hipEvent_t,
+                                hipEvent_t);
 template void launch_group<u64>(u32, u32, const GroupArgs<u64>&, const ReadArgs<u64>&, int, u32,
                                 hipStream_t, hipEvent_t, hipEvent_t);
+#else
+#error "FLIX_READ_KEY_BITS must be 32 or 64"
+#endif
 
 }  // namespace flix
