@@ -321,8 +321,8 @@ def update_heavy_rounds(args):
     rounds of 2^20 inserts of new keys then 2^20 deletes of present keys,
     uniform (even rounds) and clustered into 64 runs (odd rounds); every call
     timed with events.  The rounds run twice on fresh stores: as they come,
-    and with a restructuring after every clustered round (the paper's knob
-    against the long chains the dense runs leave), timed on its own.
+    and with a restructuring after every clustered insert batch (the paper's
+    knob against the long chains the dense runs leave), timed on its own.
     Algorithmic bytes per op follow the byte model of the update kernels."""
     import torch
     from paper_2604_16725_amd import flix
@@ -350,9 +350,9 @@ def update_heavy_rounds(args):
         rs = []
         for r, (di, dv, dd) in enumerate(rounds):
             kind = "uniform" if r % 2 == 0 else "clustered"
-            for name, fn, fams in (("insert", lambda: st.insert(di, dv),
-                                    ("insert_apply", "insert_wide")),
-                                   ("delete", lambda: st.delete(dd), ("delete_apply",))):
+            steps = [("insert", lambda: st.insert(di, dv), ("insert_apply", "insert_wide")),
+                     ("delete", lambda: st.delete(dd), ("delete_apply",))]
+            for name, fn, fams in steps:
                 st.set_timing(True)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 torch.cuda.synchronize()
@@ -364,11 +364,13 @@ def update_heavy_rounds(args):
                 st.set_timing(False)
                 rows[kind][name].append(a.elapsed_time(b))
                 kern[kind][name].append(kms)
-            if restructure and kind == "clustered":
-                torch.cuda.synchronize()
-                t1 = time.perf_counter()
-                before, after = st.restructure()
-                rs.append(((time.perf_counter() - t1) * 1e3, before, after))
+                if restructure and kind == "clustered" and name == "insert":
+                    # the dense runs became long chains: flatten them before
+                    # the deletes and the next rounds walk them
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    before, after = st.restructure()
+                    rs.append(((time.perf_counter() - t1) * 1e3, before, after))
             if st.status() != 0:
                 raise RuntimeError(f"device error in update round {r}")
         stt = st.stats()
@@ -409,7 +411,7 @@ def update_heavy_rounds(args):
                        f"into 64 runs",
            "alg_bytes_per_op_model_uniform": {"insert": ins_b, "delete": del_b},
            "rounds_as_they_come": plain,
-           "restructure_after_clustered_rounds": with_rs}
+           "restructure_after_clustered_inserts": with_rs}
     log(f"[bench] update heavy ({time.time() - t0:.0f}s): {out}")
     return out
 

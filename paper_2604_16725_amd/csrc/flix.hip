@@ -108,7 +108,7 @@ struct flix_store {
   // scratch
   void* bk[2] = {nullptr, nullptr};   // sort keys ping-pong [max_batch]
   void* bp[2] = {nullptr, nullptr};   // sort payload ping-pong [max_batch] (8-byte slots)
-  WorkItem* work = nullptr;           // [work_slots(max_batch)]
+  WorkItem* work = nullptr;           // [work_slots(max_batch) + wide_slots(max_batch)]
   SortScratch ss;
   Timing tm;
   // persistent drain: its own look-back words, histogram slots and control
@@ -575,6 +575,17 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   sa.work = s->work;
   sa.rcap = work_region_cap(s->max_batch);
   sa.ctl = s->ctl;
+  // a long slice into a single-node bucket (a dense run of new keys) is merged
+  // by a whole workgroup: the slice kernel lists those items
+  const bool wide = insert && !m_dev &&
+                    (s->cfg.insert_algo == FLIX_INSERT_TL_BULK ||
+                     s->cfg.insert_algo == FLIX_INSERT_ADAPTIVE) &&
+                    n >= wide_min_keys(s->cap);
+  if (wide) {
+    sa.wide_min = wide_min_keys(s->cap);
+    sa.wide_cap = wide_slots(s->max_batch);
+    sa.wide = s->work + work_slots(s->max_batch);
+  }
   constexpr int SS = SliceCfg<K>::S;
   u64 grid = ((u64)n + s->nb + sa.share - 1) / sa.share;
   TmTok t = tm_arm(s, F_PRE);
@@ -617,18 +628,17 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   // insert kernel choice: the single-lane kernel takes the items its selector
   // names, the lane-group kernel the complement
   u32 algo = (insert && !m_dev) ? s->cfg.insert_algo : (u32)FLIX_INSERT_TL_BULK;
-  // a long slice into a single-node bucket (a dense run of new keys) is merged
-  // by a whole workgroup; the lane-group kernel skips those items
-  if (insert && !m_dev && (algo == FLIX_INSERT_TL_BULK || algo == FLIX_INSERT_ADAPTIVE)) {
-    const u32 wmin = wide_min_keys(s->cap);
-    if (n >= wmin) {
-      ua.wide_min = wmin;
-      const u32 grid = (u32)std::min<u64>(2048, std::max<u64>(1, (items + 255) / 256));
-      const TmTok tw = tm_arm(s, F_INSERT_WIDE);
-      launch_timed(tw.b, tw.e, k_insert_wide<K, 256>, dim3(grid), dim3(256), 0, st, ua);
-      tm_done(s, F_INSERT_WIDE, tw);
-      HIP_TRY(hipGetLastError());
-    }
+  // the listed long slices go to the workgroup-wide kernel; the lane-group
+  // kernel skips them
+  if (wide) {
+    ua.wide_min = sa.wide_min;
+    ua.wide_cap = sa.wide_cap;
+    ua.wide = sa.wide;
+    const u32 grid = (u32)std::min<u64>(1024, n / sa.wide_min + 1);
+    const TmTok tw = tm_arm(s, F_INSERT_WIDE);
+    launch_timed(tw.b, tw.e, k_insert_wide<K, 256>, dim3(grid), dim3(256), 0, st, ua);
+    tm_done(s, F_INSERT_WIDE, tw);
+    HIP_TRY(hipGetLastError());
   }
   if (algo == FLIX_INSERT_ADAPTIVE && adaptive_st_max(s->cap) == 0) algo = FLIX_INSERT_TL_BULK;
   if (algo != FLIX_INSERT_TL_BULK) {
@@ -1222,7 +1232,7 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   u64 mb = cfg->max_batch;
   if ((rc = dev_alloc(&s->ctl, sizeof(Ctl))) || (rc = dev_alloc(&s->bk[0], mb * s->ksz)) ||
       (rc = dev_alloc(&s->bk[1], mb * s->ksz)) || (rc = dev_alloc(&s->bp[0], mb * 8)) ||
-      (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, work_slots(mb) * sizeof(WorkItem))) ||
+      (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, ((u64)work_slots(mb) + wide_slots(mb)) * sizeof(WorkItem))) ||
       (rc = dev_alloc(&s->ss.hist, 2 * 2048 * sizeof(u32))) ||
       (rc = dev_alloc(&s->ss.tile_ctr, 64)) || (rc = dev_alloc(&s->ss.err, 16)) ||
       (rc = dev_alloc(&s->split, (u64)kGroupMax * s->ksz)) ||

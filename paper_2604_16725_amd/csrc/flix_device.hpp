@@ -41,7 +41,7 @@ struct alignas(128) Ctl {
   u64 nkeys;           // number of live keys in the store
   u32 free_snapshot;   // free_top as seen before the current apply kernel
   u32 work_ovf;        // work items in the overflow region of the work list
-  u32 pad1;
+  u32 wide_n;          // items on the list of the workgroup-wide insert kernel
   u32 scan_total;      // output of device-wide compaction scans
   // per region: [0] items claimed, [1] first claim that did not fit (all
   // ones: none), so the region holds min([0], [1]) items
@@ -64,8 +64,15 @@ __device__ __forceinline__ void reset_work_regions(Ctl* ctl, u32 t) {
     ctl->wreg[t][0] = 0;
     ctl->wreg[t][1] = 0xFFFFFFFFu;
   }
-  if (t == 0) ctl->work_ovf = 0;
+  if (t == 0) {
+    ctl->work_ovf = 0;
+    ctl->wide_n = 0;
+  }
 }
+
+// Slots of the workgroup-wide insert list, after the work list: every item on
+// it holds at least 256 batch keys, and slices are disjoint.
+__host__ __device__ inline u32 wide_slots(u64 max_batch) { return (u32)(max_batch / 256 + 1); }
 
 // Work-list map of an apply workgroup: s_pre[r] = items in regions < r
 // (kWorkRegions + 1 entries).  All threads call; returns the item count.

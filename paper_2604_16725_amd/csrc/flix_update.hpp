@@ -43,6 +43,10 @@ struct SliceArgs {
   WorkItem* work;   // [work_slots(max_batch)]
   u32 rcap;         // work_region_cap(max_batch)
   Ctl* ctl;
+  u32 wide_min = 0; // > 0: single-node items with at least this many keys are
+                    // also listed for the workgroup-wide insert kernel
+  u32 wide_cap = 0;
+  WorkItem* wide = nullptr;   // [wide_cap]
 };
 
 template <typename K, int S, int NT>
@@ -261,6 +265,11 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
         it.e = e;
         it.head = info[r];
         a.work[w++] = it;
+        if (a.wide_min && (it.head & kSingleNode) && e - s >= a.wide_min) {
+          const u32 k = atomicAdd(&a.ctl->wide_n, 1u);
+          if (k < a.wide_cap) a.wide[k] = it;
+          else atomicCAS(&a.ctl->status, 0u, kErrInternal);   // bound violated: never expected
+        }
       }
     }
   }
@@ -394,6 +403,8 @@ struct UpdArgs {
   u32 st_max = 0;     // slice-length threshold of the kernel choice
   u32 wide_min = 0;   // > 0: single-node buckets with at least this many batch
                       // keys belong to the workgroup-wide insert kernel
+  u32 wide_cap = 0;
+  const WorkItem* wide = nullptr;   // those items, listed by the slice kernel
 };
 
 // Work items of the workgroup-wide insert kernel (k_insert_wide).
@@ -930,8 +941,6 @@ struct WideLds {
   u32 qinc[257];            // inclusive prefix of cnt
   u32 dropx[257];           // exclusive prefix of eq
   u32 tmp[8];
-  u32 list[256];            // wide items found in the current window
-  u32 nlist;
   u32 live_total, match_total;
   u32 base_id;
   u32 bad;
@@ -1088,35 +1097,17 @@ __device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideL
   __syncthreads();   // LDS is reused by the next item
 }
 
-// Every workgroup scans its windows of the work list for wide items and
-// merges each of them with all its threads.
+// The slice kernel lists the wide items; workgroup g merges items g, g + G, ...
 template <typename K, int NT>
 __global__ __launch_bounds__(NT) void k_insert_wide(UpdArgs<K> a) {
-  __shared__ UpdShared sh;
   __shared__ WideLds<K> L;
   const Ctl* ctl = a.ctl;
   if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot) return;   // the other kernels report it
-  const u32 nitems = load_work_map(ctl, sh.pre);
+  const u32 n = ctl->wide_n < a.wide_cap ? ctl->wide_n : a.wide_cap;
   unsigned long long added = 0;
-  for (u32 base = blockIdx.x * NT; base < nitems; base += gridDim.x * NT) {
-    if (threadIdx.x == 0) L.nlist = 0;
-    __syncthreads();
-    const u32 it = base + threadIdx.x;
-    if (it < nitems) {
-      WorkCursor cur;
-      cur.seek(sh.pre, it);
-      const WorkItem w = a.work[cur.slot(it, a.rcap)];
-      if (is_wide(a.wide_min, w)) L.list[atomicAdd(&L.nlist, 1u)] = it;
-    }
-    __syncthreads();
-    const u32 nl = L.nlist;
-    for (u32 q = 0; q < nl; ++q) {
-      const u32 it2 = L.list[q];
-      WorkCursor cur;
-      cur.seek(sh.pre, it2);
-      const WorkItem w = a.work[cur.slot(it2, a.rcap)];
-      wide_insert_bucket<K, NT>(a, w, L, added);
-    }
+  for (u32 i = blockIdx.x; i < n; i += gridDim.x) {
+    const WorkItem w = a.wide[i];
+    wide_insert_bucket<K, NT>(a, w, L, added);
   }
   if (threadIdx.x == 0 && added) atomicAdd((unsigned long long*)&a.ctl->nkeys, added);
 }
