@@ -305,12 +305,27 @@ int sort_batch_t(flix_store* s, const K* keys, const K* vals, u32 n, int pay, hi
 
 // Per-call counters are cleared by a one-block kernel at the start of every
 // update call (they are read by the kernels that follow on the stream).
-__global__ void k_reset_call(Ctl* ctl) {
+__global__ void k_reset_call(Ctl* ctl, u32 clear_abort) {
   if (threadIdx.x == 0) {
     ctl->need = 0;
     ctl->call_err = 0;
+    if (clear_abort) ctl->call_abort = 0;
   }
   reset_work_regions(ctl, threadIdx.x);
+}
+
+// Epoch gate: the node bound of the epoch's upserts, summed on the store as
+// it is before the epoch's deletes, decides for the whole update list.  The
+// deletes only shrink buckets and chains and return nodes, so a list that
+// passes here also passes the insert kernel's own check after the deletes;
+// a list that fails is rejected before any node changes.
+__global__ void k_epoch_gate(Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    const u32 err = ctl->call_err;
+    const bool abort = err != 0 || ctl->need > (u64)ctl->free_top;
+    ctl->call_abort = abort ? 1u : 0u;
+    if (abort) atomicCAS(&ctl->status, 0u, err != 0 ? err : kErrNomem);
+  }
 }
 
 void sort_hook_begin(void* ctx, int fam, hipEvent_t* e0, hipEvent_t* e1) {
@@ -669,10 +684,35 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   return FLIX_OK;
 }
 
+// The insert slice kernel alone, for a device-counted list (the epoch gate's
+// node bound on the store before the epoch's deletes).
+template <typename K>
+int update_slices_only(flix_store* s, const K* skeys, const K* svals, u64 n, const u32* m_dev,
+                       hipStream_t st) {
+  SliceArgs<K> sa;
+  sa.skeys = skeys;
+  sa.svals = svals;
+  sa.m = (u32)n;
+  sa.mkba = (const K*)s->mkba;
+  sa.nb = s->nb;
+  sa.hdr = s->hdr;
+  sa.bnodes = s->bnodes;
+  sa.cap = s->cap;
+  sa.share = SliceCfg<K>::S;
+  sa.work = s->work;
+  sa.rcap = work_region_cap(s->max_batch);
+  sa.ctl = s->ctl;
+  constexpr int SS = SliceCfg<K>::S;
+  const u64 grid = ((u64)n + s->nb + sa.share - 1) / sa.share;
+  hipLaunchKernelGGL((k_slices_counted<K, 256, SS, true>), dim3(grid), dim3(256), 0, st, sa, m_dev);
+  HIP_TRY(hipGetLastError());
+  return FLIX_OK;
+}
+
 template <typename K>
 int update_batch(flix_store* s, bool insert, const void* keys, const void* vals, u64 n,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl);
+  hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl, 1u);
   int r;
   int rc = sort_batch<K>(s, keys, vals, n, insert ? kPayValue : kPayNone, st, &r);
   if (rc) return rc;
@@ -796,12 +836,19 @@ int epoch_apply_t(flix_store* s, EpochSlot* es, const flix_epoch* e, hipStream_t
     return rc;
   if (e->n_update) {
     // the folded lists hold distinct keys, so deletes and upserts commute;
-    // deletes go first and return nodes to the free list
-    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl);
+    // deletes go first and return nodes to the free list.  The upserts' node
+    // bound is checked first, on the store before the deletes, so a rejected
+    // epoch leaves the store unchanged.
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl, 1u);
+    if ((rc = update_slices_only<K>(s, (const K*)es->ins_k, (const K*)es->ins_v, e->n_update,
+                                    es->counts, st)))
+      return rc;
+    hipLaunchKernelGGL(k_epoch_gate, dim3(1), dim3(64), 0, st, s->ctl);
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl, 0u);
     if ((rc = update_apply_sorted<K>(s, false, (const K*)es->del_k, nullptr, e->n_update,
                                      es->counts + 1, st)))
       return rc;
-    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl);
+    hipLaunchKernelGGL(k_reset_call, dim3(1), dim3(kWorkRegions), 0, st, s->ctl, 0u);
     if ((rc = update_apply_sorted<K>(s, true, (const K*)es->ins_k, (const K*)es->ins_v,
                                      e->n_update, es->counts, st)))
       return rc;

@@ -132,6 +132,7 @@ __global__ void k_build_free(u32 nb, u32 pool, u64 nkeys, u32* __restrict__ free
     ctl->nkeys = nkeys;
     ctl->need = 0;
     ctl->call_err = 0;
+    ctl->call_abort = 0;
     ctl->work_ovf = 0;
   }
 }

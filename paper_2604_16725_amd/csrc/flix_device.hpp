@@ -36,7 +36,8 @@ struct alignas(128) Ctl {
   u32 free_top;        // number of node ids on the free stack
   u32 status;          // sticky first device-detected error (negative code)
   u32 call_err;        // error raised by the pre-check of the current call
-  u32 pad0;
+  u32 call_abort;      // an epoch's updates were rejected as a whole: its
+                       // delete and insert kernels change nothing
   u64 need;            // pre-check: upper bound of nodes the call may take
   u64 nkeys;           // number of live keys in the store
   u32 free_snapshot;   // free_top as seen before the current apply kernel

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       if (threadIdx.x == 0) {
         a.ctl->need = 0;
         a.ctl->call_err = 0;
+        a.ctl->call_abort = 0;
       }
       reset_work_regions(a.ctl, threadIdx.x);
     }

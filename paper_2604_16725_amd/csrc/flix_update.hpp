@@ -469,7 +469,7 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
   if (threadIdx.x == 0) s_added = 0;
   __syncthreads();
   const Ctl* ctl = a.ctl;
-  bool abort_all = ctl->call_err != 0 || ctl->need > ctl->free_snapshot;
+  bool abort_all = ctl->call_err != 0 || ctl->need > ctl->free_snapshot || ctl->call_abort != 0;
   if (abort_all) {
     if (blk == 0 && threadIdx.x == 0 && ctl->call_err == 0)
       atomicCAS(a.status, 0u, kErrNomem);
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(NT) void k_insert_st(UpdArgs<K> a) {
   if (threadIdx.x == 0) sh.counter = 0;
   __syncthreads();
   const Ctl* ctl = a.ctl;
-  if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot) {
+  if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot || ctl->call_abort != 0) {
     if (blockIdx.x == 0 && threadIdx.x == 0)
       atomicCAS(a.status, 0u, ctl->call_err != 0 ? ctl->call_err : kErrNomem);
     return;
@@ -1102,7 +1102,8 @@ template <typename K, int NT>
 __global__ __launch_bounds__(NT) void k_insert_wide(UpdArgs<K> a) {
   __shared__ WideLds<K> L;
   const Ctl* ctl = a.ctl;
-  if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot) return;   // the other kernels report it
+  if (ctl->call_err != 0 || ctl->need > ctl->free_snapshot || ctl->call_abort != 0)
+    return;   // the other kernels report it
   const u32 n = ctl->wide_n < a.wide_cap ? ctl->wide_n : a.wide_cap;
   unsigned long long added = 0;
   for (u32 i = blockIdx.x; i < n; i += gridDim.x) {
@@ -1134,6 +1135,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
   K* bk = ak + a.cap;                                                   // slice keys [chunk]
   if (threadIdx.x == 0) s_removed = 0;
   __syncthreads();
+  if (a.ctl->call_abort != 0) return;   // an epoch rejected as a whole (uniform)
   const u32 nitems = load_work_map(a.ctl, sh.pre);
   const u32 f = a.cap / 2;
   u64 removed = 0;

@@ -181,3 +181,52 @@ def test_probe_requests_same_alone_and_in_mix():
             got = mix.range_vals[ep.range_ord]
             assert np.array_equal(got[m], rv.reshape(-1, RM)[m]), f"probe {i} values"
     st.close()
+
+
+def test_epoch_rejected_for_nodes_changes_nothing():
+    """An epoch whose upserts could run the node pool dry is rejected as a
+    whole before any change: its deletes are not applied either (the bound is
+    checked on the store before the deletes).  A following epoch that fits is
+    applied normally."""
+    import torch
+    from oracle.oracle import Oracle
+    from paper_2604_16725_amd.flix import FLIX_ENOMEM, Store
+    kb = 32
+    cap = 16
+    node_bytes = 16 + 2 * cap * 4
+    st = Store(key_bits=kb, capacity=cap, max_batch=1 << 13, pool_bytes=node_bytes * 120)
+    o = Oracle(kb)
+    base = np.arange(1, 1 + 100 * 8, dtype=np.uint32) * np.uint32(1000)
+    st.bulk_load(to_dev(base), to_dev(base))
+    o.bulk_load(base, base)
+    before_k, before_v = st.dump()
+    # deletes of present keys plus a dense run of new keys into one bucket
+    dele = base[::3]
+    run = np.arange(5, 5 + 3000, dtype=np.uint32)
+    uk = np.concatenate([dele, run])
+    uv = np.concatenate([np.full(dele.size, 0xFFFFFFFF, dtype=np.uint32), run])
+    lk = base[:50].copy()
+    d_uk, d_uv, d_lk = to_dev(uk), to_dev(uv), to_dev(lk)
+    out_v = torch.zeros(lk.size, dtype=st.dtype, device="cuda")
+    ep = st.make_epoch(lookup_keys=d_lk, lookup_vals=out_v, n_lookup=lk.size,
+                       update_keys=d_uk, update_vals=d_uv, n_update=uk.size)
+    st.epoch_prepare(0, ep)
+    st.epoch_apply(0, ep)
+    torch.cuda.synchronize()
+    assert st.status() == FLIX_ENOMEM
+    # the reads of the epoch ran on the unchanged store
+    assert np.array_equal(to_host(out_v, kb), o.lookup(lk))
+    ak, av = st.dump()
+    assert torch.equal(ak, before_k) and torch.equal(av, before_v), "a rejected epoch changed the store"
+    assert_same_contents(st, o, kb, "after the rejected epoch")
+    # a small epoch still applies
+    uk2 = np.concatenate([base[:10], np.array([7, 8, 9], dtype=np.uint32)])
+    uv2 = np.concatenate([np.full(10, 0xFFFFFFFF, dtype=np.uint32), np.array([70, 80, 90], dtype=np.uint32)])
+    ep2 = st.make_epoch(update_keys=to_dev(uk2), update_vals=to_dev(uv2), n_update=uk2.size)
+    st.epoch_prepare(1, ep2)
+    st.epoch_apply(1, ep2)
+    torch.cuda.synchronize()
+    assert st.status() == 0
+    o.apply_epoch(np.zeros(0, np.uint32), np.zeros(0, np.uint32), np.zeros(0, np.uint32), 0, uk2, uv2)
+    assert_same_contents(st, o, kb, "after a fitting epoch")
+    st.close()
