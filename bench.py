@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--nbatch", type=int, default=4096, help="batches in the mixed stream")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving comparison (request loop vs plain per-request form)")
-    ap.add_argument("--serve-requests", type=int, default=2000, help="requests per arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="requests per arrival rate")
     ap.add_argument("--serve-keys-log2", type=int, default=25)
     ap.add_argument("--no-grown", action="store_true",
                     help="skip the reads on a store grown by +100% and restructured")
@@ -347,11 +347,15 @@ def update_heavy_rounds(args):
                 "clustered": {"insert": [], "delete": []}}
         kern = {"uniform": {"insert": [], "delete": []},
                 "clustered": {"insert": [], "delete": []}}
+        fams_ms = {"uniform": {"insert": [], "delete": []},
+                   "clustered": {"insert": [], "delete": []}}
         rs = []
         for r, (di, dv, dd) in enumerate(rounds):
             kind = "uniform" if r % 2 == 0 else "clustered"
             steps = [("insert", lambda: st.insert(di, dv), ("insert_apply", "insert_wide")),
                      ("delete", lambda: st.delete(dd), ("delete_apply",))]
+            fam_all = ("sort_hist", "sort_pass", "sort_local", "slices", "insert_apply",
+                       "insert_wide", "delete_apply")
             for name, fn, fams in steps:
                 st.set_timing(True)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -361,9 +365,11 @@ def update_heavy_rounds(args):
                 b.record()
                 torch.cuda.synchronize()
                 kms = sum(st.kernel_time(f)[0] for f in fams)
+                per_fam = {f: st.kernel_time(f)[0] for f in fam_all}
                 st.set_timing(False)
                 rows[kind][name].append(a.elapsed_time(b))
                 kern[kind][name].append(kms)
+                fams_ms[kind][name].append(per_fam)
                 if restructure and kind == "clustered" and name == "insert":
                     # the dense runs became long chains: flatten them before
                     # the deletes and the next rounds walk them
@@ -385,7 +391,11 @@ def update_heavy_rounds(args):
                 d[name] = {"Mops_s_median": round(m / (np.median(ms) / 1000) / 1e6, 1),
                            "ms_median": round(float(np.median(ms)), 4),
                            "ms_max": round(float(ms.max()), 4), "rounds": int(ms.size),
-                           "apply_kernels_ms_median": round(float(np.median(kern[kind][name])), 4)}
+                           "ms_per_round": [round(float(x), 3) for x in ms],
+                           "apply_kernels_ms_median": round(float(np.median(kern[kind][name])), 4),
+                           "kernel_ms_median": {f: round(float(np.median([p[f] for p in fams_ms[kind][name]])), 4)
+                                                for f in fams_ms[kind][name][0]
+                                                if any(p[f] for p in fams_ms[kind][name])}}
             if d:
                 res[kind] = d
         if rs:

@@ -289,8 +289,11 @@ int flix_drain_info(flix_store* s, uint32_t* grid_blocks, uint64_t* timestamp_hz
  * owned by the caller and must stay valid until the apply completes.
  * Errors: EINVAL for a slot >= FLIX_EPOCH_SLOTS, counts above max_batch,
  * null buffers with a non-zero count, reserved != 0.  Device-detected
- * ENOMEM cancels the epoch's upserts (its deletes have been applied) and
- * sets the sticky status.  The first call allocates the slots' scratch. */
+ * ENOMEM (an upper bound of the nodes the upserts may take, summed on the
+ * store before the epoch's deletes, exceeds the free nodes) cancels the
+ * epoch's updates as a whole, deletes included, and sets the sticky status;
+ * the epoch's reads are answered.  The first call allocates the slots'
+ * scratch. */
 #define FLIX_EPOCH_SLOTS 2
 typedef struct {
   uint64_t n_lookup;

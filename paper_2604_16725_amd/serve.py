@@ -34,9 +34,15 @@ class EpochLists:
 
     def __init__(self, wl, req_ids, tomb):
         self.req_ids = list(req_ids)
-        sl = [slice(int(wl.offsets[i]), int(wl.offsets[i + 1])) for i in self.req_ids]
-        idx = np.concatenate([np.arange(s.start, s.stop) for s in sl]) if sl else \
-            np.zeros(0, dtype=np.int64)
+        ids = np.asarray(self.req_ids, dtype=np.int64)
+        # operation indices of the requests, in admitted order, without a
+        # Python loop over requests: each request's run of indices is its
+        # start plus a ramp that restarts at every request
+        starts = wl.offsets[ids].astype(np.int64)
+        lens = wl.offsets[ids + 1].astype(np.int64) - starts
+        total = int(lens.sum())
+        ramp = np.arange(total, dtype=np.int64)
+        idx = np.repeat(starts - (np.cumsum(lens) - lens), lens) + ramp
         ops, keys, aux = wl.ops[idx], wl.keys[idx], wl.aux[idx]
         is_l, is_r = ops == LOOKUP, ops == RANGE
         is_u = ops >= INSERT
@@ -52,6 +58,16 @@ class EpochLists:
     @property
     def counts(self):
         return self.lookup_keys.size, self.range_lo.size, self.update_keys.size
+
+
+def request_bytes_all(wl, key_bytes, range_max):
+    """request_bytes of every request at once (one pass over the operations)."""
+    n = wl.n_req
+    sizes = np.diff(wl.offsets).astype(np.int64)
+    req = np.repeat(np.arange(n), sizes)
+    nl = np.bincount(req, weights=(wl.ops == LOOKUP), minlength=n).astype(np.int64)
+    nr = np.bincount(req, weights=(wl.ops == RANGE), minlength=n).astype(np.int64)
+    return sizes * 2 * key_bytes + nl * key_bytes + nr * (4 + range_max * key_bytes)
 
 
 def request_bytes(wl, i, key_bytes, range_max):
@@ -99,8 +115,7 @@ class Engine:
         n = wl.n_req
         res = Results(wl, range_max, wl.keys.dtype)
         done_at = np.full(n, np.nan)
-        rbytes = np.array([request_bytes(wl, i, key_bytes, range_max) for i in range(n)],
-                          dtype=np.int64)
+        rbytes = request_bytes_all(wl, key_bytes, range_max)
         queue = collections.deque()
         inflight = {}              # slot -> (handle, EpochLists, bytes)
         next_slot = 0

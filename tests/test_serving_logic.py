@@ -75,6 +75,7 @@ def test_high_rate_coalesces_more():
 def test_budget_and_capacity_admission():
     wl = _wl(n_req=160)
     rb = np.array([serve.request_bytes(wl, i, 8, RM) for i in range(wl.n_req)])
+    assert np.array_equal(serve.request_bytes_all(wl, 8, RM), rb)
     budget = int(np.sort(rb)[-3])                    # the 2 largest requests never fit
     be = FakeBackend(_oracle(wl), RM)
     run = serve.Engine(be, max_epoch_ops=600, budget=budget).run(wl, wl.arrivals(1e5), TOMB, 8,
@@ -124,3 +125,18 @@ def test_probe_results_same_alone_and_in_mix():
         assert np.array_equal(mix.lookup[ep.flat_lookup], lv)
         if ep.range_ord.size:
             assert np.array_equal(mix.range_count[ep.range_ord], rc)
+
+
+def test_epoch_lists_match_per_request_slices():
+    """The vectorised index construction equals concatenating each request's
+    own slice of operations, in admitted order (empty lists included)."""
+    wl = _wl(n_req=300)
+    rng = np.random.default_rng(5)
+    for ids in ([], [7], [3, 1, 2], list(rng.permutation(wl.n_req)[:120])):
+        ep = serve.EpochLists(wl, ids, TOMB)
+        ref = (np.concatenate([np.arange(wl.offsets[i], wl.offsets[i + 1]) for i in ids])
+               if ids else np.zeros(0, dtype=np.int64))
+        is_l = wl.ops[ref] == serve.LOOKUP
+        assert np.array_equal(ep.flat_lookup, ref[is_l])
+        assert ep.n_ops == ref.size
+        assert np.array_equal(ep.lookup_keys, wl.keys[ref][is_l])
