@@ -787,6 +787,24 @@ def main():
         timeit("zipf_lookup", lambda: st.lookup(zl, out=ol), m)
         timeit("zipf_successor", lambda: st.successor(zs, out_k=sk, out_v=sv), m)
         timeit("zipf_range16", lambda: st.range(zlo, zhi, L, counts=rc, out_k=rk, out_v=rv), m)
+        # dense ranges (an extra beside the workload's 16-key intervals, which
+        # hold 0.25 keys on average): 2^16 ranges of 2^16 consecutive key
+        # values, about 1024 stored keys each, all returned
+        nd, Ld = 1 << 16, 1024
+        dlo_np = np.random.default_rng(0xF11CD).integers(0, (1 << 32) - (1 << 16), nd,
+                                                           dtype=np.uint64)
+        ddlo = dev(dlo_np.astype(np.uint32))
+        ddhi = dev((dlo_np + (1 << 16) - 1).astype(np.uint32))
+        drc = torch.empty(nd, dtype=torch.int32, device="cuda")
+        drk = torch.empty(nd * Ld, dtype=torch.int32, device="cuda")
+        drv = torch.empty(nd * Ld, dtype=torch.int32, device="cuda")
+        timeit("range_dense_1024", lambda: st.range(ddlo, ddhi, Ld, counts=drc, out_k=drk,
+                                                    out_v=drv), nd)
+        res_n = int(drc.to(torch.int64).sum().item())
+        breakdown["range_dense_1024"]["results_per_range"] = round(res_n / nd, 1)
+        breakdown["range_dense_1024"]["Mresults_s"] = round(
+            res_n / (breakdown["range_dense_1024"]["p50_ms"] / 1000) / 1e6, 1)
+        del drk, drv
         if st.status() != 0:
             raise RuntimeError("device error during breakdown")
 

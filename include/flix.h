@@ -160,6 +160,20 @@ int flix_range(flix_store* s, const void* d_lo, const void* d_hi, uint64_t n,
  * FLIX_ENOMEM, nothing changed.  Synchronizes; the store must be idle. */
 int flix_restructure(flix_store* s, uint64_t* nodes_before, uint64_t* nodes_after, void* stream);
 
+/* Optional device-memory allocator hook: every device buffer the library
+ * allocates afterwards (directory, node pool, scratch, the temporaries of
+ * bulk load, dump, check and restructure) comes from alloc(bytes, ctx) and
+ * goes back through free(ptr, ctx) instead of hipMalloc / hipFree, so a
+ * framework's caching allocator can back a store.  alloc returns NULL on
+ * failure (-> FLIX_ENOMEM).  The library frees a buffer only when no work of
+ * its own on the store's stream still uses it (after a synchronisation).
+ * Process-wide: set it before creating stores, and destroy a store while the
+ * hook it was created under is still set.  (NULL, NULL) restores hipMalloc /
+ * hipFree; exactly one NULL -> FLIX_EINVAL. */
+typedef void* (*flix_alloc_fn)(uint64_t bytes, void* ctx);
+typedef void (*flix_free_fn)(void* ptr, void* ctx);
+int flix_set_allocator(flix_alloc_fn alloc, flix_free_fn free, void* ctx);
+
 /* Free every resource of the store (Section 3.2 lists what a store holds: the
  * maxBucket directory and the node pool; here also the scratch).
  * Synchronizes with the device. */

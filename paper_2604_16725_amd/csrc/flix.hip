@@ -181,10 +181,29 @@ void tm_collect(flix_store* s) {
 }
 
 // ---- allocation -------------------------------------------------------------
+// Optional allocator hook (flix_set_allocator): device buffers come from it
+// instead of hipMalloc / hipFree.
+struct AllocHook {
+  flix_alloc_fn alloc = nullptr;
+  flix_free_fn free = nullptr;
+  void* ctx = nullptr;
+};
+AllocHook g_alloc;
+
 template <typename T>
 int dev_alloc(T** p, u64 bytes) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (g_alloc.alloc) {
+    void* q = g_alloc.alloc(bytes, g_alloc.ctx);
+    if (!q) {
+      std::snprintf(g_last_error, sizeof(g_last_error), "allocator hook failed for %llu bytes",
+                    (unsigned long long)bytes);
+      return FLIX_ENOMEM;
+    }
+    *p = static_cast<T*>(q);
+    return FLIX_OK;
+  }
   const hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -197,6 +216,13 @@ int dev_alloc(T** p, u64 bytes) {
 }
 template <typename T>
 void dev_free(T** p) {
+  if (*p && g_alloc.free) {
+    // hipFree waits for the device; a hook's free may not, so wait here
+    (void)hipDeviceSynchronize();
+    g_alloc.free(static_cast<void*>(*p), g_alloc.ctx);
+    *p = nullptr;
+    return;
+  }
   if (*p) (void)hipFree(*p);
   *p = nullptr;
 }
@@ -1337,6 +1363,14 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
     return rc;
   }
   *out = s;
+  return FLIX_OK;
+}
+
+int flix_set_allocator(flix_alloc_fn alloc, flix_free_fn free, void* ctx) {
+  if ((alloc == nullptr) != (free == nullptr)) return FLIX_EINVAL;
+  g_alloc.alloc = alloc;
+  g_alloc.free = free;
+  g_alloc.ctx = ctx;
   return FLIX_OK;
 }
 

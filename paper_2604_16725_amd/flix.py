@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "flix_predecessor": (i32, [vp, vp, u64, vp, vp, vp]),
         "flix_range": (i32, [vp, vp, vp, u64, u32, vp, vp, vp, vp]),
         "flix_destroy": (i32, [vp]),
+        "flix_set_allocator": (i32, [vp, vp, vp]),
         "flix_restructure": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), vp]),
         "flix_size": (i32, [vp, ctypes.POINTER(u64), vp]),
         "flix_dump": (i32, [vp, vp, vp, u64, ctypes.POINTER(u64), vp]),
@@ -154,6 +155,43 @@ def load_library(path: str = LIB_PATH):
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_hook = None   # keeps the ctypes callbacks alive while they are installed
+
+
+def use_torch_allocator(enable: bool = True):
+    """Back every device buffer the library allocates afterwards with torch's
+    caching allocator (flix_set_allocator), or restore hipMalloc / hipFree.
+    Set it before creating stores; destroy stores created under it while it
+    is still set."""
+    global _hook
+    import torch
+    lib = load_library()
+    if not enable:
+        rc = lib.flix_set_allocator(None, None, None)
+        if rc != FLIX_OK:
+            raise FlixError(rc, "flix_set_allocator")
+        _hook = None
+        return
+
+    def _alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device())
+        except Exception:  # noqa: BLE001  (out of memory: the library reports ENOMEM)
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    hook = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    rc = lib.flix_set_allocator(ctypes.cast(hook[0], ctypes.c_void_p),
+                                ctypes.cast(hook[1], ctypes.c_void_p), None)
+    if rc != FLIX_OK:
+        raise FlixError(rc, "flix_set_allocator")
+    _hook = hook
 
 
 def _ptr(t):

@@ -523,3 +523,65 @@ def test_reads_across_long_runs_of_empty_buckets(kb):
     o.insert(back, vals[150000:150100])
     assert_same_contents(s, o, kb, "after refilling")
     check_reads(s, o, kb, q, maxpq=4, lo=lo, hi=hi, where="gap refilled")
+
+
+def test_torch_allocator_hook_backs_a_store():
+    """With the allocator hook set to torch's caching allocator, a store's
+    directory, pool and scratch come from torch (its allocated bytes grow by
+    at least the pool) and every operation still matches the oracle; after
+    destroy and reset, hipMalloc serves again."""
+    import torch
+    from paper_2604_16725_amd import flix
+    kb = 32
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    flix.use_torch_allocator(True)
+    try:
+        s, o = new_pair(kb, cap=32, max_batch=1 << 14)
+        rng = np.random.default_rng(12)
+        k = np.unique(_keys(rng, kb, 50000))
+        s.bulk_load(to_dev(k), to_dev(k))
+        o.bulk_load(k, k)
+        grown = torch.cuda.memory_allocated() - before
+        st = s.stats()
+        assert grown >= st["pool_nodes"] * (16 + 2 * 32 * 4), grown
+        ins = _keys(rng, kb, 10000)
+        s.insert(to_dev(ins), to_dev(ins))
+        o.insert(ins, ins)
+        s.delete(to_dev(k[:5000]))
+        o.delete(k[:5000])
+        assert_same_contents(s, o, kb, "torch-allocated store")
+        check_reads(s, o, kb, np.concatenate([ins[:3000], _keys(rng, kb, 3000)]), maxpq=4,
+                    where="torch-allocated store")
+        s.restructure()
+        assert_same_contents(s, o, kb, "torch-allocated store, restructured")
+        s.close()
+    finally:
+        flix.use_torch_allocator(False)
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before + (1 << 20)
+    s2, o2 = new_pair(kb, cap=32, max_batch=1 << 10)
+    s2.bulk_load(to_dev(k[:100]), to_dev(k[:100]))
+    o2.bulk_load(k[:100], k[:100])
+    assert_same_contents(s2, o2, kb, "after resetting the hook")
+    s2.close()
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_dense_ranges_every_result(kb):
+    """Ranges that hold hundreds of keys each, across many nodes and buckets
+    (after growth, so chains too), with room for every result: counts, keys
+    and values all bit-exact."""
+    rng = np.random.default_rng(900 + kb)
+    dt = ktype(kb)
+    s, o = new_pair(kb, cap=64, max_batch=1 << 16)
+    k = np.unique(_keys(rng, kb, 1 << 18))
+    s.bulk_load(to_dev(k), to_dev(k ^ dt(3)))
+    o.bulk_load(k, k ^ dt(3))
+    ins = _keys(rng, kb, 1 << 16)
+    s.insert(to_dev(ins), to_dev(ins))
+    o.insert(ins, ins)
+    width = np.uint64(((1 << kb) // (1 << 18)) * 300)
+    lo = _keys(rng, kb, 4000)
+    hi = np.minimum(lo.astype(np.uint64) + width, np.uint64((1 << kb) - 1)).astype(dt)
+    check_reads(s, o, kb, lo, maxpq=512, lo=lo, hi=hi, where="dense ranges")
