@@ -88,9 +88,9 @@ typedef struct {
  * Section 5.3.5 ST-TL-Mixed, Section 3.4 adaptive compute per bucket).  All
  * give the same contents; they differ in how lanes are assigned to buckets. */
 #define FLIX_INSERT_TL_BULK 0        /* a group of lanes_per_bucket lanes per bucket; a
-                                        single-node bucket receiving at least
-                                        max(4 * capacity, 256) batch keys (a dense run) is
-                                        merged by a whole workgroup */
+                                        bucket receiving at least max(4 * capacity, 256)
+                                        batch keys (a dense run) is merged by a whole
+                                        workgroup, node by node along its chain */
 #define FLIX_INSERT_ST_SHIFT_RIGHT 1 /* one lane per bucket, key by key */
 #define FLIX_INSERT_ST_TL_MIXED 2    /* per call: ST-Shift-Right when the call averages at
                                         most FLIX_ST_MAX_KEYS batch keys per touched

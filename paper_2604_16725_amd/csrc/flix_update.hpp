@@ -43,8 +43,8 @@ struct SliceArgs {
   WorkItem* work;   // [work_slots(max_batch)]
   u32 rcap;         // work_region_cap(max_batch)
   Ctl* ctl;
-  u32 wide_min = 0; // > 0: single-node items with at least this many keys are
-                    // also listed for the workgroup-wide insert kernel
+  u32 wide_min = 0; // > 0: items with at least this many keys are also
+                    // listed for the workgroup-wide insert kernel
   u32 wide_cap = 0;
   WorkItem* wide = nullptr;   // [wide_cap]
 };
@@ -265,7 +265,7 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
         it.e = e;
         it.head = info[r];
         a.work[w++] = it;
-        if (a.wide_min && (it.head & kSingleNode) && e - s >= a.wide_min) {
+        if (a.wide_min && e - s >= a.wide_min) {
           const u32 k = atomicAdd(&a.ctl->wide_n, 1u);
           if (k < a.wide_cap) a.wide[k] = it;
           else atomicCAS(&a.ctl->status, 0u, kErrInternal);   // bound violated: never expected
@@ -401,15 +401,15 @@ struct UpdArgs {
   OccLevels occ;      // bucket occupancy summary, kept current here
   u32 sel = 0;        // insert kernels: which work items this launch takes (kSel*)
   u32 st_max = 0;     // slice-length threshold of the kernel choice
-  u32 wide_min = 0;   // > 0: single-node buckets with at least this many batch
-                      // keys belong to the workgroup-wide insert kernel
+  u32 wide_min = 0;   // > 0: buckets with at least this many batch keys in
+                      // their slice belong to the workgroup-wide insert kernel
   u32 wide_cap = 0;
   const WorkItem* wide = nullptr;   // those items, listed by the slice kernel
 };
 
 // Work items of the workgroup-wide insert kernel (k_insert_wide).
 __device__ __forceinline__ bool is_wide(u32 wide_min, const WorkItem& w) {
-  return wide_min != 0 && (w.head & kSingleNode) && w.e - w.s >= wide_min;
+  return wide_min != 0 && w.e - w.s >= wide_min;
 }
 
 // Workgroup-shared state of the apply kernels: a key counter and the map of
@@ -915,11 +915,12 @@ __global__ __launch_bounds__(NT) void k_insert_st(UpdArgs<K> a) {
 
 // ---------------------------------------------------------------------------
 // Workgroup-wide insert (elastic compute for a hot bucket, Section 3.4): a
-// single-node bucket whose slice holds at least `wide_min` batch keys (a dense
-// run of new keys) is merged by a whole workgroup instead of one lane group
-// walking the slice in node-sized chunks.  The node's keys A[0, S) are staged
-// in LDS; every live slice key (last of its equal-key run) and every kept node
-// key gets its merged position from counts, so all of them are written in
+// bucket whose slice holds at least `wide_min` batch keys (a dense run of new
+// keys) is merged by a whole workgroup instead of one lane group walking the
+// slice in node-sized chunks.  Node by node along the chain, the node X whose
+// range holds the next slice keys is staged in LDS (keys A[0, S)); every live
+// slice key of its part (last of its equal-key run) and every kept node key
+// gets its merged position from counts, so all of them are written in
 // parallel:
 //   pos(live slice key k) = rank of k among live slice keys
 //                           + #{node keys < k} - #{dropped node keys < k}
@@ -928,10 +929,11 @@ __global__ __launch_bounds__(NT) void k_insert_st(UpdArgs<K> a) {
 // where a node key is dropped when a live slice key equals it (the batch pair
 // replaces it).  The c merged pairs form k = max(1, floor(c / (cap/2))) pieces
 // of near-equal size (the split rule of the lane-group kernel); pieces 1..k-1
-// come from the free list and are chained after the head, the last piece
-// keeps the bucket's maxBucket as its fence.  The node budget bound of the
-// slice kernel, floor((S + t) / (cap/2)) - 1 for a single-node bucket, covers
-// the k - 1 new nodes.
+// come from the free list and are chained after X, the last piece keeps X's
+// fence and link.  The node budget bound of the slice kernel covers the new
+// nodes: floor((S + t) / (cap/2)) - 1 for a single-node bucket, and for a
+// chain at most one more than t_X / (cap/2) per touched node X, which sums to
+// within min(chain length, t) + t / (cap/2).
 // ---------------------------------------------------------------------------
 template <typename K>
 struct WideLds {
@@ -946,14 +948,14 @@ struct WideLds {
   u32 bad;
 };
 
+// Merge node X (header hX) with the slice part [s0, s0 + t) of the sorted
+// batch, all of whose keys lie in X's range.  Returns the pieces made.
 template <typename K, int NT>
-__device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideLds<K>& L,
-                                   unsigned long long& added_total) {
+__device__ u32 wide_merge_node(const UpdArgs<K>& a, const WorkItem& w, u32 X, const NodeHdr& hX,
+                               u32 s0, u32 t, WideLds<K>& L, unsigned long long& added_total) {
   const u32 tid = threadIdx.x, lane = tid & 63u;
   const u32 f = a.cap / 2;
-  const u32 X = w.b;
-  const u32 S = w.head & ~kSingleNode;
-  const u32 t = w.e - w.s;
+  const u32 S = hX.size;
   K* const xk = a.nkeys + (u64)X * a.cap;
   K* const xv = a.nvals + (u64)X * a.cap;
   for (u32 i = tid; i < S; i += NT) {
@@ -980,7 +982,7 @@ __device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideL
     bool live = false;
     u32 lb = 0;
     if (valid) {
-      const u32 g = w.s + j;
+      const u32 g = s0 + j;
       k = a.skeys[g];
       live = (g + 1 == a.m) || a.skeys[g + 1] != k;
       lb = lower_bound_idx<K>(L.ak, 0u, S, k);
@@ -1035,10 +1037,10 @@ __device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideL
       }
     }
     __syncthreads();
-    if (L.bad) return;
+    if (L.bad) return 0;
   }
   const u32 base_id = k > 1 ? L.base_id : 0u;
-  const u64 fence_last = (u64)a.mkba[w.b];
+  const u64 fence_last = hX.fence;
   auto node_of = [&](u32 p) -> u32 { return p == 0 ? X : a.free_ids[base_id - p]; };
   auto put = [&](u32 pos, K kk, K vv) {
     const u32 pc = (k == 1) ? 0u : piece_of(pos, c, k);
@@ -1066,7 +1068,7 @@ __device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideL
     bool live = false;
     K kk = K(0);
     if (j < t) {
-      const u32 g = w.s + j;
+      const u32 g = s0 + j;
       kk = a.skeys[g];
       live = (g + 1 == a.m) || a.skeys[g + 1] != kk;
     }
@@ -1074,7 +1076,7 @@ __device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideL
     const u32 r = block_exclusive_scan<NT>(live ? 1u : 0u, L.tmp, &tot);
     if (live) {
       const u32 lb = lower_bound_idx<K>(L.ak, 0u, S, kk);
-      put(run + r + lb - L.dropx[lb], kk, a.svals[w.s + j]);
+      put(run + r + lb - L.dropx[lb], kk, a.svals[s0 + j]);
     }
     run += tot;
   }
@@ -1086,15 +1088,79 @@ __device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideL
       continue;
     }
     a.hdr[node].size = piece_start(p + 1, c, k) - piece_start(p, c, k);
-    a.hdr[node].next = (p + 1 < k) ? node_of(p + 1) : kNil;
+    a.hdr[node].next = (p + 1 < k) ? node_of(p + 1) : hX.next;
     if (p + 1 == k) a.hdr[node].fence = fence_last;
   }
   if (tid == 0) {
     if (k > 1) a.bnodes[w.b] += k - 1;
-    if (S == 0 && c > 0) occ_set(a.occ, w.b);
+    if (S == 0 && c > 0 && X == w.b && hX.next == kNil) occ_set(a.occ, w.b);
     added_total += c - S;
   }
-  __syncthreads();   // LDS is reused by the next item
+  __syncthreads();   // LDS is reused by the next node or item
+  return k;
+}
+
+// A bucket's slice, node by node along its chain: every node whose range holds
+// keys of the slice is merged with them by the whole workgroup.  A dense run
+// of new keys lies between two stored keys, so it usually meets one node.
+template <typename K, int NT>
+__device__ void wide_insert_bucket(const UpdArgs<K>& a, const WorkItem& w, WideLds<K>& L,
+                                   unsigned long long& added_total) {
+  __shared__ u32 s_node, s_j2;
+  __shared__ NodeHdr s_h;
+  u32 j = w.s;
+  if (threadIdx.x == 0) {
+    s_node = w.b;
+    s_h = a.hdr[w.b];
+  }
+  __syncthreads();
+  while (j < w.e) {
+    if (threadIdx.x == 0) {
+      // walk to the node whose range holds skeys[j]; its part of the slice
+      // ends after its fence (the last node takes the rest)
+      u32 X = s_node;
+      NodeHdr h = s_h;
+      const K first = a.skeys[j];
+      u32 steps = 0;
+      while ((u64)first > h.fence && h.next != kNil) {
+        if (h.next >= a.pool || ++steps > a.pool) {   // never on a consistent store
+          atomicCAS(a.status, 0u, kErrInternal);
+          X = kNil;
+          break;
+        }
+        X = h.next;
+        h = a.hdr[X];
+      }
+      s_node = X;
+      s_h = h;
+      s_j2 = (X == kNil) ? w.e
+             : (h.next == kNil) ? w.e : upper_bound_idx<K>(a.skeys, j, w.e, (K)h.fence);
+      if (X != kNil && h.size > a.cap) {
+        atomicCAS(a.status, 0u, kErrInternal);
+        s_node = kNil;
+      }
+    }
+    __syncthreads();
+    const u32 X = s_node;
+    const NodeHdr h = s_h;
+    const u32 j2 = s_j2;
+    __syncthreads();
+    if (X == kNil) return;
+    if (j2 > j) wide_merge_node<K, NT>(a, w, X, h, j, j2 - j, L, added_total);
+    j = j2;
+    if (j < w.e && threadIdx.x == 0) {
+      // continue after the pieces, at the node that followed X
+      if (h.next == kNil || h.next >= a.pool) {
+        atomicCAS(a.status, 0u, kErrInternal);
+        s_node = kNil;
+      } else {
+        s_node = h.next;
+        s_h = a.hdr[h.next];
+      }
+    }
+    __syncthreads();
+    if (s_node == kNil) return;
+  }
 }
 
 // The slice kernel lists the wide items; workgroup g merges items g, g + G, ...

@@ -86,3 +86,44 @@ def test_wide_insert_into_empty_store():
     assert st["buckets"] == 1 and st["live_nodes"] == (1 << 16) // 32
     check_reads(s, o, kb, np.concatenate([k[:3000], np.array([0, 999, 1 << 20], dtype=np.uint32)]),
                 maxpq=4, where="wide empty store")
+
+
+@pytest.mark.parametrize("kb", [32, 64])
+def test_wide_insert_into_chains(kb):
+    """Long slices into chained buckets: a dense run first becomes a chain of
+    pieces; then runs that interleave with it (every node of the chain gets
+    keys), runs that upsert part of it, and runs past its end are merged node
+    by node by the workgroup-wide kernel; contents and reads match the
+    oracle after every batch."""
+    rng = np.random.default_rng(6200 + kb)
+    dt = ktype(kb)
+    s, o = new_pair(kb, cap=32, max_batch=1 << 16)
+    base = np.unique(_keys(rng, kb, 4000))
+    s.bulk_load(to_dev(base), to_dev(base))
+    o.bulk_load(base, base)
+    mx = (1 << kb) - 1
+    st = int(rng.integers(1 << 20, mx - (1 << 20), dtype=np.uint64))
+    # between two stored keys: find a gap wide enough for the runs
+    lo = int(base[np.searchsorted(base, np.uint64(st).astype(dt))])
+    start = lo + 1
+    evens = np.arange(start, start + 2 * 6000, 2, dtype=np.uint64).astype(dt)
+    odds = evens + dt(1)
+    batches = [
+        ("evens", evens),                                        # one long slice -> a chain
+        ("odds", odds),                                          # interleaves with every node
+        ("upserts", np.concatenate([evens[::3], odds[1000:3000]])),
+        ("past the end", np.arange(start + 20000, start + 23000, dtype=np.uint64).astype(dt)),
+        ("mixed", np.concatenate([evens[:700] + dt(0), _keys(rng, kb, 2000)])),
+    ]
+    for r, (name, ins) in enumerate(batches):
+        ins = ins.copy()
+        rng.shuffle(ins)
+        vals = (ins ^ dt(0x1234)) + dt(r)
+        vals[vals == dt(mx)] = 0
+        s.insert(to_dev(ins), to_dev(vals))
+        o.insert(ins, vals)
+        assert s.status() == 0, f"{name}: device error"
+        assert_same_contents(s, o, kb, f"wide into chains: {name}")
+        q = np.concatenate([ins[:2000], evens[::7], _keys(rng, kb, 500)])
+        check_reads(s, o, kb, q, maxpq=8, where=f"wide into chains: {name}")
+    log(f"wide into chains kb={kb}: {s.stats()}")
