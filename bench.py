@@ -316,6 +316,58 @@ def grown_store_reads(args, wl, dev, bufs):
             "restructured": restructured}
 
 
+def successor_across_gap(args):
+    """Successor and range queries that must cross a long run of empty
+    buckets: a 2^24-key u32 store (capacity 128, 2^18 buckets) loses a
+    rank-contiguous quarter of its keys (65,536 consecutive buckets emptied);
+    2^20 successors and 16-key ranges start uniformly inside that gap, so
+    every answer lies past it.  The same queries on the intact store are the
+    reference.  The occupancy summary makes each crossing a few word reads
+    instead of a walk over the empty buckets' headers."""
+    import torch
+    from paper_2604_16725_amd import flix
+    from paper_2604_16725_amd import workloads as w
+    m = 1 << 20
+    ks = w.KeySpace(32, 0xF11C6000)
+    keys = np.sort(ks.build(1 << 24))
+    st = flix.Store(key_bits=32, capacity=128, lanes=16, max_batch=m)
+    dk = torch.from_numpy(keys.view(np.int32)).cuda()
+    st.bulk_load(dk, dk)
+    lo_i, hi_i = (1 << 23), (1 << 23) + (1 << 22)
+    rng = np.random.default_rng(0xF11C6001)
+    q = rng.integers(int(keys[lo_i]), int(keys[hi_i - 1]), m, dtype=np.uint64).astype(np.uint32)
+    dq = torch.from_numpy(q.view(np.int32)).cuda()
+    dhi = torch.from_numpy(np.minimum(q.astype(np.uint64) + 15, 0xFFFFFFFF).astype(np.uint32)
+                           .view(np.int32)).cuda()
+    ok = torch.empty(m, dtype=torch.int32, device="cuda")
+    ov = torch.empty(m, dtype=torch.int32, device="cuda")
+    rc = torch.empty(m, dtype=torch.int32, device="cuda")
+    rv = torch.empty(m * 16, dtype=torch.int32, device="cuda")
+    reps = max(5, args.steps)
+    out = {}
+    for tag in ("intact", "gap"):
+        if tag == "gap":
+            gone = keys[lo_i:hi_i].copy()
+            rng.shuffle(gone)
+            for i in range(0, gone.size, m):
+                st.delete(torch.from_numpy(gone[i:i + m].view(np.int32)).cuda())
+            torch.cuda.synchronize()
+        p50s, _ = timed_calls(lambda: st.successor(dq, out_k=ok, out_v=ov), reps)
+        p50r, _ = timed_calls(lambda: st.range(dq, dhi, 16, counts=rc, out_v=rv, want_keys=False),
+                              reps)
+        out[tag] = {"successor_ms": round(p50s, 4), "range16_ms": round(p50r, 4)}
+    if st.status() != 0:
+        raise RuntimeError("device error in the gap queries")
+    # every successor of the gap queries is the first key after the gap
+    got = ok.cpu().numpy().view(np.uint32)
+    out["answers_past_gap"] = bool((got == keys[hi_i]).all())
+    st.close()
+    out["workload"] = ("2^24 u32 keys, 2^22 rank-contiguous keys deleted (65,536 empty buckets), "
+                       "2^20 successors and 16-key ranges starting inside the gap")
+    log(f"[bench] successor across a gap: {out}")
+    return out
+
+
 def update_heavy_rounds(args):
     """The update-heavy workload: u64 keys and values, bulk load 2^24 keys,
     rounds of 2^20 inserts of new keys then 2^20 deletes of present keys,
@@ -826,6 +878,7 @@ def main():
         bufs = {"lookup": dl, "successor": ds, "range_lo": dlo, "range_hi": dhi, "ol": ol,
                 "sk": sk, "sv": sv, "rc": rc, "rk": rk, "rv": rv, "L": L}
         grown = leg("grown_store", grown_store_reads, args, wl, dev, bufs)
+    gap = leg("successor_gap", successor_across_gap, args)
     update_heavy = leg("update_heavy", update_heavy_rounds, args) if args.update_rounds > 0 else None
     insert_kernels = None if args.no_insert_kernels else leg("insert_kernels", insert_kernel_choice,
                                                                args)
@@ -895,6 +948,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per_fam.items()},
         "breakdown": breakdown,
         "grown_store": grown,
+        "successor_across_gap": gap,
         "update_heavy": update_heavy,
         "insert_kernels": insert_kernels,
         "batching": batching,
