@@ -579,6 +579,9 @@ __global__ __launch_bounds__(NT) void k_group_read(GroupArgs<K> ga, ReadArgs<K> 
   v.e = s_e;
   v.hw = s_hw;
   v.tl = s_tl;
+  v.list = nullptr;   // ranges past their node take the one-lane path here
+  v.list_cap = 0;
+  v.nlist = nullptr;
   resolve_slices<K, NT, GL, KPL, U, IPT>(a, op, v, b0, m, ntot);
 }
 
