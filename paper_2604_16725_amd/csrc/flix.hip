@@ -227,6 +227,21 @@ void dev_free(T** p) {
   *p = nullptr;
 }
 
+// Row table and long-run buffers of the two-launch sort (batches of up to
+// kSplitMaxItems items).
+int alloc_split_scratch(SortScratch& ss, u64 items) {
+  const u64 want = items < kSplitMaxItems ? items : kSplitMaxItems;
+  int rc;
+  if (!ss.toff && (rc = dev_alloc(&ss.toff, (u64)kSplitMaxTiles * 256u * sizeof(u32)))) return rc;
+  if (want <= ss.x_items) return FLIX_OK;
+  dev_free(&ss.xk);
+  dev_free(&ss.xv);
+  ss.x_items = 0;
+  if ((rc = dev_alloc(&ss.xk, want * 8)) || (rc = dev_alloc(&ss.xv, want * 8))) return rc;
+  ss.x_items = want;
+  return FLIX_OK;
+}
+
 int ensure_sort_capacity(flix_store* s, u64 items) {
   if (items <= s->ss.max_items) return FLIX_OK;
   HIP_TRY(hipDeviceSynchronize());
@@ -242,7 +257,7 @@ int ensure_sort_capacity(flix_store* s, u64 items) {
   HIP_TRY(hipMemset(s->ss.status_cl, 0, cwords * sizeof(u64)));
   s->ss.epoch = 0;
   s->ss.max_items = items;
-  return FLIX_OK;
+  return alloc_split_scratch(s->ss, items);
 }
 
 int alloc_pool(flix_store* s, u32 pool) {
@@ -757,6 +772,8 @@ void free_slot(EpochSlot* e) {
   dev_free(&e->bsum); dev_free(&e->counts);
   dev_free(&e->ss.hist); dev_free(&e->ss.status); dev_free(&e->ss.status_cl);
   dev_free(&e->ss.tile_ctr); dev_free(&e->ss.err);
+  dev_free(&e->ss.toff); dev_free(&e->ss.xk); dev_free(&e->ss.xv);
+  e->ss.x_items = 0;
 }
 
 int alloc_slot(flix_store* s, EpochSlot* e) {
@@ -789,6 +806,7 @@ int alloc_slot(flix_store* s, EpochSlot* e) {
   e->ss.max_items = n;
   e->ss.epoch = 0;
   e->ss.parity = 0;
+  if ((rc = alloc_split_scratch(e->ss, n))) return rc;
   e->cap = n;
   return FLIX_OK;
 }
@@ -1189,6 +1207,10 @@ void destroy_all(flix_store* s) {
   dev_free(&s->ss.status);
   dev_free(&s->ss.status_cl);
   dev_free(&s->ss.tile_ctr);
+  dev_free(&s->ss.toff);
+  dev_free(&s->ss.xk);
+  dev_free(&s->ss.xv);
+  s->ss.x_items = 0;
   dev_free(&s->d_status);
   dev_free(&s->d_status_cl);
   dev_free(&s->d_hist);

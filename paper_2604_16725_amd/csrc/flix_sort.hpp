@@ -729,6 +729,578 @@ __global__ __launch_bounds__(kLocalNT) void k_local_sort(K* __restrict__ ka, V* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Batches of at most kSplitMaxItems items with 8-bit digits: two launches and
+// no device-wide look-back chain.
+//   k_tile_split: every tile of kSplitTile items is split stably on the most
+//     significant digit in LDS and written back in place, digit by digit,
+//     with the start of every digit inside the tile (one 256-entry row per
+//     tile);
+//   k_run_sort: one workgroup per top digit.  It reads its column of the row
+//     table (where its digit's segment lies in every tile), publishes the
+//     run's length, gathers the segments in tile order (a stable
+//     concatenation), sorts the run on the digits that vary inside it
+//     (LDS passes when it fits, else the dominant-key or chunked global
+//     forms), and writes it at the sum of the lengths published by the lower
+//     digits.
+// A workgroup only waits on lower digits, whose workgroups were dispatched
+// before it and publish before they wait on anything.
+constexpr int kSplitNT = 512;
+constexpr int kSplitIPT = 4;
+constexpr u32 kSplitTile = kSplitNT * kSplitIPT;
+constexpr u32 kSplitMaxTiles = 1024;
+constexpr u32 kSplitMaxItems = kSplitMaxTiles * kSplitTile;   // 2^21
+static_assert(kSplitMaxTiles <= (u32)kLocalNT, "one tile per thread of a run workgroup");
+static_assert(kSplitTile <= 65536u, "segment starts are 16-bit");
+
+template <typename K, typename V, int PAY>
+struct SplitSmem {
+  K k[kSplitTile];
+  V v[PAY == kPayNone ? 1 : kSplitTile];
+  u32 wc[kSplitNT / 64][256];
+  u32 lstart[256];
+  u32 tmp[kSplitNT / 64 + 1];
+};
+
+template <typename K, typename V, int PAY>
+__global__ __launch_bounds__(kSplitNT) void k_tile_split(const K* __restrict__ kin,
+                                                         const V* __restrict__ vin,
+                                                         K* __restrict__ ks, V* __restrict__ vs,
+                                                         u32* __restrict__ toff, u32 n,
+                                                         u32 shift) {
+  __shared__ SplitSmem<K, V, PAY> sm;
+  constexpr int IPT = kSplitIPT;
+  constexpr int NT = kSplitNT;
+  constexpr int WAVES = NT / 64;
+  const u32 tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+  const u32 tile0 = blockIdx.x * kSplitTile;
+  for (u32 i = tid; i < (u32)WAVES * 256u; i += NT) (&sm.wc[0][0])[i] = 0;
+  K key[IPT];
+  V pay[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+    key[k] = K(0);
+    if (PAY != kPayNone) pay[k] = V(0);
+    if (idx < n) {
+      key[k] = kin[idx];
+      if (PAY == kPayIndex) pay[k] = vin ? vin[idx] : (V)idx;
+      if (PAY == kPayValue) pay[k] = vin[idx];
+    }
+  }
+  __syncthreads();
+  // stable rank among the same-digit items of the wave (wave-striped order)
+  u32 rank[IPT];
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+    const bool valid = idx < n;
+    const u32 d = digit_of<K, 8>(key[k], shift);
+    u64 m = wave_ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const u64 bb = wave_ballot(bit);
+      m &= bit ? bb : ~bb;
+    }
+    const u32 below = rank_below(m);
+    const u32 cnt = (u32)__popcll(m);
+    const u32 base = valid ? sm.wc[w][d] : 0u;
+    rank[k] = base + below;
+    if (valid && below == cnt - 1) sm.wc[w][d] = base + cnt;
+  }
+  __syncthreads();
+  u32 tot = 0;
+  if (tid < 256u) {
+    u32 c[WAVES];
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) c[ww] = sm.wc[ww][tid];
+#pragma unroll
+    for (int ww = 0; ww < WAVES; ++ww) {
+      sm.wc[ww][tid] = tot;
+      tot += c[ww];
+    }
+  }
+  u32 dummy;
+  const u32 ls = block_exclusive_scan<NT>(tid < 256u ? tot : 0u, sm.tmp, &dummy);
+  if (tid < 256u) {
+    sm.lstart[tid] = ls;
+    toff[(u64)blockIdx.x * 256u + tid] = ls;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < IPT; ++k) {
+    const u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
+    if (idx < n) {
+      const u32 d = digit_of<K, 8>(key[k], shift);
+      const u32 pos = sm.lstart[d] + sm.wc[w][d] + rank[k];
+      sm.k[pos] = key[k];
+      if (PAY != kPayNone) sm.v[pos] = pay[k];
+    }
+  }
+  __syncthreads();
+  const u32 valid_n = (n - tile0) < kSplitTile ? (n - tile0) : kSplitTile;
+#pragma unroll
+  for (int r = 0; r < IPT; ++r) {
+    const u32 i = tid + (u32)r * NT;
+    if (i < valid_n) {
+      ks[tile0 + i] = sm.k[i];
+      if (PAY != kPayNone) vs[tile0 + i] = sm.v[i];
+    }
+  }
+}
+
+// Where one top digit's run lies in the split tiles: segment t starts at
+// a[t] inside tile t and holds run positions [p[t], p[t+1]).
+struct RunMap {
+  u32 p[kSplitMaxTiles + 1];
+  unsigned short a[kSplitMaxTiles];
+  u32 red[4];
+};
+constexpr size_t kRunMapBytes = (sizeof(RunMap) + 15) & ~size_t(15);
+
+template <typename K, typename V, int PAY>
+constexpr size_t run_sort_lds() {
+  return kLocalHeadBytes + kRunMapBytes + (size_t)kLocalCap * sizeof(K) +
+         (PAY == kPayNone ? 0 : (size_t)kLocalCap * sizeof(V));
+}
+
+// Staging index of run position i (0 <= i < run length): the segment is the
+// last tile whose first position is <= i (empty segments share positions).
+__device__ __forceinline__ u32 run_src(const RunMap& m, u32 ntiles, u32 i) {
+  u32 lo = 0, hi = ntiles;   // p[lo] <= i < p[hi]
+  while (hi - lo > 1) {
+    const u32 mid = (lo + hi) >> 1;
+    if (m.p[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo * kSplitTile + m.a[lo] + (i - m.p[lo]);
+}
+
+// Bit p of the result is set when digit p (below the top one) differs
+// between some two of the thread's valid items' keys across the workgroup.
+template <typename K>
+__device__ __forceinline__ u32 varying_digits(K kand, K kor, u32 npass, u32* red) {
+  const u32 tid = threadIdx.x;
+  if (tid < 4u) red[tid] = tid < 2u ? 0xFFFFFFFFu : 0u;
+  __syncthreads();
+  const u64 a = (u64)kand, o = (u64)kor;
+  u32 a0 = (u32)a, a1 = (u32)(a >> 32), o0 = (u32)o, o1 = (u32)(o >> 32);
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    a0 &= (u32)__shfl_xor((int)a0, off, 64);
+    a1 &= (u32)__shfl_xor((int)a1, off, 64);
+    o0 |= (u32)__shfl_xor((int)o0, off, 64);
+    o1 |= (u32)__shfl_xor((int)o1, off, 64);
+  }
+  if ((tid & 63u) == 0) {
+    atomicAnd(&red[0], a0);
+    atomicAnd(&red[1], a1);
+    atomicOr(&red[2], o0);
+    atomicOr(&red[3], o1);
+  }
+  __syncthreads();
+  const u64 diff = (((u64)red[1] << 32) | red[0]) ^ (((u64)red[3] << 32) | red[2]);
+  __syncthreads();
+  u32 mask = 0;
+  for (u32 p = 0; p < npass; ++p)
+    if ((diff >> (8u * p)) & 0xFFull) mask |= 1u << p;
+  return mask;
+}
+
+// LDS passes over the digits set in `passes` for cnt items held wave-striped
+// with ipt items per lane (position w*64*ipt + k*64 + lane); leaves them
+// sorted in the same layout.  All threads call.
+template <typename K, typename V, int PAY>
+__device__ void run_lds_passes(K (&key)[kLocalIPT], V (&pay)[kLocalIPT], u32 cnt, u32 ipt,
+                               u32 passes, LocalSortHead& h, K* s_k, V* s_v) {
+  constexpr int IPT = kLocalIPT;
+  constexpr int WAVES = kLocalNT / 64;
+  const u32 tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
+  u32 rank[IPT];
+  for (u32 p = 0; p < (u32)kLocalMaxPass; ++p) {
+    if (!((passes >> p) & 1u)) continue;
+    const u32 shift = p * 8u;
+    for (u32 i = tid; i < (u32)WAVES * 256u; i += kLocalNT) (&h.wc[0][0])[i] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      rank[k] = 0;
+      if ((u32)k < ipt) {   // uniform across the workgroup
+        const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+        const bool valid = li < cnt;
+        const u32 d = digit_of<K, 8>(key[k], shift);
+        u64 m = wave_ballot(valid);
+        if (m) {
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const u64 bb = wave_ballot(bit);
+            m &= bit ? bb : ~bb;
+          }
+          const u32 below = rank_below(m);
+          const u32 c = (u32)__popcll(m);
+          const u32 base = valid ? h.wc[w][d] : 0u;
+          rank[k] = base + below;
+          if (valid && below == c - 1) h.wc[w][d] = base + c;
+        }
+      }
+    }
+    __syncthreads();
+    u32 tot = 0;
+    if (tid < 256u) {
+      u32 c[WAVES];
+#pragma unroll
+      for (int ww = 0; ww < WAVES; ++ww) c[ww] = h.wc[ww][tid];
+#pragma unroll
+      for (int ww = 0; ww < WAVES; ++ww) {
+        h.wc[ww][tid] = tot;
+        tot += c[ww];
+      }
+    }
+    u32 dummy;
+    const u32 ds = block_exclusive_scan<kLocalNT>(tid < 256u ? tot : 0u, h.tmp, &dummy);
+    if (tid < 256u) h.dstart[tid] = ds;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+      if ((u32)k < ipt && li < cnt) {
+        const u32 d = digit_of<K, 8>(key[k], shift);
+        const u32 pos = h.dstart[d] + h.wc[w][d] + rank[k];
+        s_k[pos] = key[k];
+        if (PAY != kPayNone) s_v[pos] = pay[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+      if ((u32)k < ipt && li < cnt) {
+        key[k] = s_k[li];
+        if (PAY != kPayNone) pay[k] = s_v[li];
+      }
+    }
+  }
+}
+
+// Sum of the run lengths published by the digits below d (all threads call;
+// the result is workgroup-uniform).
+__device__ __forceinline__ u32 lower_runs_total(const u64* status, u32 d, u32 epoch, u32* err,
+                                                u32* tmp) {
+  const u32 tid = threadIdx.x;
+  u32 v = 0;
+  if (tid < d) {
+    u32 polls = 0;
+    while (true) {
+      const u64 s = ld_agent(&status[tid]);
+      if ((u32)(s >> 34) == epoch && ((s >> 32) & 3u) != 0u) {
+        v = (u32)s;
+        break;
+      }
+      // bounded wait: a lower digit that never publishes is a bug, and the
+      // kernel must still end; the error word reports it
+      if (++polls > (1u << 22)) {
+        atomicOr(err, 1u);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  u32 total;
+  (void)block_exclusive_scan<kLocalNT>(v, tmp, &total);
+  return total;
+}
+
+template <typename K, typename V, int PAY>
+__global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
+                                                       const V* __restrict__ vs,
+                                                       K* __restrict__ ko, V* __restrict__ vo,
+                                                       K* __restrict__ kx, V* __restrict__ vx,
+                                                       const u32* __restrict__ toff,
+                                                       u64* __restrict__ status, u32 epoch,
+                                                       u32 npass, u32 n, u32* __restrict__ err) {
+  extern __shared__ unsigned char lsm[];
+  LocalSortHead& h = *reinterpret_cast<LocalSortHead*>(lsm);
+  RunMap& m = *reinterpret_cast<RunMap*>(lsm + kLocalHeadBytes);
+  K* s_k = reinterpret_cast<K*>(lsm + kLocalHeadBytes + kRunMapBytes);
+  V* s_v = reinterpret_cast<V*>(lsm + kLocalHeadBytes + kRunMapBytes +
+                                (size_t)kLocalCap * sizeof(K));
+  constexpr int IPT = kLocalIPT;
+  const u32 tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
+  const u32 d = blockIdx.x;
+  const u32 ntiles = (n + kSplitTile - 1) / kSplitTile;   // <= kSplitMaxTiles = blockDim
+  // this digit's segment in every tile
+  u32 c = 0;
+  if (tid < ntiles) {
+    const u32 tn = (n - tid * kSplitTile) < kSplitTile ? (n - tid * kSplitTile) : kSplitTile;
+    const u32 a = toff[(u64)tid * 256u + d];
+    const u32 b = d < 255u ? toff[(u64)tid * 256u + d + 1u] : tn;
+    if (a <= b && b <= tn) {
+      c = b - a;
+    } else {   // rows inconsistent with the tiles: never expected
+      atomicOr(err, 2u);
+    }
+    m.a[tid] = (unsigned short)a;
+  }
+  u32 cnt;
+  const u32 pre = block_exclusive_scan<kLocalNT>(c, h.tmp, &cnt);
+  if (tid < ntiles) m.p[tid] = pre;
+  if (tid == 0) {
+    m.p[ntiles] = cnt;
+    st_agent(&status[d], pack_status(epoch, kFlagAgg, cnt));
+  }
+  __syncthreads();
+  if (cnt == 0) return;
+  K key[IPT];
+  V pay[IPT];
+  if (cnt <= kLocalCap) {
+    // the run lives in registers and LDS for all of its passes
+    const u32 ipt = (cnt + kLocalNT - 1) / kLocalNT;
+    K kand = ~K(0), kor = K(0);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+      key[k] = K(0);
+      if ((u32)k < ipt && li < cnt) {
+        const u32 src = run_src(m, ntiles, li);
+        key[k] = ks[src];
+        if (PAY != kPayNone) pay[k] = vs[src];
+        kand &= key[k];
+        kor |= key[k];
+      }
+    }
+    const u32 passes = varying_digits<K>(kand, kor, npass, m.red);
+    run_lds_passes<K, V, PAY>(key, pay, cnt, ipt, passes, h, s_k, s_v);
+    const u32 base = lower_runs_total(status, d, epoch, err, h.tmp);
+    if (base + cnt > n) {   // published lengths inconsistent: never expected
+      if (tid == 0) atomicOr(err, 2u);
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+      if ((u32)k < ipt && li < cnt) {
+        ko[base + li] = key[k];
+        if (PAY != kPayNone) vo[base + li] = pay[k];
+      }
+    }
+    return;
+  }
+  const u32 base = lower_runs_total(status, d, epoch, err, h.tmp);
+  if (base + cnt > n) {
+    if (tid == 0) atomicOr(err, 2u);
+    return;
+  }
+  K* const okr = ko + base;
+  V* const ovr = vo + base;
+  u32 rank[IPT];
+  // A long run is usually one repeated key (skewed batches).  With X the key
+  // in the middle of the run: the items other than X are gathered in order
+  // into LDS; if they fit, they are sorted there and written around the
+  // block of X items, which keep their input order (stable).
+  {
+    const K X = ks[run_src(m, ntiles, cnt / 2)];
+    u32 nrest = 0;
+    bool fits = true;
+    K kand = ~K(0), kor = K(0);
+    for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+      bool rest[IPT];
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
+        const bool valid = li < cnt;
+        key[k] = X;
+        if (valid) {
+          const u32 src = run_src(m, ntiles, li);
+          key[k] = ks[src];
+          if (PAY != kPayNone) pay[k] = vs[src];
+        }
+        rest[k] = valid && key[k] != X;
+        if (rest[k]) {
+          kand &= key[k];
+          kor |= key[k];
+        }
+      }
+      const u32 tot = local_class_rank(rest, rank, h);
+      if (nrest + tot > kLocalCap) {   // uniform: tot and nrest are workgroup-wide
+        fits = false;
+        break;
+      }
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        if (rest[k]) {
+          s_k[nrest + rank[k]] = key[k];
+          if (PAY != kPayNone) s_v[nrest + rank[k]] = pay[k];
+        }
+      }
+      nrest += tot;
+    }
+    if (fits) {
+      __syncthreads();
+      const u32 ipt = (nrest + kLocalNT - 1) / kLocalNT;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+        if ((u32)k < ipt && li < nrest) {
+          key[k] = s_k[li];
+          if (PAY != kPayNone) pay[k] = s_v[li];
+        }
+      }
+      const u32 passes = varying_digits<K>(kand, kor, npass, m.red) & (nrest ? ~0u : 0u);
+      run_lds_passes<K, V, PAY>(key, pay, nrest, ipt, passes, h, s_k, s_v);
+      // items below X come first, then the X block, then the rest
+      u32 mine = 0;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+        if ((u32)k < ipt && li < nrest && key[k] < X) ++mine;
+      }
+      u32 nlt;
+      (void)block_exclusive_scan<kLocalNT>(mine, h.tmp, &nlt);
+      const u32 neq = cnt - nrest;
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+        if ((u32)k < ipt && li < nrest) {
+          const u32 o = li < nlt ? li : li + neq;
+          okr[o] = key[k];
+          if (PAY != kPayNone) ovr[o] = pay[k];
+        }
+      }
+      // the X items in input order
+      u32 xbase = 0;
+      for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+        bool isx[IPT];
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
+          isx[k] = false;
+          if (li < cnt) {
+            const u32 src = run_src(m, ntiles, li);
+            isx[k] = ks[src] == X;
+            if (PAY != kPayNone) pay[k] = vs[src];
+          }
+        }
+        const u32 tot = local_class_rank(isx, rank, h);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          if (isx[k]) {
+            okr[nlt + xbase + rank[k]] = X;
+            if (PAY != kPayNone) ovr[nlt + xbase + rank[k]] = pay[k];
+          }
+        }
+        xbase += tot;
+      }
+      return;
+    }
+    __syncthreads();
+  }
+  // A long run of many keys: LSD passes in global memory, chunk by chunk in
+  // order, over the digits that vary inside the run.  The first pass reads
+  // the split tiles; the passes alternate between the run's region of the
+  // extra buffer and of the output so that the last one writes the output.
+  // The digit counts of every pass come from one sweep over the run first (a
+  // pass only permutes the run).
+  for (u32 i = tid; i < npass * 256u; i += kLocalNT) (&h.hist[0][0])[i] = 0;
+  if (tid == 0) m.red[0] = 0;
+  __syncthreads();
+  for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const u32 li = base0 + (u32)k * kLocalNT + tid;
+      key[k] = li < cnt ? ks[run_src(m, ntiles, li)] : K(0);
+    }
+    // Skewed runs repeat a few keys: the wave's most common case, the first
+    // valid lane's digit, is added once with its lane count, the other lanes
+    // add one each (LDS atomics on one address would serialise the wave).
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const bool valid = base0 + (u32)k * kLocalNT + tid < cnt;
+      const u64 vm = wave_ballot(valid);
+      if (vm == 0) continue;   // uniform across the wave
+      const int src = __ffsll((unsigned long long)vm) - 1;
+      for (u32 p = 0; p < npass; ++p) {
+        const u32 dg = digit_of<K, 8>(key[k], p * 8u);
+        const u32 d0 = (u32)__shfl((int)dg, src, 64);
+        const u64 same = wave_ballot(valid && dg == d0);
+        if ((int)lane == src) atomicAdd(&h.hist[p][d0], (u32)__popcll(same));
+        if (valid && dg != d0) atomicAdd(&h.hist[p][dg], 1u);
+      }
+    }
+  }
+  __syncthreads();
+  // a digit is trivial when one value holds the whole run
+  if (tid < 256u) {
+    u32 t = 0;
+    for (u32 p = 0; p < npass; ++p)
+      if (h.hist[p][tid] == cnt) t |= 1u << p;
+    if (t) atomicOr(&m.red[0], t);
+  }
+  __syncthreads();
+  const u32 passes = ~m.red[0] & ((1u << npass) - 1u);
+  const u32 npasses = (u32)__popc(passes);
+  K* const xkr = kx + base;
+  V* const xvr = vx + base;
+  u32 done = 0;
+  for (u32 p = 0; p < npass; ++p) {
+    if (!((passes >> p) & 1u)) continue;
+    const u32 shift = p * 8u;
+    const bool first = done == 0;
+    const bool to_out = ((npasses - 1u - done) & 1u) == 0u;
+    // the previous pass wrote the other region
+    const K* ik = to_out ? xkr : okr;
+    const V* iv = to_out ? xvr : ovr;
+    K* ok = to_out ? okr : xkr;
+    V* ov = to_out ? ovr : xvr;
+    {
+      const u32 cc = tid < 256u ? h.hist[p][tid] : 0u;
+      u32 dummy;
+      const u32 ex = block_exclusive_scan<kLocalNT>(cc, h.tmp, &dummy);
+      if (tid < 256u) h.off[tid] = ex;
+      __syncthreads();
+    }
+    for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
+        key[k] = K(0);
+        if (li < cnt) {
+          const u32 src = first ? run_src(m, ntiles, li) : li;
+          key[k] = first ? ks[src] : ik[src];
+          if (PAY != kPayNone) pay[k] = first ? vs[src] : iv[src];
+        }
+      }
+      for (u32 i = tid; i < (kLocalNT / 64) * 256u; i += kLocalNT) (&h.wc[0][0])[i] = 0;
+      __syncthreads();
+      local_rank<K>(key, base0, cnt, shift, h, rank);
+      __syncthreads();
+      const u32 tot = local_wave_prefix(h);
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
+        if (li < cnt) {
+          const u32 dg = digit_of<K, 8>(key[k], shift);
+          const u32 pos = h.off[dg] + h.wc[w][dg] + rank[k];
+          ok[pos] = key[k];
+          if (PAY != kPayNone) ov[pos] = pay[k];
+        }
+      }
+      __syncthreads();
+      if (tid < 256u) h.off[tid] += tot;
+      __syncthreads();
+    }
+    ++done;
+  }
+  if (npasses == 0) {   // every key of the run is equal: copy it in order
+    for (u32 li = tid; li < cnt; li += kLocalNT) {
+      const u32 src = run_src(m, ntiles, li);
+      okr[li] = ks[src];
+      if (PAY != kPayNone) ovr[li] = vs[src];
+    }
+  }
+}
+
 // Scratch shared by every sort call of one store.
 struct SortScratch {
   u32* hist = nullptr;      // [2][P*R] ping-pong histogram slots
@@ -740,8 +1312,12 @@ struct SortScratch {
   u32 epoch = 0;            // last epoch used
   u32 parity = 0;           // histogram slot of the next call
   u64 max_items = 0;        // capacity of the status array, in items
-  // optional per-kernel timing hooks (family 0: histogram, 1: one pass,
-  // 2: local run sort):
+  u32* toff = nullptr;      // [kSplitMaxTiles][256] digit starts of the split tiles
+  void* xk = nullptr;       // [x_items] keys of long runs between passes (8-byte slots)
+  void* xv = nullptr;       // [x_items] their payloads (8-byte slots)
+  u64 x_items = 0;
+  // optional per-kernel timing hooks (family 0: histogram, 1: one pass or
+  // the tile split, 2: the per-run sort):
   // on_begin hands out the start/stop events of the next dispatch
   void (*on_begin)(void* ctx, int family, hipEvent_t* e0, hipEvent_t* e1) = nullptr;
   void (*on_end)(void* ctx, int family, hipEvent_t e0, hipEvent_t e1) = nullptr;
@@ -803,6 +1379,45 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
   }
   if ((u64)n > s.max_items) return hipErrorInvalidValue;
   const u32 ntiles = (n + kSortTile - 1) / kSortTile;
+  if (RB == 8 && n <= kSplitMaxItems && s.toff && s.xk && s.xv && n <= s.x_items) {
+    // two launches: tile split on the top digit, then one workgroup per run
+    if (s.epoch >= (1u << 30) - 1u) {
+      hipError_t e = hipMemsetAsync(s.status, 0, sort_status_words(s.max_items, RB) * sizeof(u64), st);
+      if (e != hipSuccess) return e;
+      e = hipMemsetAsync(s.status_cl, 0, sort_cluster_words(s.max_items) * sizeof(u64), st);
+      if (e != hipSuccess) return e;
+      s.epoch = 0;
+    }
+    const u32 epoch = ++s.epoch;
+    const u32 nsplit = (n + kSplitTile - 1) / kSplitTile;
+    {
+      SortTimer t(s, 1);
+      launch_timed(t.e0, t.e1, k_tile_split<K, V, PAY>, dim3(nsplit), dim3(kSplitNT), 0, st, kin,
+                   vin, k0, v0, s.toff, n, (u32)((P - 1) * RB));
+      t.end();
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    constexpr size_t lds = run_sort_lds<K, V, PAY>();
+    static bool lds_set = false;
+    if (!lds_set) {
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_run_sort<K, V, PAY>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+      lds_set = true;
+    }
+    {
+      SortTimer t(s, 2);
+      launch_timed(t.e0, t.e1, k_run_sort<K, V, PAY>, dim3(R), dim3(kLocalNT), (uint32_t)lds, st,
+                   (const K*)k0, (const V*)v0, k1, v1, (K*)s.xk, (V*)s.xv, (const u32*)s.toff,
+                   s.status, epoch, (u32)(P - 1), n, s.err);
+      t.end();
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    *result_buf = 1;
+    return hipSuccess;
+  }
   u32* hist = s.hist + (size_t)s.parity * (P * R);
   u32* hist_next = s.hist + (size_t)(s.parity ^ 1u) * (P * R);
   s.parity ^= 1u;

@@ -81,11 +81,13 @@ def test_sort_skewed_top_digit_runs(kb):
     assert np.array_equal(to_host(ko, kb), k[ref])
 
 
-@pytest.mark.parametrize("n", [1 << 22, (1 << 22) + 1])
+@pytest.mark.parametrize("n", [1 << 21, (1 << 21) + 1, 1 << 22, (1 << 22) + 1])
 def test_sort_at_the_per_run_limit(n):
-    """2^22 keys still take the top-digit pass and the per-run sort (runs of
-    ~16K items, above the LDS run size, take the chunked path); one more key
-    takes the onesweep passes."""
+    """2^21 keys are the most the tile split takes (1024 tiles, one per
+    thread of a run workgroup); one more key takes the top-digit onesweep
+    pass and the per-run sort up to 2^22 keys (runs of ~16K items, above the
+    LDS run size, take the chunked path); one more takes the onesweep
+    passes."""
     from paper_2604_16725_amd.flix import Store
     log(f"sort at the per-run limit n={n}")
     s = Store(key_bits=32, capacity=64, radix_bits=8, max_batch=(1 << 22) + 1)
@@ -96,6 +98,29 @@ def test_sort_at_the_per_run_limit(n):
     ref = np.argsort(k, kind="stable")
     assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
     assert np.array_equal(to_host(ko, 32), k[ref])
+
+
+@pytest.mark.parametrize("kb,nvary", [(32, 1), (32, 2), (32, 3), (64, 2), (64, 5), (64, 7)])
+def test_sort_long_runs_varying_digits(kb, nvary):
+    """One top digit holds 60000 keys that differ only in their lowest
+    `nvary` digits (the others are equal inside the run), so the run is too
+    long for LDS and too varied for the dominant-key form: its chunked global
+    passes skip the digits that do not vary, with an odd or even number of
+    passes left, and must still end in the output buffer, stable."""
+    from paper_2604_16725_amd.flix import Store
+    log(f"long runs kb={kb} nvary={nvary}")
+    s = Store(key_bits=kb, capacity=64, radix_bits=8, max_batch=1 << 17)
+    rng = np.random.default_rng(40 + kb + nvary)
+    top = np.uint64(0xC3) << np.uint64(kb - 8)
+    mid = np.uint64(0x5A5A5A5A5A5A5A5A) & np.uint64((1 << (kb - 8)) - 1)
+    mid &= ~np.uint64((1 << (8 * nvary)) - 1)
+    low = rng.integers(0, 1 << (8 * nvary), 60000, dtype=np.uint64)
+    k = np.concatenate([top | mid | low, _keys(rng, kb, 20000).astype(np.uint64)])
+    k = rng.permutation(k).astype(ktype(kb))
+    ko, io = s.sort_pairs(to_dev(k))
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
+    assert np.array_equal(to_host(ko, kb), k[ref])
 
 
 @pytest.mark.parametrize("kb", [32, 64])
