@@ -582,6 +582,8 @@ __global__ __launch_bounds__(NT) void k_group_read(GroupArgs<K> ga, ReadArgs<K> 
   v.list = nullptr;   // ranges past their node take the one-lane path here
   v.list_cap = 0;
   v.nlist = nullptr;
+  v.lnode = nullptr;
+  v.lbk = nullptr;
   resolve_slices<K, NT, GL, KPL, U, IPT>(a, op, v, b0, m, ntot);
 }
 

@@ -42,10 +42,16 @@ struct SliceView {
   const u32* e;
   const u32* hw;
   const unsigned short* tl;
-  u32* list;        // LDS room for the ranges that run past their node
-  u32 list_cap;     // (0: none; such ranges then take the one-lane path)
+  u32* list;        // LDS room for the ranges handed to the wave-wide copy
+  u32 list_cap;     // (0: none; every range then stays on the one-lane path)
   u32* nlist;       // LDS counter of that list
+  u32* lnode;       // per list entry: node and bucket where the copy resumes
+  u32* lbk;         // (the position goes to pos[j], the results so far to cnt[j])
 };
+
+// A range on the one-lane path hands its copy to a whole wave when one node
+// holds more than this many of its results.
+constexpr u32 kLaneRangeMax = 16;
 
 template <typename K, int KPL>
 struct alignas(sizeof(K) * KPL >= 16 ? 16 : sizeof(K) * KPL) KeyVec {
@@ -68,12 +74,13 @@ struct ReadSmem {
   u32 nslow;        // ranges listed for the wave-wide copy
 };
 
-// Ranges whose results run past their node (listed by phase B): one wave per
-// range walks the nodes in order, 64 keys per step with coalesced loads, and
+// Ranges handed over by the one-lane path (a node holds more than
+// kLaneRangeMax of their results): one wave per range resumes at the node and
+// position the lane reached, 64 keys per step with coalesced loads, and
 // writes the results it keeps with coalesced stores; the keys of a node are
 // sorted, so the in-range lanes of a step form a prefix.  All threads call.
 template <typename K, int NT>
-__device__ __forceinline__ void range_waves(const ReadArgs<K>& a, const SliceView<K>& v, u32 b0) {
+__device__ __forceinline__ void range_waves(const ReadArgs<K>& a, const SliceView<K>& v) {
   __syncthreads();
   const u32 n = *v.nlist < v.list_cap ? *v.nlist : v.list_cap;
   const u32 lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
@@ -81,90 +88,73 @@ __device__ __forceinline__ void range_waves(const ReadArgs<K>& a, const SliceVie
   const OccLevels occ = occ_levels(a.occ, a.nb);
   for (u32 li = wv; li < n; li += NW) {
     const u32 j = v.list[li];
-    const u32 lb = v.pos[j] >> 16;
-    u32 b = b0 + lb;
-    const K x = v.q[j];
+    u32 node = v.lnode[li];
+    u32 b = v.lbk[li];
+    u32 p = v.pos[j];
+    u32 cnt = v.cnt[j];
     const K hi = v.hi[j];
     const u32 orig = v.idx[j];
     const u64 ob = (u64)orig * a.maxpq;
-    u32 cnt = 0;
-    if (x <= hi) {
-      // node of bucket b whose range holds x (lane 0 walks, all lanes follow)
-      u32 node = 0, size = 0, next = 0;
-      if (lane == 0) {
-        NodeHdr h;
-        node = locate_node(a.hdr, a.pool, b, (u64)x, &h);
-        size = h.size;
-        next = h.next;
-      }
-      node = __shfl(node, 0, 64);
-      size = __shfl(size, 0, 64);
-      next = __shfl(next, 0, 64);
-      bool bad = node == kBadLink || size > a.cap;
-      // lower bound of x in the node: keys below x, counted 64 at a time
-      u32 p = 0;
-      if (!bad) {
-        const K* keys = a.nkeys + (u64)node * a.cap;
-        for (u32 i0 = 0; i0 < size; i0 += 64) {
-          const u32 i = i0 + lane;
-          const bool below = i < size && keys[i] < x;
-          const u32 c = (u32)__popcll(wave_ballot(below));
-          p += c;
-          if (c < 64) break;
-        }
-      }
-      bool done = bad;
-      while (!done) {
-        const K* keys = a.nkeys + (u64)node * a.cap;
-        const K* vals = a.nvals + (u64)node * a.cap;
-        for (u32 i0 = p; i0 < size; i0 += 64) {
-          const u32 i = i0 + lane;
-          const bool valid = i < size;
-          const K k = valid ? keys[i] : K(0);
-          const bool in = valid && k <= hi;
-          const u32 nin = (u32)__popcll(wave_ballot(in));
-          if (in) {
-            const u32 r = cnt + lane;
-            if (r < a.maxpq) {
-              if (a.out_k) a.out_k[ob + r] = k;
-              if (a.out_v) a.out_v[ob + r] = vals[i];
-            }
-          }
-          cnt += nin;
-          const u32 avail = size - i0 < 64u ? size - i0 : 64u;
-          if (nin < avail) {   // a key above hi: the range ends in this node
-            done = true;
-            break;
+    u32 size = 0, next = 0;
+    if (lane == 0) {
+      const NodeHdr h = a.hdr[node];
+      size = h.size;
+      next = h.next;
+    }
+    size = __shfl(size, 0, 64);
+    next = __shfl(next, 0, 64);
+    bool bad = size > a.cap;
+    bool done = bad;
+    while (!done) {
+      const K* keys = a.nkeys + (u64)node * a.cap;
+      const K* vals = a.nvals + (u64)node * a.cap;
+      for (u32 i0 = p; i0 < size; i0 += 64) {
+        const u32 i = i0 + lane;
+        const bool valid = i < size;
+        const K k = valid ? keys[i] : K(0);
+        const bool in = valid && k <= hi;
+        const u32 nin = (u32)__popcll(wave_ballot(in));
+        if (in) {
+          const u32 r = cnt + lane;
+          if (r < a.maxpq) {
+            if (a.out_k) a.out_k[ob + r] = k;
+            if (a.out_v) a.out_v[ob + r] = vals[i];
           }
         }
-        if (done) break;
-        // next node of the chain, else the next bucket that holds a key
-        u32 nn = 0, nsize = 0, nnext = 0;
-        if (lane == 0) {
-          NodeHdr h, g;
-          h.next = next;
-          h.size = size;
-          nn = next_nonempty(a.hdr, occ, a.nb, a.pool, &b, h, &g);
-          nsize = g.size;
-          nnext = g.next;
-        }
-        nn = __shfl(nn, 0, 64);
-        nsize = __shfl(nsize, 0, 64);
-        nnext = __shfl(nnext, 0, 64);
-        b = __shfl(b, 0, 64);
-        if (nn == kNil) break;
-        if (nn == kBadLink || nsize > a.cap) {
-          bad = true;
+        cnt += nin;
+        const u32 avail = size - i0 < 64u ? size - i0 : 64u;
+        if (nin < avail) {   // a key above hi: the range ends in this node
+          done = true;
           break;
         }
-        node = nn;
-        size = nsize;
-        next = nnext;
-        p = 0;
       }
-      if (bad && lane == 0) atomicCAS(a.err, 0u, kErrInternal);
-      if (bad) cnt = 0;
+      if (done) break;
+      // next node of the chain, else the next bucket that holds a key
+      u32 nn = 0, nsize = 0, nnext = 0;
+      if (lane == 0) {
+        NodeHdr h, g;
+        h.next = next;
+        h.size = size;
+        nn = next_nonempty(a.hdr, occ, a.nb, a.pool, &b, h, &g);
+        nsize = g.size;
+        nnext = g.next;
+      }
+      nn = __shfl(nn, 0, 64);
+      nsize = __shfl(nsize, 0, 64);
+      nnext = __shfl(nnext, 0, 64);
+      b = __shfl(b, 0, 64);
+      if (nn == kNil) break;
+      if (nn == kBadLink || nsize > a.cap) {
+        bad = true;
+        break;
+      }
+      node = nn;
+      size = nsize;
+      next = nnext;
+      p = 0;
     }
+    if (bad && lane == 0) atomicCAS(a.err, 0u, kErrInternal);
+    if (bad) cnt = 0;
     if (lane == 0) a.counts[orig] = cnt;
   }
 }
@@ -356,14 +346,6 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
       }
       continue;
     }
-    if (op == kOpRange && v.list_cap) {
-      // a range that runs past its node: listed for the wave-wide copy below
-      const u32 li = atomicAdd(v.nlist, 1u);
-      if (li < v.list_cap) {
-        v.list[li] = j;
-        continue;
-      }
-    }
     if (op == kOpPredecessor) {
       bool bad = false;
       const u64 at = predecessor_slot<K>(a.hdr, a.nkeys, occ_levels(a.occ, a.nb), a.pool, a.cap, b, x, &bad);
@@ -406,10 +388,29 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
     } else {
       const K hi = s_hi[j];
       u32 cnt = 0;
+      bool handed = false;
       if (x <= hi) {
         const u64 ob = (u64)orig * a.maxpq;
         while (true) {
-          u32 ub = upper_bound_idx<K>(keys, p, h.size, hi);
+          // more than kLaneRangeMax results in this node: a wave copies them
+          u32 lim = h.size;
+          if (v.list_cap && p + kLaneRangeMax < h.size) {
+            if (keys[p + kLaneRangeMax] <= hi) {
+              const u32 li = atomicAdd(v.nlist, 1u);
+              if (li < v.list_cap) {
+                v.list[li] = j;
+                v.lnode[li] = node;
+                v.lbk[li] = b;
+                s_pos[j] = p;
+                s_cnt[j] = cnt;
+                handed = true;
+                break;
+              }
+            } else {
+              lim = p + kLaneRangeMax;   // keys[lim] > hi: the range ends before lim
+            }
+          }
+          u32 ub = upper_bound_idx<K>(keys, p, lim, hi);
           for (u32 r = p; r < ub; ++r, ++cnt) {
             if (cnt < a.maxpq) {
               if (a.out_k) a.out_k[ob + cnt] = keys[r];
@@ -430,10 +431,10 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
           p = 0;
         }
       }
-      a.counts[orig] = cnt;
+      if (!handed) a.counts[orig] = cnt;
     }
   }
-  if (op == kOpRange && v.list_cap) range_waves<K, NT>(a, v, b0);
+  if (op == kOpRange && v.list_cap) range_waves<K, NT>(a, v);
 }
 
 // One share (workgroup-sized unit) of a read batch; `vb` is the share index.
@@ -574,6 +575,8 @@ __device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
   v.list = reinterpret_cast<u32*>(s_mk);
   v.list_cap = S;
   v.nlist = &sm.nslow;
+  v.lnode = s_e;    // phase A is done with the slice ends and head words
+  v.lbk = s_hw;     // when phase B hands ranges over
   if (tid == 0) sm.nslow = 0;
   resolve_slices<K, NT, GL, KPL, U, RQ>(a, op, v, b0, nq, ntouch);
 }
