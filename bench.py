@@ -97,14 +97,28 @@ def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8, read_path="sorted"
     # sorts per step: insert (key + value) and delete (key only), plus the
     # three read batches (key + input position) on the sorted read path
     pay = [vbytes, 0] if groups else [4, 4, 4, vbytes, 0]
-    fam["sort_hist"] = len(pay) * m * kbytes
-    # batches of up to 2^22 keys with 8-bit digits: one device-wide pass on
-    # the top digit, then one read and one write of every pair by the
-    # per-run sort; otherwise P device-wide passes
-    local = rb == 8 and m <= (1 << 22)
-    fam["sort_pass"] = sum((1 if local else P) * m * 2 * (kbytes + p) for p in pay)
-    if local:
-        fam["sort_local"] = sum(m * 2 * (kbytes + p) for p in pay)
+    # input payload read by the first launch: the read batches' input
+    # positions are generated, not read
+    pay_in = [vbytes, 0] if groups else [0, 0, 0, vbytes, 0]
+    split = rb == 8 and m <= (1 << 21)
+    if split:
+        # batches of up to 2^21 keys with 8-bit digits: the tile split reads
+        # the pairs and writes them back split, with one 256-entry row of
+        # digit starts per 2048-key tile; the per-run sort reads its column
+        # of the rows (two entries per tile), the split pairs and writes the
+        # sorted ones
+        ntiles = -(-m // 2048)
+        fam["sort_pass"] = sum(m * (kbytes + pi) + m * (kbytes + p) + ntiles * 1024
+                               for p, pi in zip(pay, pay_in))
+        fam["sort_local"] = sum(m * 2 * (kbytes + p) + 256 * ntiles * 8 for p in pay)
+    else:
+        fam["sort_hist"] = len(pay) * m * kbytes
+        # up to 2^22 keys: one device-wide pass on the top digit, then the
+        # per-run sort; otherwise P device-wide passes
+        local = rb == 8 and m <= (1 << 22)
+        fam["sort_pass"] = sum((1 if local else P) * m * 2 * (kbytes + p) for p in pay)
+        if local:
+            fam["sort_local"] = sum(m * 2 * (kbytes + p) for p in pay)
 
     def read_bytes(keys, extra_out, val_reads, hi_bytes=0, head_bytes=16):
         # every maxBucket entry, the sorted (or grouped) batch (key +
@@ -405,9 +419,9 @@ def update_heavy_rounds(args):
         for r, (di, dv, dd) in enumerate(rounds):
             kind = "uniform" if r % 2 == 0 else "clustered"
             steps = [("insert", lambda: st.insert(di, dv), ("insert_apply", "insert_wide")),
-                     ("delete", lambda: st.delete(dd), ("delete_apply",))]
+                     ("delete", lambda: st.delete(dd), ("delete_apply", "delete_wide"))]
             fam_all = ("sort_hist", "sort_pass", "sort_local", "slices", "insert_apply",
-                       "insert_wide", "delete_apply")
+                       "insert_wide", "delete_apply", "delete_wide")
             for name, fn, fams in steps:
                 st.set_timing(True)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -733,7 +747,8 @@ def main():
     log("[bench] warmup done")
 
     fams = ["sort_hist", "sort_pass", "sort_local", "read_cuts", "read_apply", "part",
-            "group_read", "slices", "insert_apply", "delete_apply", "insert_st", "insert_wide"]
+            "group_read", "slices", "insert_apply", "delete_apply", "insert_st", "insert_wide",
+            "delete_wide"]
 
     def run_steps(k):
         torch.cuda.synchronize()

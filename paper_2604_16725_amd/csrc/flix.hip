@@ -34,13 +34,15 @@ static __device__ __align__(256) u32 scratch[kNoAllocWords];
 
 namespace {
 
-constexpr int kFamilies = 12;
+constexpr int kFamilies = 13;
 const char* kFamilyNames[kFamilies] = {"sort_hist", "sort_pass", "read_apply", "slices",
                                        "insert_apply", "delete_apply", "read_cuts", "sort_local",
-                                       "part", "group_read", "insert_st", "insert_wide"};
+                                       "part", "group_read", "insert_st", "insert_wide",
+                                       "delete_wide"};
 enum Family {
   F_HIST = 0, F_PASS = 1, F_READ = 2, F_PRE = 3, F_INSERT = 4, F_DELETE = 5, F_CUTS = 6,
-  F_LOCAL = 7, F_PART = 8, F_GROUP = 9, F_INSERT_ST = 10, F_INSERT_WIDE = 11
+  F_LOCAL = 7, F_PART = 8, F_GROUP = 9, F_INSERT_ST = 10, F_INSERT_WIDE = 11,
+  F_DELETE_WIDE = 12
 };
 int sort_family(int fam) { return fam == 0 ? F_HIST : fam == 1 ? F_PASS : F_LOCAL; }
 
@@ -637,7 +639,10 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
                     (s->cfg.insert_algo == FLIX_INSERT_TL_BULK ||
                      s->cfg.insert_algo == FLIX_INSERT_ADAPTIVE) &&
                     n >= wide_min_keys(s->cap);
-  if (wide) {
+  // a long slice or a long chain of a delete goes to the workgroup-wide
+  // delete kernel
+  const bool wide_del = !insert && !m_dev && n >= kWideDelKeys;
+  if (wide || wide_del) {
     sa.wide_min = wide_min_keys(s->cap);
     sa.wide_cap = wide_slots(s->max_batch);
     sa.wide = s->work + work_slots(s->max_batch);
@@ -722,6 +727,16 @@ int update_apply_sorted(flix_store* s, bool insert, const K* skeys, const K* sva
   }
   tm_done(s, insert ? F_INSERT : F_DELETE, t);
   HIP_TRY(hipGetLastError());
+  if (wide_del) {
+    ua.wide_min = sa.wide_min;
+    ua.wide_cap = sa.wide_cap;
+    ua.wide = sa.wide;
+    const u32 grid = (u32)std::min<u64>(1024, n / kWideDelKeys + 1);
+    const TmTok tw = tm_arm(s, F_DELETE_WIDE);
+    launch_timed(tw.b, tw.e, k_delete_wide<K, 256>, dim3(grid), dim3(256), 0, st, ua);
+    tm_done(s, F_DELETE_WIDE, tw);
+    HIP_TRY(hipGetLastError());
+  }
   return FLIX_OK;
 }
 

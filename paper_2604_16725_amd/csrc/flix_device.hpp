@@ -73,7 +73,9 @@ __device__ __forceinline__ void reset_work_regions(Ctl* ctl, u32 t) {
 
 // Slots of the workgroup-wide insert list, after the work list: every item on
 // it holds at least 256 batch keys, and slices are disjoint.
-__host__ __device__ inline u32 wide_slots(u64 max_batch) { return (u32)(max_batch / 256 + 1); }
+// Wide work items: an insert slice holds at least 256 keys, a wide delete
+// slice at least 16.
+__host__ __device__ inline u32 wide_slots(u64 max_batch) { return (u32)(max_batch / 16 + 1); }
 
 // Work-list map of an apply workgroup: s_pre[r] = items in regions < r
 // (kWorkRegions + 1 entries).  All threads call; returns the item count.

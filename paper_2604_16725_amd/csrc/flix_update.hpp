@@ -29,6 +29,19 @@ struct alignas(16) WorkItem {
 };
 constexpr u32 kSingleNode = 0x80000000u;
 
+// Delete items for the workgroup-wide delete (k_delete_wide): a slice of at
+// least `wide_min` keys, or at least kWideDelKeys keys into a chain of at
+// least kWideDelChain nodes.  The slice kernel sets kWideItem in their head
+// word and lists them; the lane-group delete skips them.
+constexpr u32 kWideDelChain = 8;
+constexpr u32 kWideDelKeys = 16;
+constexpr u32 kWideItem = 0x40000000u;
+
+__device__ __forceinline__ bool wide_delete_item(u32 len, u32 chain_nodes, u32 wide_min) {
+  return wide_min != 0 &&
+         (len >= wide_min || (chain_nodes >= kWideDelChain && len >= kWideDelKeys));
+}
+
 template <typename K>
 struct SliceArgs {
   const K* skeys;
@@ -215,6 +228,10 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
         const NodeHdr h = a.hdr[b];
         const bool single = h.next == kNil;
         info[r] = h.size | (single ? kSingleNode : 0u);
+        // a long slice or a long chain goes to the workgroup-wide delete
+        if (!INSERT && a.wide_min &&
+            wide_delete_item(e - s, single ? 1u : a.bnodes[b], a.wide_min))
+          info[r] |= kWideItem;
         if (INSERT) {
           // live keys inside this share, plus (bucket 0 only) every key before
           // q0 counted as live: an upper bound is all the budget needs
@@ -265,7 +282,7 @@ __device__ void slices_share(const SliceArgs<K>& a, u32 vb, SliceSmem<K, S, NT>&
         it.e = e;
         it.head = info[r];
         a.work[w++] = it;
-        if (a.wide_min && e - s >= a.wide_min) {
+        if (INSERT ? (a.wide_min && e - s >= a.wide_min) : (it.head & kWideItem) != 0) {
           const u32 k = atomicAdd(&a.ctl->wide_n, 1u);
           if (k < a.wide_cap) a.wide[k] = it;
           else atomicCAS(&a.ctl->status, 0u, kErrInternal);   // bound violated: never expected
@@ -1217,6 +1234,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       cur.move(sh.pre, it + stride);
       wnext = a.work[cur.slot(it + stride, a.rcap)];
     }
+    if (w.head & kWideItem) continue;   // k_delete_wide takes it
     // predecessor state (P), kept in registers; P == kNil before the head
     u32 P = kNil;
     NodeHdr hP;
@@ -1411,6 +1429,316 @@ __global__ __launch_bounds__(NT) void k_delete_apply(UpdArgs<K> a, u32 lds_items
   extern __shared__ unsigned char s_dyn[];
   __shared__ UpdShared sh;
   delete_items<K, GL, NT>(a, lds_items, blockIdx.x, gridDim.x, s_dyn, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup-wide delete (elastic compute for a long chain, Section 3.4): the
+// lane-group delete walks a chain node by node, staging, compacting and
+// writing each touched node before it reads the next header, so a bucket
+// whose chain holds hundreds of nodes (a dense run of inserts makes one) costs
+// hundreds of dependent rounds.  Here one workgroup takes such a bucket:
+//   1. one lane walks the headers (a window of up to kWideDelNodes nodes);
+//   2. every slice key finds its node by its fence (binary search in LDS),
+//      which gives each node its part of the slice;
+//   3. the waves compact the touched nodes in parallel (a key of the node
+//      that is in its part is removed; survivors move left);
+//   4. one lane replays the structure rule of the lane-group delete over the
+//      new sizes, in chain order (a node joins its predecessor when their
+//      sizes sum to at most cap/2, when it is empty, or when the predecessor
+//      is the emptied head; the walk ends once the slice is consumed and the
+//      predecessor neither is the emptied head nor changed to at most cap/2),
+//      writing headers as it goes;
+//   5. the waves append every joined node's survivors to its predecessor and
+//      the joined nodes go back to the free list.
+// The result is the lane-group kernel's, node for node.
+// ---------------------------------------------------------------------------
+constexpr u32 kWideDelNodes = 512;     // nodes per window
+constexpr u32 kWideDelStage = 256;     // slice keys a wave stages per node
+
+constexpr int NTW = 256;   // threads of the wide delete kernel
+
+template <typename K>
+struct WideDelLds {
+  u32 id[kWideDelNodes];
+  u32 next[kWideDelNodes];
+  u32 size[kWideDelNodes];      // before compaction, then after
+  u32 cnt[kWideDelNodes + 1];   // slice keys per node, then where each node's part starts
+  u32 dst[kWideDelNodes];       // node that takes this node's survivors (kNil: none)
+  u32 off[kWideDelNodes];       // their first slot there
+  u32 tl[kWideDelNodes];        // touched nodes of the window
+  u32 jl[kWideDelNodes];        // joined nodes of the window, in chain order
+  u64 fence[kWideDelNodes];
+  u32 tmp[NTW / 64 + 1];
+  u32 ntl;
+  K stg[4][kWideDelStage];      // per wave: the part of the slice of its node
+  u32 nw;                       // nodes in this window
+  u32 j0;                       // slice position where this window's parts begin
+  u32 cont;                     // node after the window (kNil: the chain ends in it)
+  u32 stop;                     // the structure walk has ended
+  u32 nfree;                    // nodes of this window returned to the free list
+  u32 free_base;
+  u32 bad;
+  u32 removed;
+  // predecessor, carried across windows
+  u32 P, Psize, Pnext, Pdirty, Phead;
+  u64 Pfence;
+  u32 freed_total;
+  u32 was_empty;
+  u32 walked;                   // nodes walked so far
+};
+
+template <typename K, int NT>
+__device__ void wide_delete_bucket(const UpdArgs<K>& a, const WorkItem& w, WideDelLds<K>& L) {
+  static_assert(NT == 256, "four waves, one staging row each");
+  const u32 tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+  constexpr u32 NW = NT / 64;
+  const u32 f = a.cap / 2;
+  if (tid == 0) {
+    L.cont = w.b;
+    L.j0 = w.s;
+    L.stop = 0;
+    L.bad = 0;
+    L.removed = 0;
+    L.P = kNil;
+    L.Psize = 0;
+    L.Pnext = kNil;
+    L.Pdirty = 0;
+    L.Phead = 0;
+    L.Pfence = 0;
+    L.freed_total = 0;
+    L.was_empty = 0;
+    L.walked = 0;
+  }
+  __syncthreads();
+  while (true) {
+    // 1. walk the next window of the chain (one lane)
+    if (tid == 0) {
+      u32 X = L.cont;
+      u32 nw = 0;
+      while (X != kNil && nw < kWideDelNodes) {
+        // a link outside the pool, or a chain longer than the pool (a
+        // cycle): never on a consistent store
+        if (X >= a.pool || ++L.walked > a.pool) {
+          L.bad = 1;
+          break;
+        }
+        const NodeHdr h = a.hdr[X];
+        if (h.size > a.cap) {
+          L.bad = 1;
+          break;
+        }
+        L.id[nw] = X;
+        L.next[nw] = h.next;
+        L.size[nw] = h.size;
+        L.fence[nw] = h.fence;
+        ++nw;
+        X = h.next;
+      }
+      L.nw = nw;
+      L.cont = X;
+      if (L.bad) atomicCAS(a.status, 0u, kErrInternal);
+      if (L.P == kNil && nw > 0) L.was_empty = (L.size[0] == 0 && L.next[0] == kNil) ? 1u : 0u;
+    }
+    for (u32 i = tid; i <= kWideDelNodes; i += NT) L.cnt[i] = 0;
+    __syncthreads();
+    if (L.bad) return;
+    const u32 nw = L.nw;
+    const u32 j0 = L.j0;
+    const bool last_window = L.cont == kNil;
+    // 2. the node of every slice key from j0 on: the first node of the window
+    //    whose fence is >= the key; the chain's last node takes the rest;
+    //    keys past this window's last fence belong to later windows
+    for (u32 j = j0 + tid; j < w.e; j += NT) {
+      const K k = a.skeys[j];
+      u32 lo = 0, hi = nw;
+      while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (L.fence[mid] < (u64)k) lo = mid + 1; else hi = mid;
+      }
+      if (lo == nw && last_window) lo = nw - 1;
+      if (lo < nw) atomicAdd(&L.cnt[lo], 1u);
+    }
+    if (tid == 0) L.ntl = 0;
+    __syncthreads();
+    {
+      // where every node's part starts (two nodes per thread), and the list
+      // of touched nodes
+      static_assert(kWideDelNodes == 2 * NT, "two window nodes per thread");
+      const u32 c0 = 2 * tid < nw ? L.cnt[2 * tid] : 0u;
+      const u32 c1 = 2 * tid + 1 < nw ? L.cnt[2 * tid + 1] : 0u;
+      u32 total;
+      const u32 ex = block_exclusive_scan<NT>(c0 + c1, L.tmp, &total);
+      if (2 * tid < nw) {
+        L.cnt[2 * tid] = j0 + ex;
+        if (c0) L.tl[atomicAdd(&L.ntl, 1u)] = 2 * tid;
+      }
+      if (2 * tid + 1 < nw) {
+        L.cnt[2 * tid + 1] = j0 + ex + c0;
+        if (c1) L.tl[atomicAdd(&L.ntl, 1u)] = 2 * tid + 1;
+      }
+      if (tid == 0) L.cnt[nw] = j0 + total;
+    }
+    __syncthreads();
+    // 3. compaction of the touched nodes, one wave per node
+    u32 removed = 0;
+    const u32 ntl = L.ntl;
+    for (u32 ti = wv; ti < ntl; ti += NW) {
+      const u32 i = L.tl[ti];
+      const u32 s = L.cnt[i], e = L.cnt[i + 1];
+      const u32 X = L.id[i];
+      const u32 S = L.size[i];
+      const u32 t = e - s;
+      const bool staged = t <= kWideDelStage;
+      if (staged)
+        for (u32 q = lane; q < t; q += 64) L.stg[wv][q] = a.skeys[s + q];
+      wave_lds_sync();
+      K* const xk = a.nkeys + (u64)X * a.cap;
+      K* const xv = a.nvals + (u64)X * a.cap;
+      u32 kept = 0;
+      for (u32 i0 = 0; i0 < S; i0 += 64) {
+        const u32 p = i0 + lane;
+        bool keep = false;
+        K kk = K(0), vv = K(0);
+        if (p < S) {
+          kk = xk[p];
+          vv = xv[p];
+          u32 q;
+          if (staged) {
+            q = lower_bound_idx<K>(L.stg[wv], 0u, t, kk);
+            keep = !(q < t && L.stg[wv][q] == kk);
+          } else {
+            q = lower_bound_idx<K>(a.skeys, s, e, kk);
+            keep = !(q < e && a.skeys[q] == kk);
+          }
+        }
+        const u64 km = wave_ballot(keep);
+        const u32 dstp = kept + rank_below(km);
+        // survivors only move left, and every load of this step is complete
+        // before its stores (they use the loaded values)
+        if (keep && dstp != p) {
+          xk[dstp] = kk;
+          xv[dstp] = vv;
+        }
+        kept += (u32)__popcll(km);
+      }
+      if (lane == 0) L.size[i] = kept;
+      removed += S - kept;
+    }
+    if (lane == 0 && removed) atomicAdd(&L.removed, removed);
+    __syncthreads();
+    // 4. the structure rule in chain order, from the carried predecessor
+    if (tid == 0) {
+      u32 P = L.P, Psize = L.Psize, Pnext = L.Pnext, Pdirty = L.Pdirty, Phead = L.Phead;
+      u64 Pfence = L.Pfence;
+      u32 nfree = 0;
+      u32 i = 0;
+      bool stop = false;
+      for (; i < nw; ++i) {
+        if (P != kNil) {
+          // the lane-group walk reaches node i only while this holds
+          const bool more = L.cnt[i] < w.e || (Phead && Psize == 0) || (Pdirty && Psize <= f);
+          if (!more) {
+            stop = true;
+            break;
+          }
+        }
+        const u32 sx = L.size[i];
+        const bool touched = L.cnt[i + 1] > L.cnt[i];
+        const bool join = P != kNil && (Psize + sx <= f || sx == 0 || (Phead && Psize == 0));
+        if (join) {
+          L.dst[i] = P;
+          L.off[i] = Psize;
+          L.jl[nfree] = i;
+          Psize += sx;
+          Pfence = L.fence[i];
+          Pnext = L.next[i];
+          Pdirty = 1;
+          ++nfree;
+        } else {
+          if (P != kNil && Pdirty) {
+            NodeHdr h;
+            h.fence = Pfence;
+            h.size = Psize;
+            h.next = Pnext;
+            a.hdr[P] = h;
+          }
+          P = L.id[i];
+          Psize = sx;
+          Pfence = L.fence[i];
+          Pnext = L.next[i];
+          Pdirty = touched ? 1u : 0u;
+          Phead = P == w.b ? 1u : 0u;
+        }
+      }
+      if (stop || last_window) {
+        if (P != kNil && Pdirty) {
+          NodeHdr h;
+          h.fence = Pfence;
+          h.size = Psize;
+          h.next = Pnext;
+          a.hdr[P] = h;
+        }
+        stop = true;
+      }
+      L.P = P;
+      L.Psize = Psize;
+      L.Pnext = Pnext;
+      L.Pdirty = Pdirty;
+      L.Phead = Phead;
+      L.Pfence = Pfence;
+      L.stop = stop ? 1u : 0u;
+      L.nfree = nfree;
+      if (nfree) {
+        const u32 base = atomicAdd(&a.ctl->free_top, nfree);
+        L.free_base = base;
+        if ((u64)base + nfree > a.pool) {   // more frees than nodes: never expected
+          atomicCAS(a.status, 0u, kErrInternal);
+          L.nfree = 0;
+        }
+      }
+      L.freed_total += nfree;
+      L.j0 = L.cnt[nw];
+    }
+    __syncthreads();
+    // 5. survivors of the joined nodes to their predecessors; freed ids
+    const u32 nj = L.nfree;
+    for (u32 q0 = wv; q0 < nj; q0 += NW) {
+      const u32 i = L.jl[q0];
+      const u32 D = L.dst[i];
+      const u32 X = L.id[i];
+      const u32 sx = L.size[i];
+      const u32 o = L.off[i];
+      for (u32 q = lane; q < sx; q += 64) {
+        a.nkeys[(u64)D * a.cap + o + q] = a.nkeys[(u64)X * a.cap + q];
+        a.nvals[(u64)D * a.cap + o + q] = a.nvals[(u64)X * a.cap + q];
+      }
+      if (lane == 0) a.free_ids[L.free_base + q0] = X;
+    }
+    __syncthreads();
+    if (L.stop) break;
+  }
+  if (tid == 0) {
+    if (L.freed_total) a.bnodes[w.b] -= L.freed_total;
+    // an emptied bucket ends with its head as predecessor, size 0, no link
+    if (!L.was_empty && L.P == w.b && L.Psize == 0 && L.Pnext == kNil) occ_clear(a.occ, w.b);
+    if (L.removed)
+      atomicAdd((unsigned long long*)&a.ctl->nkeys, (unsigned long long)(0ull - (u64)L.removed));
+  }
+  __syncthreads();   // LDS is reused by the next item
+}
+
+// The slice kernel lists the wide delete items; workgroup g takes items g,
+// g + G, ...
+template <typename K, int NT>
+__global__ __launch_bounds__(NT) void k_delete_wide(UpdArgs<K> a) {
+  __shared__ WideDelLds<K> L;
+  const Ctl* ctl = a.ctl;
+  if (ctl->call_abort != 0) return;   // an epoch rejected as a whole
+  const u32 n = ctl->wide_n < a.wide_cap ? ctl->wide_n : a.wide_cap;
+  for (u32 i = blockIdx.x; i < n; i += gridDim.x) {
+    const WorkItem w = a.wide[i];
+    wide_delete_bucket<K, NT>(a, w, L);
+  }
 }
 
 }  // namespace flix
