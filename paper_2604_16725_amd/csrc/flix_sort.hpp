@@ -1100,11 +1100,25 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
   // block of X items, which keep their input order (stable).
   {
     const K X = ks[run_src(m, ntiles, cnt / 2)];
-    u32 nrest = 0;
-    bool fits = true;
+    // the form only pays when X holds a good share of the run (a skewed
+    // batch); 64 evenly spaced samples decide, so a run of many distinct
+    // keys (a clustered batch) goes straight to the global passes
+    if (tid < 64u) {
+      const u32 li = (u32)(((u64)cnt * tid) / 64u);
+      const u64 bm = wave_ballot(ks[run_src(m, ntiles, li)] == X);
+      if (tid == 0) m.red[1] = (u32)__popcll(bm);
+    }
+    __syncthreads();
+    const bool try_dominant = m.red[1] >= 16u;
+    // the X items' payloads go to the run's region of the extra buffer in
+    // input order as they are met, and are copied behind the smaller keys
+    // once their number is known
+    V* const xvr0 = vx + base;
+    u32 nrest = 0, xbase = 0;
+    bool fits = try_dominant;
     K kand = ~K(0), kor = K(0);
-    for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
-      bool rest[IPT];
+    for (u32 base0 = 0; fits && base0 < cnt; base0 += kLocalCap) {
+      bool rest[IPT], isx[IPT];
 #pragma unroll
       for (int k = 0; k < IPT; ++k) {
         const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
@@ -1116,6 +1130,7 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
           if (PAY != kPayNone) pay[k] = vs[src];
         }
         rest[k] = valid && key[k] != X;
+        isx[k] = valid && key[k] == X;
         if (rest[k]) {
           kand &= key[k];
           kor |= key[k];
@@ -1134,6 +1149,18 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
         }
       }
       nrest += tot;
+      // every valid item is X or not, and valid items are a prefix of the
+      // chunk, so an X item's rank among the chunk's X items is its position
+      // less the non-X items before it
+      if (PAY != kPayNone) {
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          const u32 pos = w * 64u * IPT + (u32)k * 64u + lane;
+          if (isx[k]) xvr0[xbase + pos - rank[k]] = pay[k];
+        }
+      }
+      const u32 valid_n = cnt - base0 < kLocalCap ? cnt - base0 : kLocalCap;
+      xbase += valid_n - tot;
     }
     if (fits) {
       __syncthreads();
@@ -1167,29 +1194,23 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
           if (PAY != kPayNone) ovr[o] = pay[k];
         }
       }
-      // the X items in input order
-      u32 xbase = 0;
-      for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
-        bool isx[IPT];
+      // the X block (the payload copies were written by other threads before
+      // the barriers above); IPT loads in flight per thread before the stores
+      for (u32 i0 = 0; i0 < neq; i0 += kLocalNT * IPT) {
+        V xv[IPT];
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-          const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
-          isx[k] = false;
-          if (li < cnt) {
-            const u32 src = run_src(m, ntiles, li);
-            isx[k] = ks[src] == X;
-            if (PAY != kPayNone) pay[k] = vs[src];
-          }
+          const u32 i = i0 + (u32)k * kLocalNT + tid;
+          if (PAY != kPayNone && i < neq) xv[k] = xvr0[i];
         }
-        const u32 tot = local_class_rank(isx, rank, h);
 #pragma unroll
         for (int k = 0; k < IPT; ++k) {
-          if (isx[k]) {
-            okr[nlt + xbase + rank[k]] = X;
-            if (PAY != kPayNone) ovr[nlt + xbase + rank[k]] = pay[k];
+          const u32 i = i0 + (u32)k * kLocalNT + tid;
+          if (i < neq) {
+            okr[nlt + i] = X;
+            if (PAY != kPayNone) ovr[nlt + i] = xv[k];
           }
         }
-        xbase += tot;
       }
       return;
     }
@@ -1200,9 +1221,25 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
   // the split tiles; the passes alternate between the run's region of the
   // extra buffer and of the output so that the last one writes the output.
   // The digit counts of every pass come from one sweep over the run first (a
-  // pass only permutes the run).
+  // pass only permutes the run), after an AND/OR sweep has found the digits
+  // that vary inside it: only those are counted and passed over.
+  u32 vary;
+  {
+    K kand = ~K(0), kor = K(0);
+    for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base0 + (u32)k * kLocalNT + tid;
+        if (li < cnt) {
+          const K kk = ks[run_src(m, ntiles, li)];
+          kand &= kk;
+          kor |= kk;
+        }
+      }
+    }
+    vary = varying_digits<K>(kand, kor, npass, m.red);
+  }
   for (u32 i = tid; i < npass * 256u; i += kLocalNT) (&h.hist[0][0])[i] = 0;
-  if (tid == 0) m.red[0] = 0;
   __syncthreads();
   for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
 #pragma unroll
@@ -1220,6 +1257,7 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
       if (vm == 0) continue;   // uniform across the wave
       const int src = __ffsll((unsigned long long)vm) - 1;
       for (u32 p = 0; p < npass; ++p) {
+        if (!((vary >> p) & 1u)) continue;   // uniform across the workgroup
         const u32 dg = digit_of<K, 8>(key[k], p * 8u);
         const u32 d0 = (u32)__shfl((int)dg, src, 64);
         const u64 same = wave_ballot(valid && dg == d0);
@@ -1229,15 +1267,7 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
     }
   }
   __syncthreads();
-  // a digit is trivial when one value holds the whole run
-  if (tid < 256u) {
-    u32 t = 0;
-    for (u32 p = 0; p < npass; ++p)
-      if (h.hist[p][tid] == cnt) t |= 1u << p;
-    if (t) atomicOr(&m.red[0], t);
-  }
-  __syncthreads();
-  const u32 passes = ~m.red[0] & ((1u << npass) - 1u);
+  const u32 passes = vary;
   const u32 npasses = (u32)__popc(passes);
   K* const xkr = kx + base;
   V* const xvr = vx + base;
