@@ -893,7 +893,7 @@ def main():
         bufs = {"lookup": dl, "successor": ds, "range_lo": dlo, "range_hi": dhi, "ol": ol,
                 "sk": sk, "sv": sv, "rc": rc, "rk": rk, "rv": rv, "L": L}
         grown = leg("grown_store", grown_store_reads, args, wl, dev, bufs)
-    gap = leg("successor_gap", successor_across_gap, args)
+    gap = None if args.no_breakdown else leg("successor_gap", successor_across_gap, args)
     update_heavy = leg("update_heavy", update_heavy_rounds, args) if args.update_rounds > 0 else None
     insert_kernels = None if args.no_insert_kernels else leg("insert_kernels", insert_kernel_choice,
                                                                args)
