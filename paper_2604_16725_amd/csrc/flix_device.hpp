@@ -147,6 +147,24 @@ __device__ __forceinline__ u32 rank_below(u64 m) {
 
 __device__ __forceinline__ u64 wave_ballot(bool p) { return __ballot(p); }
 
+// Lanes (among `valid`) whose RB-bit digit d equals this lane's: a lane
+// differs from another where some bit of their digits differs, i.e. where the
+// ballot of that bit differs from this lane's bit widened to 0 or all ones;
+// OR over the bits, complemented.  (RB ballots; per bit one XOR and one OR per
+// 32-bit half.)
+template <int RB>
+__device__ __forceinline__ u64 match_digit(u32 d, u64 valid) {
+  u32 x0 = 0, x1 = 0;
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const u32 t = (u32)((int)(d << (31 - b)) >> 31);   // bit b as 0 or all ones
+    const u64 bb = wave_ballot(t != 0u);
+    x0 |= (u32)bb ^ t;
+    x1 |= (u32)(bb >> 32) ^ t;
+  }
+  return valid & ~(((u64)x1 << 32) | (u64)x0);
+}
+
 // Orders a wave's LDS writes before its later LDS reads (by any of its lanes).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

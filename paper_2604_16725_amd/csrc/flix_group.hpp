@@ -477,13 +477,7 @@ __global__ __launch_bounds__(NT) void k_group_read(GroupArgs<K> ga, ReadArgs<K> 
       const u32 li = w * 64u * IPT + (u32)k * 64u + lane;
       const bool valid = li < m;
       const u32 d = digit_of<K, 8>(key[k], shift);
-      u64 msk = wave_ballot(valid);
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const u64 bb = wave_ballot(bit);
-        msk &= bit ? bb : ~bb;
-      }
+      const u64 msk = match_digit<8>(d, wave_ballot(valid));
       const u32 below = rank_below(msk);
       const u32 cnt = (u32)__popcll(msk);
       const u32 base = valid ? s_wc[w][d] : 0u;

@@ -213,13 +213,7 @@ __device__ void onesweep_tile(const PassArgs<K, V>& pa, u32 tile,
     u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
     bool valid = idx < n;
     u32 d = digit_of<K, RB>(key[k], shift);
-    u64 m = wave_ballot(valid);
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      bool bit = (d >> b) & 1u;
-      u64 bb = wave_ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
+    const u64 m = match_digit<RB>(d, wave_ballot(valid));
     u32 below = rank_below(m);
     u32 cnt = __popcll(m);
     u32 base = valid ? s_wc[w][d] : 0u;
@@ -405,13 +399,7 @@ __device__ __forceinline__ void local_rank(const K (&key)[kLocalIPT], u32 nvalid
     const u32 li = nvalid_base + w * 64u * kLocalIPT + (u32)k * 64u + lane;
     const bool valid = li < n;
     const u32 d = digit_of<K, 8>(key[k], shift);
-    u64 m = wave_ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const u64 bb = wave_ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
+    const u64 m = match_digit<8>(d, wave_ballot(valid));
     const u32 below = rank_below(m);
     const u32 cnt = (u32)__popcll(m);
     const u32 base = valid ? h.wc[w][d] : 0u;
@@ -796,13 +784,7 @@ __global__ __launch_bounds__(kSplitNT) void k_tile_split(const K* __restrict__ k
     const u32 idx = tile0 + w * 64u * IPT + (u32)k * 64u + lane;
     const bool valid = idx < n;
     const u32 d = digit_of<K, 8>(key[k], shift);
-    u64 m = wave_ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const u64 bb = wave_ballot(bit);
-      m &= bit ? bb : ~bb;
-    }
+    const u64 m = match_digit<8>(d, wave_ballot(valid));
     const u32 below = rank_below(m);
     const u32 cnt = (u32)__popcll(m);
     const u32 base = valid ? sm.wc[w][d] : 0u;
@@ -929,14 +911,9 @@ __device__ void run_lds_passes(K (&key)[kLocalIPT], V (&pay)[kLocalIPT], u32 cnt
         const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
         const bool valid = li < cnt;
         const u32 d = digit_of<K, 8>(key[k], shift);
-        u64 m = wave_ballot(valid);
-        if (m) {
-#pragma unroll
-          for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const u64 bb = wave_ballot(bit);
-            m &= bit ? bb : ~bb;
-          }
+        const u64 vm = wave_ballot(valid);
+        if (vm) {
+          const u64 m = match_digit<8>(d, vm);
           const u32 below = rank_below(m);
           const u32 c = (u32)__popcll(m);
           const u32 base = valid ? h.wc[w][d] : 0u;
