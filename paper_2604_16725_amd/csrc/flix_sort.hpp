@@ -1079,14 +1079,18 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
     const K X = ks[run_src(m, ntiles, cnt / 2)];
     // the form only pays when X holds a good share of the run (a skewed
     // batch); 64 evenly spaced samples decide, so a run of many distinct
-    // keys (a clustered batch) goes straight to the global passes
+    // keys (a clustered batch) goes straight to the split below
     if (tid < 64u) {
       const u32 li = (u32)(((u64)cnt * tid) / 64u);
       const u64 bm = wave_ballot(ks[run_src(m, ntiles, li)] == X);
       if (tid == 0) m.red[1] = (u32)__popcll(bm);
     }
     __syncthreads();
-    const bool try_dominant = m.red[1] >= 16u;
+    // (and only when the samples leave the other items room in LDS: a run
+    // of two or three hot keys goes to the split below at once)
+    const u32 same = m.red[1];
+    const bool try_dominant =
+        same >= 16u && (u64)cnt * (64u - same) <= (u64)kLocalCap * 58u;
     // the X items' payloads go to the run's region of the extra buffer in
     // input order as they are met, and are copied behind the smaller keys
     // once their number is known
@@ -1193,100 +1197,102 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
     }
     __syncthreads();
   }
-  // A long run of many keys: LSD passes in global memory, chunk by chunk in
-  // order, over the digits that vary inside the run.  The first pass reads
-  // the split tiles; the passes alternate between the run's region of the
-  // extra buffer and of the output so that the last one writes the output.
-  // The digit counts of every pass come from one sweep over the run first (a
-  // pass only permutes the run), after an AND/OR sweep has found the digits
-  // that vary inside it: only those are counted and passed over.
-  u32 vary;
-  {
+  // A long run of many keys.  An AND/OR sweep finds the digits that vary
+  // inside it; the run is split stably on the highest of them into the extra
+  // buffer (one histogram sweep, one pass), which leaves 256 sub-runs in
+  // order.  Consecutive sub-runs are then taken in groups of up to kLocalCap
+  // items and sorted in registers and LDS on the digits that vary inside the
+  // group (the digits above the split one are constant in the run, so each
+  // group only needs its own order); a sub-run longer than kLocalCap is
+  // sorted by chunked global passes over its varying digits.  Everything is
+  // written at the group's or sub-run's place in the output.
+  K* const xkr = kx + base;
+  V* const xvr = vx + base;
+  // key of item i: from the split tiles (mapped) or a contiguous region
+  auto load_key = [&](bool mapped, const K* ik, u32 i) -> K {
+    return mapped ? ks[run_src(m, ntiles, i)] : ik[i];
+  };
+  // digits (below `below`) that vary among n items
+  auto sweep_vary = [&](bool mapped, const K* ik, u32 n, u32 below) -> u32 {
     K kand = ~K(0), kor = K(0);
-    for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+    for (u32 base0 = 0; base0 < n; base0 += kLocalCap) {
 #pragma unroll
       for (int k = 0; k < IPT; ++k) {
         const u32 li = base0 + (u32)k * kLocalNT + tid;
-        if (li < cnt) {
-          const K kk = ks[run_src(m, ntiles, li)];
+        if (li < n) {
+          const K kk = load_key(mapped, ik, li);
           kand &= kk;
           kor |= kk;
         }
       }
     }
-    vary = varying_digits<K>(kand, kor, npass, m.red);
-  }
-  for (u32 i = tid; i < npass * 256u; i += kLocalNT) (&h.hist[0][0])[i] = 0;
-  __syncthreads();
-  for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+    return varying_digits<K>(kand, kor, npass, m.red) & ((1u << below) - 1u);
+  };
+  // digit histograms (digits in `mask`) of n items into h.hist
+  auto sweep_hist = [&](bool mapped, const K* ik, u32 n, u32 mask) {
+    for (u32 i = tid; i < npass * 256u; i += kLocalNT)
+      if ((mask >> (i / 256u)) & 1u) (&h.hist[0][0])[i] = 0;
+    __syncthreads();
+    for (u32 base0 = 0; base0 < n; base0 += kLocalCap) {
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      const u32 li = base0 + (u32)k * kLocalNT + tid;
-      key[k] = li < cnt ? ks[run_src(m, ntiles, li)] : K(0);
-    }
-    // Skewed runs repeat a few keys: the wave's most common case, the first
-    // valid lane's digit, is added once with its lane count, the other lanes
-    // add one each (LDS atomics on one address would serialise the wave).
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = base0 + (u32)k * kLocalNT + tid;
+        key[k] = li < n ? load_key(mapped, ik, li) : K(0);
+      }
+      // Skewed runs repeat a few keys: the wave's most common case, the first
+      // valid lane's digit, is added once with its lane count, the other lanes
+      // add one each (LDS atomics on one address would serialise the wave).
 #pragma unroll
-    for (int k = 0; k < IPT; ++k) {
-      const bool valid = base0 + (u32)k * kLocalNT + tid < cnt;
-      const u64 vm = wave_ballot(valid);
-      if (vm == 0) continue;   // uniform across the wave
-      const int src = __ffsll((unsigned long long)vm) - 1;
-      for (u32 p = 0; p < npass; ++p) {
-        if (!((vary >> p) & 1u)) continue;   // uniform across the workgroup
-        const u32 dg = digit_of<K, 8>(key[k], p * 8u);
-        const u32 d0 = (u32)__shfl((int)dg, src, 64);
-        const u64 same = wave_ballot(valid && dg == d0);
-        if ((int)lane == src) atomicAdd(&h.hist[p][d0], (u32)__popcll(same));
-        if (valid && dg != d0) atomicAdd(&h.hist[p][dg], 1u);
+      for (int k = 0; k < IPT; ++k) {
+        const bool valid = base0 + (u32)k * kLocalNT + tid < n;
+        const u64 vm = wave_ballot(valid);
+        if (vm == 0) continue;   // uniform across the wave
+        const int src = __ffsll((unsigned long long)vm) - 1;
+        for (u32 p = 0; p < npass; ++p) {
+          if (!((mask >> p) & 1u)) continue;   // uniform across the workgroup
+          const u32 dg = digit_of<K, 8>(key[k], p * 8u);
+          const u32 d0 = (u32)__shfl((int)dg, src, 64);
+          const u64 same = wave_ballot(valid && dg == d0);
+          if ((int)lane == src) atomicAdd(&h.hist[p][d0], (u32)__popcll(same));
+          if (valid && dg != d0) atomicAdd(&h.hist[p][dg], 1u);
+        }
       }
     }
-  }
-  __syncthreads();
-  const u32 passes = vary;
-  const u32 npasses = (u32)__popc(passes);
-  K* const xkr = kx + base;
-  V* const xvr = vx + base;
-  u32 done = 0;
-  for (u32 p = 0; p < npass; ++p) {
-    if (!((passes >> p) & 1u)) continue;
+    __syncthreads();
+  };
+  // h.off = exclusive prefix of the histogram of digit p
+  auto digit_starts = [&](u32 p) {
+    const u32 cc = tid < 256u ? h.hist[p][tid] : 0u;
+    u32 dummy;
+    const u32 ex = block_exclusive_scan<kLocalNT>(cc, h.tmp, &dummy);
+    if (tid < 256u) h.off[tid] = ex;
+    __syncthreads();
+  };
+  // one stable counting pass on digit p over n items, chunk by chunk in
+  // order, from the tiles or (ik, iv) to (ok, ov); h.off holds the starts
+  auto chunk_pass = [&](bool mapped, const K* ik, const V* iv, u32 n, u32 p, K* ok, V* ov) {
     const u32 shift = p * 8u;
-    const bool first = done == 0;
-    const bool to_out = ((npasses - 1u - done) & 1u) == 0u;
-    // the previous pass wrote the other region
-    const K* ik = to_out ? xkr : okr;
-    const V* iv = to_out ? xvr : ovr;
-    K* ok = to_out ? okr : xkr;
-    V* ov = to_out ? ovr : xvr;
-    {
-      const u32 cc = tid < 256u ? h.hist[p][tid] : 0u;
-      u32 dummy;
-      const u32 ex = block_exclusive_scan<kLocalNT>(cc, h.tmp, &dummy);
-      if (tid < 256u) h.off[tid] = ex;
-      __syncthreads();
-    }
-    for (u32 base0 = 0; base0 < cnt; base0 += kLocalCap) {
+    for (u32 base0 = 0; base0 < n; base0 += kLocalCap) {
 #pragma unroll
       for (int k = 0; k < IPT; ++k) {
         const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
         key[k] = K(0);
-        if (li < cnt) {
-          const u32 src = first ? run_src(m, ntiles, li) : li;
-          key[k] = first ? ks[src] : ik[src];
-          if (PAY != kPayNone) pay[k] = first ? vs[src] : iv[src];
+        if (li < n) {
+          const u32 src = mapped ? run_src(m, ntiles, li) : li;
+          key[k] = mapped ? ks[src] : ik[src];
+          if (PAY != kPayNone) pay[k] = mapped ? vs[src] : iv[src];
         }
       }
       for (u32 i = tid; i < (kLocalNT / 64) * 256u; i += kLocalNT) (&h.wc[0][0])[i] = 0;
       __syncthreads();
-      local_rank<K>(key, base0, cnt, shift, h, rank);
+      local_rank<K>(key, base0, n, shift, h, rank);
       __syncthreads();
       const u32 tot = local_wave_prefix(h);
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < IPT; ++k) {
         const u32 li = base0 + w * 64u * IPT + (u32)k * 64u + lane;
-        if (li < cnt) {
+        if (li < n) {
           const u32 dg = digit_of<K, 8>(key[k], shift);
           const u32 pos = h.off[dg] + h.wc[w][dg] + rank[k];
           ok[pos] = key[k];
@@ -1297,14 +1303,96 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
       if (tid < 256u) h.off[tid] += tot;
       __syncthreads();
     }
-    ++done;
-  }
-  if (npasses == 0) {   // every key of the run is equal: copy it in order
-    for (u32 li = tid; li < cnt; li += kLocalNT) {
-      const u32 src = run_src(m, ntiles, li);
-      okr[li] = ks[src];
-      if (PAY != kPayNone) ovr[li] = vs[src];
+  };
+  // n contiguous items copied in order
+  auto copy_items = [&](bool mapped, const K* ik, const V* iv, u32 n, K* ok, V* ov) {
+    for (u32 li = tid; li < n; li += kLocalNT) {
+      const u32 src = mapped ? run_src(m, ntiles, li) : li;
+      ok[li] = mapped ? ks[src] : ik[src];
+      if (PAY != kPayNone) ov[li] = mapped ? vs[src] : iv[src];
     }
+  };
+
+  const u32 vary = sweep_vary(true, nullptr, cnt, npass);
+  if (vary == 0) {   // every key of the run is equal: copy it in order
+    copy_items(true, nullptr, nullptr, cnt, okr, ovr);
+    return;
+  }
+  const u32 ph = 31u - (u32)__clz(vary);   // highest varying digit
+  // 1. split on digit ph into the extra buffer; h.hist[ph] becomes the
+  //    sub-run starts (no later step writes that row)
+  sweep_hist(true, nullptr, cnt, 1u << ph);
+  digit_starts(ph);
+  if (tid < 256u) h.hist[ph][tid] = h.off[tid];
+  __syncthreads();
+  chunk_pass(true, nullptr, nullptr, cnt, ph, xkr, xvr);
+  // 2. the sub-runs in order
+  u32 v = 0;
+  while (v < 256u) {   // uniform: every thread reads the same LDS row
+    const u32 s0 = h.hist[ph][v];
+    u32 v2 = v;
+    while (v2 < 256u) {
+      const u32 e2 = v2 < 255u ? h.hist[ph][v2 + 1] : cnt;
+      if (e2 - s0 > kLocalCap) break;
+      ++v2;
+    }
+    if (v2 > v) {
+      // sub-runs v .. v2-1 fit LDS together: sort them there
+      const u32 n = (v2 < 256u ? h.hist[ph][v2] : cnt) - s0;
+      if (n > 0) {
+        const u32 ipt = (n + kLocalNT - 1) / kLocalNT;
+        K kand = ~K(0), kor = K(0);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+          key[k] = K(0);
+          if ((u32)k < ipt && li < n) {
+            key[k] = xkr[s0 + li];
+            if (PAY != kPayNone) pay[k] = xvr[s0 + li];
+            kand &= key[k];
+            kor |= key[k];
+          }
+        }
+        const u32 passes = varying_digits<K>(kand, kor, npass, m.red) & ((2u << ph) - 1u);
+        run_lds_passes<K, V, PAY>(key, pay, n, ipt, passes, h, s_k, s_v);
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+          const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+          if ((u32)k < ipt && li < n) {
+            okr[s0 + li] = key[k];
+            if (PAY != kPayNone) ovr[s0 + li] = pay[k];
+          }
+        }
+        __syncthreads();
+      }
+      v = v2;
+      continue;
+    }
+    // sub-run v alone is longer than kLocalCap: chunked passes over the
+    // digits (below ph) that vary inside it, from the extra buffer,
+    // alternating with the output region, the last one into the output
+    const u32 n = (v < 255u ? h.hist[ph][v + 1] : cnt) - s0;
+    K* const sxk = xkr + s0;
+    V* const sxv = xvr + s0;
+    K* const sok = okr + s0;
+    V* const sov = ovr + s0;
+    const u32 vary2 = sweep_vary(false, sxk, n, ph);
+    const u32 np2 = (u32)__popc(vary2);
+    if (np2 > 0) sweep_hist(false, sxk, n, vary2);
+    u32 done = 0;
+    for (u32 p = 0; p < ph; ++p) {
+      if (!((vary2 >> p) & 1u)) continue;
+      digit_starts(p);
+      const bool to_out = (done & 1u) == 0u;   // the input is in the extra buffer
+      chunk_pass(false, to_out ? sxk : sok, to_out ? sxv : sov, n, p, to_out ? sok : sxk,
+                 to_out ? sov : sxv);
+      ++done;
+    }
+    if ((done & 1u) == 0u) {   // an even number of passes left it in the extra buffer
+      copy_items(false, sxk, sxv, n, sok, sov);
+      __syncthreads();
+    }
+    ++v;
   }
 }
 

@@ -124,6 +124,31 @@ def test_sort_long_runs_varying_digits(kb, nvary):
 
 
 @pytest.mark.parametrize("kb", [32, 64])
+def test_sort_clustered_ranges_share_a_top_digit(kb):
+    """Ranges of consecutive keys that share a top digit (a clustered batch
+    where two or three runs land in one top digit): the long run is split on
+    its highest varying digit, then sub-runs go to LDS in groups or, when one
+    is longer than the LDS run size, through chunked passes (an even number
+    of them ends with a copy into the output)."""
+    from paper_2604_16725_amd.flix import Store
+    log(f"clustered ranges kb={kb}")
+    s = Store(key_bits=kb, capacity=64, radix_bits=8, max_batch=1 << 17)
+    rng = np.random.default_rng(60 + kb)
+    top = np.uint64(0x7E) << np.uint64(kb - 8)
+    sh = np.uint64(kb - 16)
+    starts = [top | (np.uint64(0x11) << sh), top | (np.uint64(0x93) << sh) | np.uint64(0xFF00),
+              top | (np.uint64(0xC4) << sh)]
+    lens = [16384, 9000, 300]
+    parts = [np.arange(int(a), int(a) + n, dtype=np.uint64) for a, n in zip(starts, lens)]
+    k = np.concatenate(parts + [parts[1][::7], _keys(rng, kb, 30000).astype(np.uint64)])
+    k = rng.permutation(k).astype(ktype(kb))
+    ko, io = s.sort_pairs(to_dev(k))
+    ref = np.argsort(k, kind="stable")
+    assert np.array_equal(io.cpu().numpy(), ref.astype(np.int32))
+    assert np.array_equal(to_host(ko, kb), k[ref])
+
+
+@pytest.mark.parametrize("kb", [32, 64])
 def test_sort_dominant_key_run(kb):
     """A top-digit run made mostly of one repeated key (a Zipf-skewed batch):
     the repeated key's items keep their input order between the sorted
