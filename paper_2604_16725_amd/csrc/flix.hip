@@ -98,6 +98,7 @@ struct flix_store {
   u64* occ = nullptr;    // bucket occupancy summary [occ_words(nb_alloc)]
   OccLevels occl{};      // its three levels for the current bucket count
   u32* cuts = nullptr;   // read-share cuts [(max_batch + nb_alloc) / 512 + 2]
+  u32* mktop = nullptr;  // [257] first MKBA entry of every top key digit
   // bucket groups of the read path (flix_group.hpp)
   bool grp_ok = false;   // the store's shape fits the group kernels
   u32 ngrp = 1, bpg = 1;
@@ -324,15 +325,17 @@ u32 auto_pool(const flix_store* s, u64 nbuckets) {
 // payload: 0 none, 1 index, 2 value.  Result in s->bk[r], s->bp[r].
 template <typename K>
 int sort_batch_t(flix_store* s, const K* keys, const K* vals, u32 n, int pay, hipStream_t st,
-                 int* r) {
+                 int* r, const RunCuts<K>* cuts = nullptr, bool* cuts_done = nullptr) {
   hipError_t e;
   K* k0 = (K*)s->bk[0];
   K* k1 = (K*)s->bk[1];
+  if (cuts_done) *cuts_done = false;
   if (pay == kPayIndex) {
     u32* p0 = (u32*)s->bp[0];
     u32* p1 = (u32*)s->bp[1];
     e = s->rb == 4 ? radix_sort<K, u32, 4, kPayIndex>(keys, nullptr, k0, p0, k1, p1, n, s->ss, st, r)
-                   : radix_sort<K, u32, 8, kPayIndex>(keys, nullptr, k0, p0, k1, p1, n, s->ss, st, r);
+                   : radix_sort<K, u32, 8, kPayIndex>(keys, nullptr, k0, p0, k1, p1, n, s->ss, st, r,
+                                                      cuts, cuts_done);
   } else if (pay == kPayValue) {
     K* p0 = (K*)s->bp[0];
     K* p1 = (K*)s->bp[1];
@@ -385,8 +388,8 @@ void sort_hook_end(void* ctx, int fam, hipEvent_t e0, hipEvent_t e1) {
 
 template <typename K>
 int sort_batch(flix_store* s, const void* keys, const void* vals, u64 n, int pay, hipStream_t st,
-               int* r) {
-  return sort_batch_t<K>(s, (const K*)keys, (const K*)vals, (u32)n, pay, st, r);
+               int* r, const RunCuts<K>* cuts = nullptr, bool* cuts_done = nullptr) {
+  return sort_batch_t<K>(s, (const K*)keys, (const K*)vals, (u32)n, pay, st, r, cuts, cuts_done);
 }
 
 // ---- read path --------------------------------------------------------------
@@ -404,7 +407,8 @@ struct ReadCfg<u64> {
 // Bucket kernel over an already sorted read list (keys + original index).
 template <typename K>
 int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u64 n, void* out_k,
-                      void* out_v, const void* hi, u32* counts, u32 maxpq, hipStream_t st) {
+                      void* out_v, const void* hi, u32* counts, u32 maxpq, hipStream_t st,
+                      bool cuts_ready = false) {
   ReadArgs<K> a;
   a.skeys = skeys;
   a.sidx = sidx;
@@ -428,7 +432,9 @@ int read_apply_sorted(flix_store* s, int op, const K* skeys, const u32* sidx, u6
   // cut list: half a wave per share boundary (the list holds cuts_for(max_batch,
   // nb_alloc) >= grid + 1 entries)
   a.cuts = nullptr;
-  if (s->cuts && grid + 1 <= cuts_for(s->max_batch, s->nb_alloc)) {
+  if (cuts_ready) {
+    a.cuts = s->cuts;   // written by the batch sort
+  } else if (s->cuts && grid + 1 <= cuts_for(s->max_batch, s->nb_alloc)) {
     const u32 ncuts = (u32)grid + 1u;
     const TmTok tc = tm_arm(s, F_CUTS);
     launch_timed(tc.b, tc.e, k_merge_cuts<K>, dim3((ncuts + 7) / 8), dim3(256), 0, st, skeys,
@@ -522,10 +528,24 @@ int read_batch(flix_store* s, int op, const void* keys, u64 n, void* out_k, void
   if (s->cfg.read_path == FLIX_READ_GROUPS && s->grp_ok && n <= (u64)kGroupTilesMax * kPartTile)
     return read_batch_groups<K>(s, op, (const K*)keys, n, out_k, out_v, hi, counts, maxpq, st);
   int r;
-  int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r);
+  // the run sort also writes the read kernel's share cuts when it can
+  RunCuts<K> rc_args{};
+  const u64 grid = ((u64)n + s->nb + ReadCfg<K>::S - 1) / ReadCfg<K>::S;
+  const bool want = s->cuts && s->mktop && grid + 1 <= cuts_for(s->max_batch, s->nb_alloc);
+  if (want) {
+    rc_args.mk = (const K*)s->mkba;
+    rc_args.mktop = s->mktop;
+    rc_args.nb = s->nb;
+    rc_args.share = ReadCfg<K>::S;
+    rc_args.ncuts = (u32)grid + 1u;
+    rc_args.cuts = s->cuts;
+  }
+  bool cuts_done = false;
+  int rc = sort_batch<K>(s, keys, nullptr, n, kPayIndex, st, &r, want ? &rc_args : nullptr,
+                         &cuts_done);
   if (rc) return rc;
   return read_apply_sorted<K>(s, op, (const K*)s->bk[r], (const u32*)s->bp[r], n, out_k, out_v, hi,
-                              counts, maxpq, st);
+                              counts, maxpq, st, cuts_done);
 }
 
 // ---- update path ------------------------------------------------------------
@@ -1017,6 +1037,21 @@ int dump_body(flix_store* s, void* ko, void* vo, u64 capacity, hipStream_t st) {
 // per bucket, the last key of a group is its maxBucket, KEY_MAX for the last
 // bucket).  The pool and a directory of at least nbk buckets are allocated.
 // Asynchronous on st.
+// First MKBA entry of every top key digit (the block boundaries of the read
+// cuts that the run sort writes).
+template <typename K>
+__global__ void k_mk_top(const K* __restrict__ mk, u32 nb, u32* __restrict__ top) {
+  const u32 t = threadIdx.x;
+  const K x = (K)((K)t << (sizeof(K) * 8 - 8));
+  u32 lo = 0, hi = nb;
+  while (lo < hi) {
+    const u32 mid = (lo + hi) >> 1;
+    if (mk[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  top[t] = lo;
+  if (t == 0) top[256] = nb;
+}
+
 template <typename K>
 int build_layout(flix_store* s, const K* ck, const K* cv, u64 nd, u32 nbk, hipStream_t st) {
   const u32 pool = s->pool;
@@ -1031,6 +1066,8 @@ int build_layout(flix_store* s, const K* ck, const K* cv, u64 nd, u32 nbk, hipSt
   u64 g = std::min<u64>((nbk + 255) / 256, 65536);
   hipLaunchKernelGGL((k_build_dir<K>), dim3(g), dim3(256), 0, st, ck, nd, s->fill, nbk,
                      (K*)s->mkba, s->hdr, s->bnodes);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL((k_mk_top<K>), dim3(1), dim3(256), 0, st, (const K*)s->mkba, nbk, s->mktop);
   HIP_TRY(hipGetLastError());
   // occupancy summary of the new directory
   s->occl.w0 = s->occ;
@@ -1226,6 +1263,7 @@ void destroy_all(flix_store* s) {
   dev_free(&s->ss.xk);
   dev_free(&s->ss.xv);
   s->ss.x_items = 0;
+  dev_free(&s->mktop);
   dev_free(&s->d_status);
   dev_free(&s->d_status_cl);
   dev_free(&s->d_hist);
@@ -1340,7 +1378,8 @@ int flix_create(const flix_config* cfg, void* stream, flix_store** out) {
   s->max_batch = cfg->max_batch;
   int rc = FLIX_OK;
   u64 mb = cfg->max_batch;
-  if ((rc = dev_alloc(&s->ctl, sizeof(Ctl))) || (rc = dev_alloc(&s->bk[0], mb * s->ksz)) ||
+  if ((rc = dev_alloc(&s->ctl, sizeof(Ctl))) || (rc = dev_alloc(&s->mktop, 257 * sizeof(u32))) ||
+      (rc = dev_alloc(&s->bk[0], mb * s->ksz)) ||
       (rc = dev_alloc(&s->bk[1], mb * s->ksz)) || (rc = dev_alloc(&s->bp[0], mb * 8)) ||
       (rc = dev_alloc(&s->bp[1], mb * 8)) || (rc = dev_alloc(&s->work, ((u64)work_slots(mb) + wide_slots(mb)) * sizeof(WorkItem))) ||
       (rc = dev_alloc(&s->ss.hist, 2 * 2048 * sizeof(u32))) ||

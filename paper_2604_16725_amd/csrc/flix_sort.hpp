@@ -988,6 +988,48 @@ __device__ __forceinline__ u32 lower_runs_total(const u64* status, u32 d, u32 ep
   return total;
 }
 
+// Merge-path cuts of the read kernel's shares, written by the run sort: the
+// merge of the sorted batch with the directory maxima (MKBA) is, top digit
+// by top digit, the merge of one run with the MKBA entries of that digit, so
+// the workgroup of digit d finds every cut whose diagonal falls in its block
+// [base + mktop[d], base + cnt + mktop[d + 1]) by a binary search over its
+// own run and MKBA slice (ties to the keys: a key equal to MKBA[i] belongs
+// to bucket i).  This replaces a device-wide search launch per read call.
+template <typename K>
+struct RunCuts {
+  const K* mk;          // MKBA (nb entries); null: no cuts wanted
+  const u32* mktop;     // [257] first MKBA entry of every top digit
+  u32 nb;
+  u32 share;            // merged items per share
+  u32 ncuts;            // shares + 1 (the last diagonal is the merge's end)
+  u32* cuts;
+};
+
+// Cuts of block d (all threads call; run: the sorted run (cnt keys), mks:
+// the digit's MKBA entries (nmk), both in LDS or global memory).
+template <typename K>
+__device__ void write_block_cuts(const RunCuts<K>& rc, u32 d, u32 base, u32 cnt, const K* run,
+                                 const K* mks, u32 nmk, u64 total) {
+  const u64 b0 = (u64)base + rc.mktop[d];
+  const u64 b1 = b0 + cnt + nmk;
+  const u32 c0 = (u32)((b0 + rc.share - 1) / rc.share);
+  const u32 c1 = d == 255u ? rc.ncuts : (u32)((b1 + rc.share - 1) / rc.share);
+  for (u32 c = c0 + threadIdx.x; c < c1; c += kLocalNT) {
+    u64 dd = (u64)c * rc.share;
+    if (dd > total) dd = total;
+    const u32 l = (u32)(dd - b0);   // local diagonal, at most cnt + nmk
+    // the run items among the first l items of merge(run, mks): the
+    // predicate run[p] <= mks[l - p - 1] holds exactly for p below the cut
+    u32 lo = l > nmk ? l - nmk : 0u;
+    u32 hi = l < cnt ? l : cnt;
+    while (lo < hi) {
+      const u32 mid = (lo + hi) >> 1;
+      if (run[mid] <= mks[l - mid - 1]) lo = mid + 1; else hi = mid;
+    }
+    rc.cuts[c] = base + lo;
+  }
+}
+
 template <typename K, typename V, int PAY>
 __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
                                                        const V* __restrict__ vs,
@@ -995,7 +1037,8 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
                                                        K* __restrict__ kx, V* __restrict__ vx,
                                                        const u32* __restrict__ toff,
                                                        u64* __restrict__ status, u32 epoch,
-                                                       u32 npass, u32 n, u32* __restrict__ err) {
+                                                       u32 npass, u32 n, u32* __restrict__ err,
+                                                       RunCuts<K> rcut) {
   extern __shared__ unsigned char lsm[];
   LocalSortHead& h = *reinterpret_cast<LocalSortHead*>(lsm);
   RunMap& m = *reinterpret_cast<RunMap*>(lsm + kLocalHeadBytes);
@@ -1006,6 +1049,22 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
   const u32 tid = threadIdx.x, w = tid >> 6, lane = tid & 63u;
   const u32 d = blockIdx.x;
   const u32 ntiles = (n + kSplitTile - 1) / kSplitTile;   // <= kSplitMaxTiles = blockDim
+  // the read kernel's cuts of this digit's block, once the run is in place
+  // (run: its sorted keys in LDS or in the output); the MKBA slice is staged
+  // in the payload area of LDS when it fits (the payloads are written out)
+  auto block_cuts = [&](u32 base, u32 cnt, const K* run) {
+    if (rcut.mk == nullptr) return;
+    const u32 m0 = rcut.mktop[d];
+    const u32 nmk = rcut.mktop[d + 1] - m0;
+    const K* mks = rcut.mk + m0;
+    if (PAY != kPayNone && (size_t)nmk * sizeof(K) <= (size_t)kLocalCap * sizeof(V)) {
+      K* st = reinterpret_cast<K*>(s_v);
+      for (u32 i = threadIdx.x; i < nmk; i += kLocalNT) st[i] = mks[i];
+      mks = st;
+    }
+    __syncthreads();
+    write_block_cuts<K>(rcut, d, base, cnt, run, mks, nmk, (u64)n + rcut.nb);
+  };
   // this digit's segment in every tile
   u32 c = 0;
   if (tid < ntiles) {
@@ -1027,7 +1086,10 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
     st_agent(&status[d], pack_status(epoch, kFlagAgg, cnt));
   }
   __syncthreads();
-  if (cnt == 0) return;
+  if (cnt == 0) {
+    if (rcut.mk != nullptr) block_cuts(lower_runs_total(status, d, epoch, err, h.tmp), 0u, s_k);
+    return;
+  }
   K key[IPT];
   V pay[IPT];
   if (cnt <= kLocalCap) {
@@ -1060,6 +1122,15 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
         ko[base + li] = key[k];
         if (PAY != kPayNone) vo[base + li] = pay[k];
       }
+    }
+    if (rcut.mk != nullptr) {
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < IPT; ++k) {
+        const u32 li = w * 64u * ipt + (u32)k * 64u + lane;
+        if ((u32)k < ipt && li < cnt) s_k[li] = key[k];
+      }
+      block_cuts(base, cnt, s_k);
     }
     return;
   }
@@ -1193,6 +1264,10 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
           }
         }
       }
+      if (rcut.mk != nullptr) {
+        __syncthreads();   // the run is in the output: search it there
+        block_cuts(base, cnt, okr);
+      }
       return;
     }
     __syncthreads();
@@ -1316,6 +1391,10 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
   const u32 vary = sweep_vary(true, nullptr, cnt, npass);
   if (vary == 0) {   // every key of the run is equal: copy it in order
     copy_items(true, nullptr, nullptr, cnt, okr, ovr);
+    if (rcut.mk != nullptr) {
+      __syncthreads();
+      block_cuts(base, cnt, okr);
+    }
     return;
   }
   const u32 ph = 31u - (u32)__clz(vary);   // highest varying digit
@@ -1394,6 +1473,10 @@ __global__ __launch_bounds__(kLocalNT) void k_run_sort(const K* __restrict__ ks,
     }
     ++v;
   }
+  if (rcut.mk != nullptr) {
+    __syncthreads();   // the run is in the output: search it there
+    block_cuts(base, cnt, okr);
+  }
 }
 
 // Scratch shared by every sort call of one store.
@@ -1465,7 +1548,9 @@ inline u64 sort_cluster_words(u64 max_items) {
 // `reset_status` is called when the epoch counter wraps.
 template <typename K, typename V, int RB, int PAY>
 hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u32 n,
-                      SortScratch& s, hipStream_t st, int* result_buf) {
+                      SortScratch& s, hipStream_t st, int* result_buf,
+                      const RunCuts<K>* cuts = nullptr, bool* cuts_done = nullptr) {
+  if (cuts_done) *cuts_done = false;
   constexpr int R = RadixShape<K, RB>::R;
   constexpr int P = RadixShape<K, RB>::P;
   if (n == 0) {
@@ -1503,14 +1588,17 @@ hipError_t radix_sort(const K* kin, const V* vin, K* k0, V* v0, K* k1, V* v1, u3
     }
     {
       SortTimer t(s, 2);
+      RunCuts<K> rc{};
+      if (cuts) rc = *cuts;
       launch_timed(t.e0, t.e1, k_run_sort<K, V, PAY>, dim3(R), dim3(kLocalNT), (uint32_t)lds, st,
                    (const K*)k0, (const V*)v0, k1, v1, (K*)s.xk, (V*)s.xv, (const u32*)s.toff,
-                   s.status, epoch, (u32)(P - 1), n, s.err);
+                   s.status, epoch, (u32)(P - 1), n, s.err, rc);
       t.end();
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     *result_buf = 1;
+    if (cuts_done && cuts && cuts->mk) *cuts_done = true;
     return hipSuccess;
   }
   u32* hist = s.hist + (size_t)s.parity * (P * R);
