@@ -76,7 +76,8 @@ def ensure_built():
 
 
 # ----------------------------------------------------------------------------
-# Algorithmic byte model (what the method must move)
+# Algorithmic byte model (what the method must move: directory entries, the
+# sorted batch, headers and live node lines of touched buckets, values, outputs)
 # ----------------------------------------------------------------------------
 def byte_model(wl, mkba, sizes_cap, kbytes=4, vbytes=4, rb=8, read_path="sorted"):
     """Bytes per step for every kernel family, from the actual batches."""
@@ -686,8 +687,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the store would shard by key range; see DESIGN.md). Run with --gpus 1.",
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the store would shard by key range). Run with --gpus 1.",
               file=sys.stderr, flush=True)
         sys.exit(2)
     ensure_built()
