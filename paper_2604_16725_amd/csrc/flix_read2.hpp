@@ -27,6 +27,11 @@ namespace flix {
 
 constexpr u32 kPosMiss = 0xFFFFu;   // lookup miss inside a single-node bucket
 constexpr u32 kPosSlow = 0xFFFEu;   // resolve on the global-memory path
+// The answer continues past the end of a single-node bucket's node: a
+// successor goes straight to the next bucket that holds a key, a range copies
+// from position lt of the node (lt | size << 16 in the count slot) onwards,
+// without locating the node or searching it again.
+constexpr u32 kPosNext = 0xFFFDu;
 constexpr u32 kChainBit = 0x80000000u;   // head-word flag: the bucket is a chain
 
 // LDS arrays of one set of slices being resolved: the sorted keys of the
@@ -41,6 +46,7 @@ struct SliceView {
   u32* cnt;
   const u32* e;
   const u32* hw;
+  u32 nhw;          // head words loaded: local buckets 0 .. nhw-1
   const unsigned short* tl;
   u32* list;        // LDS room for the ranges handed to the wave-wide copy
   u32 list_cap;     // (0: none; every range then stays on the one-lane path)
@@ -159,6 +165,30 @@ __device__ __forceinline__ void range_waves(const ReadArgs<K>& a, const SliceVie
   }
 }
 
+// n consecutive (key, value) results of a node, from slot `at` of the pool,
+// to outputs from position `o`: loads of four results are issued before
+// their stores.
+template <typename K>
+__device__ __forceinline__ void copy_results(const ReadArgs<K>& a, u64 at, u32 n, u64 o) {
+  for (u32 r0 = 0; r0 < n; r0 += 4) {
+    K kk[4], vv[4];
+#pragma unroll
+    for (u32 q = 0; q < 4; ++q) {
+      if (r0 + q < n) {
+        if (a.out_k) kk[q] = a.nkeys[at + r0 + q];
+        if (a.out_v) vv[q] = a.nvals[at + r0 + q];
+      }
+    }
+#pragma unroll
+    for (u32 q = 0; q < 4; ++q) {
+      if (r0 + q < n) {
+        if (a.out_k) a.out_k[o + r0 + q] = kk[q];
+        if (a.out_v) a.out_v[o + r0 + q] = vv[q];
+      }
+    }
+  }
+}
+
 // Phases A and B over the touched buckets of one set of slices (all threads
 // of the workgroup call; `ntouch` buckets listed in v.tl, local bucket lb is
 // global bucket b0 + lb, at most RQ * NT keys).
@@ -181,9 +211,15 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
     const u32 gl = tid % GL;
     const u32 gbase = (tid & 63) - gl;
     const u64 gmask = (GL == 64) ? ~0ull : (((1ull << GL) - 1ull) << gbase);
+    // A node holding at most half the group's slots (a bulk-loaded node at
+    // fill cap/2) is spread over all GL lanes, KH keys each, and the
+    // comparisons of the upper KPL - KH slots are skipped while no group of
+    // the wave holds a fuller node: half the comparisons per key.
+    constexpr bool kHalf = KPL >= 2;
+    constexpr int KH = kHalf ? KPL / 2 : KPL;
     for (u32 i0 = gid * U; i0 < ntouch; i0 += NG * U) {
       KeyVec<K, KPL> kv[U];
-      u32 lbs[U], sizes[U];
+      u32 lbs[U], sizes[U], kpls[U];
       bool single[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -192,10 +228,16 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
         const u32 hw = (i < ntouch) ? s_hw[lbs[u]] : 0u;
         sizes[u] = hw & ~kChainBit;
         single[u] = (i < ntouch) && !(hw & kChainBit);
-        if (single[u] && gl * KPL < sizes[u]) {
-          const KeyVec<K, KPL>* src = reinterpret_cast<const KeyVec<K, KPL>*>(
-              a.nkeys + (u64)(b0 + lbs[u]) * a.cap + (u64)gl * KPL);
-          kv[u] = *src;
+        kpls[u] = (kHalf && sizes[u] <= (u32)(GL * KH)) ? (u32)KH : (u32)KPL;
+        if (single[u] && gl * kpls[u] < sizes[u]) {
+          const K* src = a.nkeys + (u64)(b0 + lbs[u]) * a.cap + (u64)gl * kpls[u];
+          if (kHalf && kpls[u] == (u32)KH) {
+            const KeyVec<K, KH> h = *reinterpret_cast<const KeyVec<K, KH>*>(src);
+#pragma unroll
+            for (int k = 0; k < KH; ++k) kv[u].k[k] = h.k[k];
+          } else {
+            kv[u] = *reinterpret_cast<const KeyVec<K, KPL>*>(src);
+          }
         }
       }
 #pragma unroll
@@ -205,6 +247,8 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
         const u32 s = lb ? s_e[lb - 1] : 0u;
         const u32 e = s_e[lb];
         const u32 size = sizes[u];
+        const u32 kpl = kpls[u];
+        const bool full = kpl == (u32)KPL;
         if (!single[u]) {
           for (u32 j = s + gl; j < e; j += GL) s_pos[j] = (lb << 16) | kPosSlow;
           continue;
@@ -229,47 +273,60 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
           if (op == kOpLookup) {
             int hit = -1;
 #pragma unroll
-            for (int k = 0; k < KPL; ++k)
-              if (gl * KPL + k < size && kv[u].k[k] == x) hit = k;
+            for (int k = 0; k < KH; ++k)
+              if (gl * kpl + k < size && kv[u].k[k] == x) hit = k;
+            if (kHalf && full) {
+#pragma unroll
+              for (int k = KH; k < KPL; ++k)
+                if (gl * kpl + k < size && kv[u].k[k] == x) hit = k;
+            }
             u64 bal = wave_ballot(hit >= 0) & gmask;
             if (bal == 0) {
               if (gl == 0) s_pos[j] = (lb << 16) | kPosMiss;
             } else if (hit >= 0) {
-              s_pos[j] = (lb << 16) | (gl * KPL + (u32)hit);
+              s_pos[j] = (lb << 16) | (gl * kpl + (u32)hit);
             }
           } else {
             // Lower bound of x (and upper bound of hi for ranges).  The
-            // node is sorted and lane l holds positions [l*KPL, l*KPL+KPL),
+            // node is sorted and lane l holds positions [l*kpl, l*kpl+kpl),
             // so the lanes whose first key is below x form a prefix of L
             // lanes and the bound lies in lane L-1: one ballot over first
             // keys plus that lane's own count.
             // A predecessor needs the upper bound of x itself.
-            const bool v0 = gl * KPL < size;
+            const bool v0 = gl * kpl < size;
             const K ub = (op == kOpRange) ? hi : x;
             const bool need_ub = op == kOpRange || op == kOpPredecessor;
             u32 c_lt = 0, c_le = 0;
 #pragma unroll
-            for (int k = 0; k < KPL; ++k) {
-              const bool v = gl * KPL + k < size;
+            for (int k = 0; k < KH; ++k) {
+              const bool v = gl * kpl + k < size;
               c_lt += (v && kv[u].k[k] < x) ? 1u : 0u;
               if (need_ub) c_le += (v && kv[u].k[k] <= ub) ? 1u : 0u;
+            }
+            if (kHalf && full) {
+#pragma unroll
+              for (int k = KH; k < KPL; ++k) {
+                const bool v = gl * kpl + k < size;
+                c_lt += (v && kv[u].k[k] < x) ? 1u : 0u;
+                if (need_ub) c_le += (v && kv[u].k[k] <= ub) ? 1u : 0u;
+              }
             }
             u32 lt = 0;
             if (op != kOpPredecessor) {
               const u32 L1 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] < x) & gmask);
               const u32 s_lt = (u32)__shfl((int)c_lt, (int)(gbase + (L1 ? L1 - 1 : 0)), 64);
-              lt = L1 ? (L1 - 1) * KPL + s_lt : 0u;
+              lt = L1 ? (L1 - 1) * kpl + s_lt : 0u;
             }
             u32 le = 0;
             if (need_ub) {
               const u32 L2 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] <= ub) & gmask);
               const u32 s_le = (u32)__shfl((int)c_le, (int)(gbase + (L2 ? L2 - 1 : 0)), 64);
-              le = L2 ? (L2 - 1) * KPL + s_le : 0u;
+              le = L2 ? (L2 - 1) * kpl + s_le : 0u;
             }
             if (gl == 0) {
               u32 code;
               if (op == kOpSuccessor) {
-                code = lt < size ? lt : kPosSlow;
+                code = lt < size ? lt : kPosNext;   // past the node: next bucket
               } else if (op == kOpPredecessor) {
                 code = le > 0 ? le - 1 : kPosSlow;   // none in this node: look before it
               } else {
@@ -280,7 +337,8 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
                   code = lt;
                   s_cnt[j] = le > lt ? le - lt : 0u;
                 } else {
-                  code = kPosSlow;   // range may continue past this node
+                  code = kPosNext;   // every key from lt on is in the range
+                  s_cnt[j] = lt | (size << 16);
                 }
               }
               s_pos[j] = (lb << 16) | code;
@@ -304,10 +362,21 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
     for (u32 r = 0; r < RQ; ++r) {
       const u32 j = tid + r * NT;
       pc[r] = j < nq ? s_pos[j] : kPosSlow;
-      const u32 pos = pc[r] & 0xFFFFu;
+      u32 pos = pc[r] & 0xFFFFu;
+      if (op == kOpSuccessor && pos == kPosNext) {
+        // past its node's end: the first key of the next bucket when that
+        // bucket's head word is at hand and its head node (which holds its
+        // smallest keys) holds a key
+        const u32 nlb = (pc[r] >> 16) + 1u;
+        if (nlb < v.nhw && (s_hw[nlb] & ~kChainBit) > 0) {
+          pc[r] = nlb << 16;
+          pos = 0;
+          s_pos[j] = pc[r];
+        }
+      }
       rv[r] = NF;
       rk[r] = NF;
-      if (pos != kPosSlow && pos != kPosMiss) {
+      if (pos < kPosNext) {
         const u64 at = (u64)(b0 + (pc[r] >> 16)) * a.cap + pos;
         rv[r] = a.nvals[at];
         if (with_key) rk[r] = a.nkeys[at];
@@ -316,7 +385,8 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
 #pragma unroll
     for (u32 r = 0; r < RQ; ++r) {
       const u32 j = tid + r * NT;
-      if ((pc[r] & 0xFFFFu) != kPosSlow) {
+      const u32 pos = pc[r] & 0xFFFFu;
+      if (pos != kPosSlow && pos != kPosNext) {
         const u32 orig = s_idx[j];
         a.out_v[orig] = rv[r];
         if (with_key) a.out_k[orig] = rk[r];
@@ -330,20 +400,12 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
     u32 b = b0 + lb;
     const u32 orig = s_idx[j];
     const K x = s_q[j];
-    if (pos != kPosSlow) {
-      const u64 nb_ = (u64)b * a.cap;
-      if (op != kOpRange) {
-        continue;   // written above
-      } else {
-        const u32 cnt = s_cnt[j];
-        const u32 wn = cnt < a.maxpq ? cnt : a.maxpq;
-        const u64 ob = (u64)orig * a.maxpq;
-        for (u32 r = 0; r < wn; ++r) {
-          if (a.out_k) a.out_k[ob + r] = a.nkeys[nb_ + pos + r];
-          if (a.out_v) a.out_v[ob + r] = a.nvals[nb_ + pos + r];
-        }
-        a.counts[orig] = cnt;
-      }
+    if (pos != kPosSlow && pos != kPosNext) {
+      if (op != kOpRange) continue;   // written above
+      const u32 cnt = s_cnt[j];
+      const u32 wn = cnt < a.maxpq ? cnt : a.maxpq;
+      copy_results<K>(a, (u64)b * a.cap + pos, wn, (u64)orig * a.maxpq);
+      a.counts[orig] = cnt;
       continue;
     }
     if (op == kOpPredecessor) {
@@ -354,18 +416,36 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
       a.out_v[orig] = at == ~0ull ? NF : a.nvals[at];
       continue;
     }
-    // Global-memory path: walk the chain to the node holding x.
     NodeHdr h;
-    u32 node = locate_node(a.hdr, a.pool, b, (u64)x, &h);
-    if (node == kBadLink) {
-      atomicCAS(a.err, 0u, kErrInternal);
-      if (op == kOpRange) a.counts[orig] = 0;
-      else a.out_v[orig] = NF;
-      if (op == kOpSuccessor) a.out_k[orig] = NF;
-      continue;
+    u32 node, p;
+    bool all_in = false;   // range: every key from p to the node's end is in it
+    if (pos == kPosNext) {
+      // single-node bucket, resolved up to its node's end in phase A
+      node = b;
+      h.fence = 0;
+      h.next = kNil;
+      if (op == kOpRange) {
+        const u32 c = s_cnt[j];
+        p = c & 0xFFFFu;
+        h.size = c >> 16;
+        all_in = true;
+      } else {
+        p = 0;
+        h.size = 0;   // successor: nothing left in this node
+      }
+    } else {
+      // Global-memory path: walk the chain to the node holding x.
+      node = locate_node(a.hdr, a.pool, b, (u64)x, &h);
+      if (node == kBadLink) {
+        atomicCAS(a.err, 0u, kErrInternal);
+        if (op == kOpRange) a.counts[orig] = 0;
+        else a.out_v[orig] = NF;
+        if (op == kOpSuccessor) a.out_k[orig] = NF;
+        continue;
+      }
+      p = lower_bound_idx<K>(a.nkeys + (u64)node * a.cap, 0u, h.size, x);
     }
     const K* keys = a.nkeys + (u64)node * a.cap;
-    u32 p = lower_bound_idx<K>(keys, 0u, h.size, x);
     if (op == kOpLookup) {
       a.out_v[orig] = (p < h.size && keys[p] == x) ? a.nvals[(u64)node * a.cap + p] : NF;
     } else if (op == kOpSuccessor) {
@@ -395,7 +475,7 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
           // more than kLaneRangeMax results in this node: a wave copies them
           u32 lim = h.size;
           if (v.list_cap && p + kLaneRangeMax < h.size) {
-            if (keys[p + kLaneRangeMax] <= hi) {
+            if (all_in || keys[p + kLaneRangeMax] <= hi) {
               const u32 li = atomicAdd(v.nlist, 1u);
               if (li < v.list_cap) {
                 v.list[li] = j;
@@ -410,13 +490,13 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
               lim = p + kLaneRangeMax;   // keys[lim] > hi: the range ends before lim
             }
           }
-          u32 ub = upper_bound_idx<K>(keys, p, lim, hi);
-          for (u32 r = p; r < ub; ++r, ++cnt) {
-            if (cnt < a.maxpq) {
-              if (a.out_k) a.out_k[ob + cnt] = keys[r];
-              if (a.out_v) a.out_v[ob + cnt] = a.nvals[(u64)node * a.cap + r];
-            }
+          const u32 ub = all_in ? h.size : upper_bound_idx<K>(keys, p, lim, hi);
+          all_in = false;
+          if (cnt < a.maxpq) {
+            const u32 room = a.maxpq - cnt;
+            copy_results<K>(a, (u64)node * a.cap + p, ub - p < room ? ub - p : room, ob + cnt);
           }
+          cnt += ub - p;
           if (ub < h.size) break;
           NodeHdr g;
           u32 nn = next_nonempty(a.hdr, occ_levels(a.occ, a.nb), a.nb, a.pool, &b, h, &g);
@@ -531,7 +611,6 @@ __device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
 
   // Bound search: every bucket pulls its slice; compact the touched buckets.
   constexpr u32 PER = (S + 1 + NT - 1) / NT;
-  u32 flags = 0, nt = 0;
 #pragma unroll
   for (u32 r = 0; r < PER; ++r) {
     u32 lb = tid * PER + r;
@@ -541,22 +620,37 @@ __device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
     }
   }
   __syncthreads();
+  // The touched buckets are listed by slice length (one key, two keys,
+  // more), so the lane groups of a wave, which step through their buckets'
+  // slices together, mostly hold slices of one length.
+  static_assert(S + 1 < 1024, "class counts are packed in 10 bits");
+  u32 flags = 0, packed = 0;
 #pragma unroll
   for (u32 r = 0; r < PER; ++r) {
     u32 lb = tid * PER + r;
     if (lb <= nbl) {
-      u32 s = lb ? s_e[lb - 1] : 0u;
-      if (s_e[lb] > s) {
-        flags |= 1u << r;
-        ++nt;
+      const u32 s = lb ? s_e[lb - 1] : 0u;
+      const u32 len = s_e[lb] - s;
+      if (len > 0) {
+        const u32 c = len < 3u ? len - 1u : 2u;
+        flags |= (c + 1u) << (2u * r);
+        packed += 1u << (10u * c);
       }
     }
   }
-  u32 ntot;
-  u32 w = block_exclusive_scan<NT>(nt, s_tmp, &ntot);
+  u32 tot;
+  const u32 ex = block_exclusive_scan<NT>(packed, s_tmp, &tot);
+  const u32 t0 = tot & 1023u, t1 = (tot >> 10) & 1023u, t2 = tot >> 20;
+  u32 w0 = ex & 1023u, w1 = t0 + ((ex >> 10) & 1023u), w2 = t0 + t1 + (ex >> 20);
 #pragma unroll
-  for (u32 r = 0; r < PER; ++r)
-    if (flags & (1u << r)) s_tl[w++] = (unsigned short)(tid * PER + r);
+  for (u32 r = 0; r < PER; ++r) {
+    const u32 c = (flags >> (2u * r)) & 3u;
+    const unsigned short lb = (unsigned short)(tid * PER + r);
+    if (c == 1u) s_tl[w0++] = lb;
+    else if (c == 2u) s_tl[w1++] = lb;
+    else if (c == 3u) s_tl[w2++] = lb;
+  }
+  const u32 ntot = t0 + t1 + t2;
   if (tid == 0) s_ntouch = ntot;
   __syncthreads();
   const u32 ntouch = s_ntouch;
@@ -569,6 +663,7 @@ __device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
   v.cnt = s_cnt;
   v.e = s_e;
   v.hw = s_hw;
+  v.nhw = nbl + 1;
   v.tl = s_tl;
   // the maxBucket entries are no longer needed: their room lists the ranges
   // that continue past their node
