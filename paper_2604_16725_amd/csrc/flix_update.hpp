@@ -599,21 +599,35 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       }
       // Node items below the chunk's smallest key neither move nor meet a
       // chunk key: the duplicate scan starts at the group-aligned run that
-      // holds the first node key >= bk[0].
-      const u32 f0 = lower_bound_idx<K>(ak, 0u, sa, bk[0]);
+      // holds the first node key >= bk[0].  When the whole node is in the
+      // registers and node plus chunk fit it, the merge cannot split it: the
+      // first key >= bk[0] is counted by ballots, the duplicate scan is
+      // skipped (the merged count follows from the move below) and the node
+      // items move from the registers.
+      const bool fast = first == sa && sa + tb <= a.cap;
+      u32 f0 = 0;
+      if (fast) {
+        const K c0 = bk[0];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f0 += g.count((u32)r * GL + g.lane < sa && nk[r] < c0);
+      } else {
+        f0 = lower_bound_idx<K>(ak, 0u, sa, bk[0]);
+      }
       const u32 i_lo = f0 - f0 % GL;
       // duplicates between node and chunk
       u32 dd = 0;
-      for (u32 i0 = i_lo; i0 < sa; i0 += GL) {
-        u32 i = i0 + g.lane;
-        bool drop = false;
-        if (i < sa) {
-          u32 p = lower_bound_idx<K>(bk, 0u, tb, ak[i]);
-          drop = p < tb && bk[p] == ak[i];
+      if (!fast) {
+        for (u32 i0 = i_lo; i0 < sa; i0 += GL) {
+          u32 i = i0 + g.lane;
+          bool drop = false;
+          if (i < sa) {
+            u32 p = lower_bound_idx<K>(bk, 0u, tb, ak[i]);
+            drop = p < tb && bk[p] == ak[i];
+          }
+          dd += g.count(drop);
         }
-        dd += g.count(drop);
       }
-      const u32 c = sa + tb - dd;
+      u32 c = sa + tb - dd;   // fast: an upper bound until the move has counted duplicates
       u32 k = 1;
       u32 base_id = 0;
       if (c > a.cap) {
@@ -637,22 +651,43 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         K* const xk = a.nkeys + (u64)X * a.cap;
         K* const xv = a.nvals + (u64)X * a.cap;
         u32 drop_before = 0;
-        for (u32 i0 = i_lo; i0 < sa; i0 += GL) {
-          const u32 i = i0 + g.lane;
-          bool drop = false;
-          u32 pos = 0;
-          K kk = K(0), vv = K(0);
-          if (i < sa) {
-            kk = ak[i];
-            vv = av[i];
-            const u32 p = lower_bound_idx<K>(bk, 0u, tb, kk);
-            drop = p < tb && bk[p] == kk;
-            pos = i - (drop_before + g.rank(drop)) + p;
+        if (fast) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if ((u32)r * GL < i_lo || (u32)r * GL >= sa) continue;   // uniform in the group
+            const u32 i = (u32)r * GL + g.lane;
+            bool drop = false;
+            u32 pos = 0;
+            if (i < sa) {
+              const u32 p = lower_bound_idx<K>(bk, 0u, tb, nk[r]);
+              drop = p < tb && bk[p] == nk[r];
+              pos = i - (drop_before + g.rank(drop)) + p;
+            }
+            drop_before += g.count(drop);
+            if (i < sa && !drop && pos != i) {
+              xk[pos] = nk[r];
+              xv[pos] = nv[r];
+            }
           }
-          drop_before += g.count(drop);
-          if (i < sa && !drop && pos != i) {
-            xk[pos] = kk;
-            xv[pos] = vv;
+          c = sa + tb - drop_before;
+        } else {
+          for (u32 i0 = i_lo; i0 < sa; i0 += GL) {
+            const u32 i = i0 + g.lane;
+            bool drop = false;
+            u32 pos = 0;
+            K kk = K(0), vv = K(0);
+            if (i < sa) {
+              kk = ak[i];
+              vv = av[i];
+              const u32 p = lower_bound_idx<K>(bk, 0u, tb, kk);
+              drop = p < tb && bk[p] == kk;
+              pos = i - (drop_before + g.rank(drop)) + p;
+            }
+            drop_before += g.count(drop);
+            if (i < sa && !drop && pos != i) {
+              xk[pos] = kk;
+              xv[pos] = vv;
+            }
           }
         }
         u32 match_before = 0;
