@@ -572,7 +572,6 @@ __global__ __launch_bounds__(NT) void k_group_read(GroupArgs<K> ga, ReadArgs<K> 
   v.cnt = s_cnt;
   v.e = s_e;
   v.hw = s_hw;
-  v.nhw = nbl;
   v.tl = s_tl;
   v.list = nullptr;   // ranges past their node take the one-lane path here
   v.list_cap = 0;

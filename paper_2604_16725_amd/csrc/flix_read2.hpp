@@ -46,7 +46,6 @@ struct SliceView {
   u32* cnt;
   const u32* e;
   const u32* hw;
-  u32 nhw;          // head words loaded: local buckets 0 .. nhw-1
   const unsigned short* tl;
   u32* list;        // LDS room for the ranges handed to the wave-wide copy
   u32 list_cap;     // (0: none; every range then stays on the one-lane path)
@@ -165,6 +164,17 @@ __device__ __forceinline__ void range_waves(const ReadArgs<K>& a, const SliceVie
   }
 }
 
+template <typename K>
+__device__ __forceinline__ K shfl_key(K v, u32 src) {
+  if constexpr (sizeof(K) == 4) {
+    return (K)__shfl((int)v, (int)src, 64);
+  } else {
+    const u32 lo = (u32)__shfl((int)(u32)v, (int)src, 64);
+    const u32 hi = (u32)__shfl((int)(u32)((u64)v >> 32), (int)src, 64);
+    return (K)(((u64)hi << 32) | lo);
+  }
+}
+
 // n consecutive (key, value) results of a node, from slot `at` of the pool,
 // to outputs from position `o`: loads of four results are issued before
 // their stores.
@@ -198,6 +208,7 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
   constexpr int NG = NT / GL;
   const u32 tid = threadIdx.x;
   const K* s_q = v.q;
+  K* s_kq = const_cast<K*>(v.q);   // successor: answer keys of resolved queries
   const K* s_hi = v.hi;
   const u32* s_idx = v.idx;
   u32* s_pos = v.pos;
@@ -265,6 +276,7 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
             if (gl == 0) {
               s_pos[j] = s_pos[j - 1];
               if (op == kOpRange) s_cnt[j] = s_cnt[j - 1];
+              if (op == kOpSuccessor) s_kq[j] = s_kq[j - 1];
             }
             continue;
           }
@@ -312,10 +324,27 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
               }
             }
             u32 lt = 0;
+            K skey = K(0);
             if (op != kOpPredecessor) {
               const u32 L1 = (u32)__popcll(wave_ballot(v0 && kv[u].k[0] < x) & gmask);
               const u32 s_lt = (u32)__shfl((int)c_lt, (int)(gbase + (L1 ? L1 - 1 : 0)), 64);
               lt = L1 ? (L1 - 1) * kpl + s_lt : 0u;
+              if (op == kOpSuccessor) {
+                // the key at lt: this lane's first slot >= x, taken from lane
+                // L1-1, or from lane L1's first slot when lane L1-1 holds
+                // nothing >= x
+                K cand = kv[u].k[0];
+#pragma unroll
+                for (int k = 1; k < KH; ++k)
+                  if (c_lt == (u32)k) cand = kv[u].k[k];
+                if (kHalf && full) {
+#pragma unroll
+                  for (int k = KH; k < KPL; ++k)
+                    if (c_lt == (u32)k) cand = kv[u].k[k];
+                }
+                const u32 src = L1 == 0 ? 0u : (s_lt < kpl ? L1 - 1 : L1);
+                skey = shfl_key(cand, gbase + src);
+              }
             }
             u32 le = 0;
             if (need_ub) {
@@ -327,6 +356,7 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
               u32 code;
               if (op == kOpSuccessor) {
                 code = lt < size ? lt : kPosNext;   // past the node: next bucket
+                if (lt < size) s_kq[j] = skey;   // the answer's key replaces the query
               } else if (op == kOpPredecessor) {
                 code = le > 0 ? le - 1 : kPosSlow;   // none in this node: look before it
               } else {
@@ -363,23 +393,13 @@ __device__ __forceinline__ void resolve_slices(const ReadArgs<K>& a, int op, con
       const u32 j = tid + r * NT;
       pc[r] = j < nq ? s_pos[j] : kPosSlow;
       u32 pos = pc[r] & 0xFFFFu;
-      if (op == kOpSuccessor && pos == kPosNext) {
-        // past its node's end: the first key of the next bucket when that
-        // bucket's head word is at hand and its head node (which holds its
-        // smallest keys) holds a key
-        const u32 nlb = (pc[r] >> 16) + 1u;
-        if (nlb < v.nhw && (s_hw[nlb] & ~kChainBit) > 0) {
-          pc[r] = nlb << 16;
-          pos = 0;
-          s_pos[j] = pc[r];
-        }
-      }
       rv[r] = NF;
       rk[r] = NF;
       if (pos < kPosNext) {
         const u64 at = (u64)(b0 + (pc[r] >> 16)) * a.cap + pos;
         rv[r] = a.nvals[at];
-        if (with_key) rk[r] = a.nkeys[at];
+        if (op == kOpSuccessor) rk[r] = s_q[j];
+        else if (with_key) rk[r] = a.nkeys[at];
       }
     }
 #pragma unroll
@@ -663,7 +683,6 @@ __device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
   v.cnt = s_cnt;
   v.e = s_e;
   v.hw = s_hw;
-  v.nhw = nbl + 1;
   v.tl = s_tl;
   // the maxBucket entries are no longer needed: their room lists the ranges
   // that continue past their node
@@ -682,7 +701,7 @@ __device__ __forceinline__ void read_share(const ReadArgs<K>& a, int op, u32 vb,
 // out, which keeps the register and scalar-register budget for the one that
 // runs.
 template <typename K, int NT, int S, int GL, int KPL, int U, int OP>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OP == kOpRange ? 6 : 8))) void k_read_apply2(
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) void k_read_apply2(
     ReadArgs<K> a) {
   __shared__ ReadSmem<K, S, NT> sm;
   read_share<K, NT, S, GL, KPL, U>(a, OP, blockIdx.x, sm);

@@ -17,7 +17,12 @@ struct ReadShare {
 template <typename K, int GL, int KPL>
 void read2_k(const ReadArgs<K>& a, int op, u32 grid, hipStream_t st, hipEvent_t e0,
              hipEvent_t e1) {
-  constexpr int U = KPL >= 16 ? 2 : 4;
+  // One bucket per lane group at a time: the eight resident waves per SIMD
+  // keep enough node loads in flight, and the registers of more buckets cost
+  // spills or occupancy (lookup / successor / range16 kernels on a 2^26-key
+  // store: 69 / 87 / 98 us holding two to four buckets, 64 / 84 / 95 us
+  // holding one).
+  constexpr int U = 1;
   constexpr int S = ReadShare<K>::S;
   switch (op) {
     case kOpLookup:
