@@ -1306,12 +1306,16 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       // the node's slice goes to LDS when it fits, else it is searched in place
       const bool slice_lds = touched && (j2 - j) <= a.chunk;
       // One round trip for the slice's first 4*GL keys and the node's first
-      // 4*GL items (X's data has not been written by this kernel).
+      // NR*GL items (X's data has not been written by this kernel).  Five
+      // rounds of registers cover a bulk-loaded node plus the keys a batch
+      // just added (a fourth round left them to a second round trip; a sixth
+      // costs a wave per SIMD).
       const bool stage_x = touched || join;
       const K* xsk = a.nkeys + (u64)X * a.cap;
       const K* xsv = a.nvals + (u64)X * a.cap;
-      const u32 first = stage_x ? (sx < 4u * GL ? sx : 4u * GL) : 0u;
-      K nk[4], nv[4];
+      constexpr int NR = 5;
+      const u32 first = stage_x ? (sx < (u32)NR * GL ? sx : (u32)NR * GL) : 0u;
+      K nk[NR], nv[NR];
       if (slice_lds) {
         for (u32 i0 = j; i0 < j2; i0 += 4 * GL) {
           K kk[4];
@@ -1322,7 +1326,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
           }
           if (i0 == j) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < NR; ++r) {
               const u32 i = r * GL + g.lane;
               if (i < first) {
                 nk[r] = xsk[i];
@@ -1338,7 +1342,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NR; ++r) {
           const u32 i = r * GL + g.lane;
           if (i < first) {
             nk[r] = xsk[i];
@@ -1348,7 +1352,7 @@ __device__ void delete_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
       }
       if (stage_x) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NR; ++r) {
           const u32 i = r * GL + g.lane;
           if (i < first) {
             ak[i] = nk[r];
