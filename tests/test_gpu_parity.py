@@ -276,6 +276,60 @@ def test_reads_small(kb, cap):
 
 
 @pytest.mark.parametrize("kb", [32, 64])
+@pytest.mark.parametrize("cap,lanes", [(128, 16), (128, 32), (64, 16), (256, 64), (32, 16)])
+def test_reads_at_the_half_node_boundary(kb, cap, lanes):
+    """The read kernel spreads a node holding at most half of a lane group's
+    slots over all of its lanes (half the comparisons per query) and uses
+    every slot for a fuller node; one batch meets nodes below, at and just
+    above half full, nodes close to full and chained buckets, so the lane
+    groups of one wave take both forms.  Lookups of present and absent keys,
+    successors, predecessors and short and long ranges, bit-exact."""
+    dt = ktype(kb)
+    rng = np.random.default_rng(cap * 31 + lanes + kb)
+    s, o = new_pair(kb, cap=cap, lanes=lanes, max_batch=1 << 16)
+    base = np.unique(_keys(rng, kb, 30000))
+    s.bulk_load(to_dev(base), to_dev(base ^ dt(0x5A)))
+    o.bulk_load(base, base ^ dt(0x5A))
+    mk = s.copy_layout()["mkba"].astype(np.uint64)
+    nb = mk.size
+    half = cap // 2
+    deltas = [-3, -1, 0, 1, 2, half // 2, half - 1, half + 3]
+    present = set(int(x) for x in base)
+    ins, dele = [], []
+    for b in rng.choice(np.arange(1, nb - 1), size=min(240, nb - 2), replace=False):
+        lo_b, hi_b = int(mk[b - 1]) + 1, int(mk[b])
+        d = deltas[int(rng.integers(0, len(deltas)))]
+        if d > 0:
+            got = 0
+            while got < d:
+                x = int(rng.integers(lo_b, hi_b, endpoint=True, dtype=np.uint64))
+                if x not in present:
+                    present.add(x)
+                    ins.append(x)
+                    got += 1
+        elif d < 0:
+            own = base[(base >= lo_b) & (base <= hi_b)]
+            dele.extend(int(x) for x in own[: -d])
+    ins = np.array(ins, dtype=np.uint64).astype(dt)
+    dele = np.array(dele, dtype=np.uint64).astype(dt)
+    s.insert(to_dev(ins), to_dev(ins ^ dt(0x33)))
+    o.insert(ins, ins ^ dt(0x33))
+    s.delete(to_dev(dele))
+    o.delete(dele)
+    assert s.status() == 0
+    assert_same_contents(s, o, kb, "half-node boundary store")
+    sizes = s.copy_layout()["size"][:nb]
+    log(f"half-node boundary cap={cap} lanes={lanes}: node sizes {np.bincount(np.minimum(sizes, cap))[half - 3: half + 4]} around half, max {sizes.max()}")
+    cur, _ = o.dump()
+    q = np.concatenate([cur[rng.integers(0, cur.size, 6000)], _keys(rng, kb, 3000),
+                        mk.astype(dt), (mk[:-1] + 1).astype(dt), ins[:2000], dele[:500]])
+    rng.shuffle(q)
+    check_reads(s, o, kb, q, maxpq=8, where="half-node boundary")
+    hi = np.minimum(q.astype(np.uint64) + np.uint64(40), np.uint64((1 << kb) - 1)).astype(dt)
+    check_reads(s, o, kb, q, maxpq=4, lo=q, hi=hi, where="half-node boundary, short ranges")
+
+
+@pytest.mark.parametrize("kb", [32, 64])
 def test_reads_on_empty_and_single(kb):
     s, o = new_pair(kb, cap=64, max_batch=1024)
     mx = (1 << kb) - 1
