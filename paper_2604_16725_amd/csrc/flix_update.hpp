@@ -820,12 +820,12 @@ __device__ void insert_items(const UpdArgs<K>& a, u32 lds_items, u32 blk, u32 nb
   __syncthreads();
 }
 
-// Six waves per SIMD (80 VGPRs): with a half-node merge chunk the LDS of six
-// workgroups fits a CU, and the register budget is then the limit (32-bit
-// keys; 64-bit keys would spill).
+// Five waves per SIMD for 32-bit keys (85 VGPRs, no spills): the register
+// path of a node that fits the registers needs more than the 80 registers of
+// six waves, which spilled and was 6% slower; 64-bit keys take what they need.
 template <typename K, int GL, int NT>
 __global__ __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 6 : 1))) void k_insert_apply(
+__attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 5 : 1))) void k_insert_apply(
     UpdArgs<K> a, u32 lds_items) {
   extern __shared__ unsigned char s_dyn[];
   __shared__ UpdShared sh;
