@@ -4,20 +4,23 @@
 // slice of the sorted batch that falls into (MKBA[i-1], MKBA[i]]), organised
 // for wave64 latency hiding:
 //   1. merge-path cut of "MKBA (+) sorted batch" into equal shares: loaded
-//      from the cut list k_merge_cuts wrote, or (persistent drain) found by a
-//      cooperative 128-ary search (three dependent rounds instead of ~21);
+//      from the cut list (written by the run sort, else by k_merge_cuts), or
+//      (persistent drain) found by a cooperative 128-ary search (three
+//      dependent rounds instead of ~21);
 //   2. one coalesced round of loads: the share's keys, their input positions,
 //      MKBA entries and node headers (and range upper bounds);
 //   3. every bucket takes its slice by upper_bound of its maxBucket in LDS;
+//      the touched buckets are listed by slice length;
 //   4. phase A: groups of GL lanes hold the live keys of U buckets at a time in
-//      registers (KPL keys per lane, 16-byte loads) and resolve each key of the
-//      slice with ballots: lookup match, successor / range lower and upper
-//      bounds inside the node; the result position goes to LDS;
+//      registers (KPL keys per lane, or KPL/2 spread over all lanes for a node
+//      at most half full; 16-byte loads) and resolve each key of the slice
+//      with ballots: lookup match, successor / range lower and upper bounds
+//      inside the node (and a successor's key); the result goes to LDS;
 //   5. phase B: one lane per key loads the value(s) and writes the outputs,
 //      all keys of the share in flight at once.
-// Keys whose answer lies outside the single staged node (chained buckets, a
-// successor or range running past the node's end) take the global-memory path
-// of flix_read.hpp.
+// Keys whose answer lies outside the single staged node take the global-memory
+// path of flix_read.hpp: chained buckets from their head, a successor or range
+// running past its node's end from where phase A left it.
 #pragma once
 
 #include "flix_device.hpp"
